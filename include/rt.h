@@ -1,0 +1,218 @@
+/*
+ * rt.h -- C ABI of the MI355X (gfx950) radio-propagation ray tracer.
+ *
+ * Implements the data-parallel hot path of the differentiable ray tracer of
+ * Hoydis et al., "Sionna RT: Differentiable Ray Tracing for Radio Propagation
+ * Modeling" (arXiv 2303.11103): shooting Fibonacci-lattice rays through a
+ * triangle mesh with specular reflections (Sec. II-B), transforming the
+ * polarised field at every interaction with Fresnel coefficients of materials
+ * given by (eps_r, sigma), mu_r = 1 (Sec. II), accumulating coverage maps of
+ * path gain (Sec. II-A, Fig. 2), finding exact specular paths with the image
+ * method from candidate primitive sequences, removing duplicates and adding
+ * line of sight (Sec. II-B), and returning path coefficients and delays
+ * (Sec. II-A, the `a, tau` of the channel impulse response) with angles of
+ * departure and arrival, plus gradients of received power with respect to
+ * materials and transmitter pose (Sec. I, II; Sec. III-A and III-B).
+ *
+ * Conventions for every entry point
+ *   - Return value: rt_status, RT_OK (0) on success, a negative code on
+ *     failure; rt_last_error() returns a thread-local message for the last
+ *     failure of the calling thread.  On failure no output is guaranteed to be
+ *     written.
+ *   - Arguments marked (host) are host pointers, read during the call only.
+ *     Arguments marked (dev) are device pointers on the context's device,
+ *     owned by the caller (e.g. torch tensors); the library never frees them.
+ *     The library owns only the opaque handles it returns (rt_ctx, rt_scene),
+ *     released by the matching *_destroy call, and its internal scratch.
+ *   - All device work is enqueued on the context's HIP stream (rt_set_stream);
+ *     calls return without waiting for it unless documented otherwise.
+ *   - Argument errors (NaN/inf coordinates, out-of-range indices, sizes) are
+ *     detected on the host before any launch and return RT_ERR_ARG.
+ *   - A context is not thread safe: use one context per host thread.
+ *   - Units: metres, seconds, hertz, radians, siemens per metre.
+ *   - Layouts are row-major.  Float outputs are IEEE binary32 unless stated.
+ */
+#ifndef RT_MI355X_H
+#define RT_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rt_status;
+#define RT_OK            0
+#define RT_ERR_ARG      -1  /* invalid argument (host-side validation) */
+#define RT_ERR_CAPACITY -2  /* an output or internal table is too small; see rt_last_error */
+#define RT_ERR_DEVICE   -3  /* a HIP call failed */
+#define RT_ERR_OOM      -4  /* device memory allocation failed */
+
+typedef struct rt_ctx rt_ctx;
+typedef struct rt_scene rt_scene;
+
+/* Radio material at the carrier frequency (Sec. II: relative permittivity and
+ * conductivity, non-magnetic).  sigma = +INFINITY denotes a perfect electric
+ * conductor (Fresnel coefficients r_perp = -1, r_par = +1). */
+typedef struct {
+    float eps_r;  /* relative permittivity, > 0 */
+    float sigma;  /* conductivity [S/m], >= 0 or +INFINITY */
+} rt_material;
+
+/* Antenna patterns (Sec. II, Listing 2: preconfigured patterns such as the
+ * 3GPP TR 38.901 element).  Polarisation is vertical (RT_POL_V). */
+#define RT_PATTERN_ISO      0  /* isotropic, C_theta = 1, C_phi = 0 */
+#define RT_PATTERN_TR38901  1  /* TR 38.901 Table 7.3-1 element, 8 dBi, 65 deg beamwidths */
+#define RT_POL_V            0
+
+/* A transmitter or receiver (Sec. II-A: position and orientation given by
+ * yaw, pitch, roll; orientation R = Rz(yaw) Ry(pitch) Rx(roll), positive
+ * pitch tilts the +x boresight towards -z). */
+typedef struct {
+    float pos[3];
+    float yaw, pitch, roll;
+    int32_t pattern;  /* RT_PATTERN_* */
+    int32_t pol;      /* RT_POL_V */
+} rt_device;
+
+/* Tracing parameters. */
+typedef struct {
+    double freq_hz;           /* carrier frequency, > 0 */
+    int32_t max_depth;        /* maximum number of reflections, 0..8 (0 = LOS only) */
+    int32_t max_paths_per_rx; /* rt_compute_paths: path slots per (tx, rx), 1..256 */
+    int64_t num_rays;         /* Fibonacci lattice size N, 1..2^40 */
+    double t_min;             /* minimum accepted hit distance [m], >= 0 (1e-4 typical) */
+    int64_t ray_begin;        /* trace rays ray_begin, ray_begin + ray_stride, ... < N */
+    int64_t ray_stride;       /* >= 1 (1 = all rays from ray_begin) */
+} rt_trace_params;
+
+/* Horizontal coverage grid: cell (ix, iy) covers [x0 + ix*cell, x0 + (ix+1)*cell)
+ * x [y0 + iy*cell, y0 + (iy+1)*cell) at height z; maps are stored [ny][nx]. */
+typedef struct {
+    double x0, y0, cell, z;
+    int32_t nx, ny;
+} rt_grid;
+
+/* Scene information returned by rt_scene_info. */
+typedef struct {
+    int64_t num_triangles;
+    int32_t num_faces;      /* coplanar same-material triangle groups */
+    int32_t num_materials;
+    int64_t bvh_nodes;
+    int32_t bvh_depth;
+    int32_t reserved;
+    double build_ms;        /* host time of scene preparation + BVH build */
+} rt_scene_info_t;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device` using the null stream. */
+rt_status rt_create(rt_ctx** out, int32_t device);
+rt_status rt_destroy(rt_ctx* ctx);
+/* Enqueue all later work of this context on `hip_stream` (a hipStream_t, or
+ * NULL for the null stream).  The stream must outlive its use. */
+rt_status rt_set_stream(rt_ctx* ctx, void* hip_stream);
+/* Block until all work enqueued by this context has finished. */
+rt_status rt_synchronize(rt_ctx* ctx);
+const char* rt_last_error(void);
+
+/* ------------------------------------------------------------------ scene */
+
+/* Build a scene from a triangle mesh (Sec. II: surfaces are triangle meshes,
+ * each object has a radio material).
+ *   V [nv][3] (host) float vertex positions; F [nt][3] (host) vertex indices
+ *   in [0, nv); tri_mat [nt] (host) material index in [0, nm); mats [nm]
+ *   (host).  Triangles with zero area are rejected (RT_ERR_ARG).
+ * Prepares per-triangle records, groups coplanar same-material triangles into
+ * faces (the primitives of candidate paths), builds a bounding volume
+ * hierarchy on the host and uploads everything to the device (synchronous). */
+rt_status rt_scene_create(rt_ctx* ctx, const float* V, int64_t nv, const int32_t* F, int64_t nt,
+                          const int32_t* tri_mat, const rt_material* mats, int32_t nm, rt_scene** out);
+/* Replace the material table (same count); no rebuild.  Synchronous. */
+rt_status rt_scene_set_materials(rt_scene* scene, const rt_material* mats, int32_t nm);
+rt_status rt_scene_info(const rt_scene* scene, rt_scene_info_t* out);
+/* Face id per triangle, in input order: face_ids [nt] (host). */
+rt_status rt_scene_face_ids(const rt_scene* scene, int32_t* face_ids);
+rt_status rt_scene_destroy(rt_scene* scene);
+
+/* ------------------------------------------------------------------ rays */
+
+/* Fibonacci-lattice directions (Sec. II-B) of rays ray_begin + k*ray_stride,
+ * k < count: dirs [count][3] (dev) float64.  Ray i of N points to
+ * z = 1 - (2i+1)/N, azimuth 2 pi frac(i g) with frac(i g) computed as the
+ * 64-bit product i * 0x9E3779B97F4A7C15 over 2^64. */
+rt_status rt_fibonacci_directions(rt_ctx* ctx, int64_t num_rays, int64_t ray_begin, int64_t ray_stride,
+                                  int64_t count, double* dirs);
+
+/* Trace the lattice rays of one transmitter and record, per segment
+ * k = 0..max_depth and traced ray j (ray index ray_begin + j*ray_stride), the
+ * closest-hit triangle (input index; -1 miss, -2 ray already terminated) and
+ * its distance (float64, +inf on a miss):
+ *   hit_tri [max_depth+1][count] (dev) int32, hit_t [max_depth+1][count] (dev)
+ *   float64, count = number of traced rays.
+ * Uses the same kernels as rt_coverage_map. */
+rt_status rt_trace_record(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p, const rt_device* tx,
+                          int32_t* hit_tri, double* hit_t);
+
+/* Coverage map (Sec. II-A, Fig. 2: path gain per cell of a plane).  Shoots
+ * the lattice rays of one transmitter with up to max_depth specular
+ * reflections and adds, for every crossing of the plane z = grid.z by a ray
+ * segment, the ray-tube estimate
+ *   (lambda/4pi)^2 (4pi/N) |F_rx(-d) . E|^2 / (cell^2 |d_z|)
+ * to the crossed cell, where E is the ray's field (transmit pattern times the
+ * reflection operators so far) and F_rx the receive pattern of rx_ant.
+ *   gain [ny][nx] (dev) linear path gain, hits [ny][nx] (dev) crossings;
+ *   gain_db [ny][nx] (dev, nullable) 10 log10(gain) (-inf where no hit);
+ *   ray_bounces (dev, nullable) uint64 [max_depth+1]: traced segments per
+ *   depth (their sum is the number of closest-hit queries).
+ * The map is cleared first.  Sub-lattices (ray_begin, ray_stride) add only
+ * their own rays with the weight of the full lattice N. */
+rt_status rt_coverage_map(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p, const rt_device* tx,
+                          const rt_device* rx_ant, const rt_grid* grid, float* gain, uint32_t* hits,
+                          float* gain_db, uint64_t* ray_bounces);
+
+/* Paths between ntx transmitters and nrx receivers (Sec. II-A
+ * compute_paths; Sec. II-B): for every transmitter the lattice rays are shot
+ * (max_depth reflections), the face sequence of every hit prefix becomes a
+ * candidate, duplicates are removed, the image method is applied to every
+ * candidate for every receiver and the line-of-sight path is added.  A path
+ * is kept when its reflection points lie on their faces, on the front sides,
+ * and every segment is unoccluded.  Outputs, shape [ntx][nrx][P] with
+ * P = max_paths_per_rx, paths of one (tx, rx) sorted by (depth, faces):
+ *   a [..][2] (dev) complex coefficient (re, im) excluding exp(-j 2 pi f tau)
+ *   T [..][2][2][2] (dev) 2x2 complex transfer matrix from (theta, phi) at
+ *     departure to (theta, phi) at arrival (re, im)
+ *   tau [..] (dev) delay [s];  aod [..][2], aoa [..][2] (dev) (theta, phi)
+ *   depth [..] (dev) int32 number of reflections
+ *   faces [..][max(max_depth,1)] (dev) int32 face ids (-1 padded)
+ *   num_paths [ntx][nrx] (dev) int32 paths found (not truncated)
+ * Unused slots get a = 0, tau = -1, depth = -1.  When some (tx, rx) has more
+ * than P paths the call fails with RT_ERR_CAPACITY (message gives the
+ * required P); num_paths is still written.  Synchronous (reads counters). */
+rt_status rt_compute_paths(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p, const rt_device* tx,
+                           int32_t ntx, const rt_device* rx, int32_t nrx, float* a, float* T, float* tau,
+                           float* aod, float* aoa, int32_t* depth, int32_t* faces, int32_t* num_paths);
+
+/* Number of distinct candidate face sequences found by the last
+ * rt_compute_paths call for its last transmitter. */
+rt_status rt_last_candidate_count(rt_ctx* ctx, int64_t* count);
+
+/* Gradient of a loss of received powers (Sec. I and III: gradients with
+ * respect to material properties and transmitter orientation and position).
+ * For one transmitter and the given paths (face sequences as returned by
+ * rt_compute_paths, shape [nrx][P][max(max_depth,1)], with depth [nrx][P]),
+ * the received power of rx r is P_r = sum_p |a_p|^2.  Given the upstream
+ * adjoint dL_dP [nrx] (dev) float64, writes
+ *   grad [2*nm + 5] (dev) float64 = sum_r dL_dP[r] dP_r/d(theta) for theta =
+ *   (eps_r, sigma) of every material, tx x, y, z, tx yaw, tx pitch.
+ * Faces and depths are the checkpoint of the forward pass: geometry and
+ * fields are recomputed from them.  Enqueued, not synchronous. */
+rt_status rt_paths_power_grad(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p, const rt_device* tx,
+                              const rt_device* rx, int32_t nrx, int32_t P, const int32_t* depth,
+                              const int32_t* faces, const double* dL_dP, double* grad);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RT_MI355X_H */

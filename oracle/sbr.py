@@ -78,17 +78,19 @@ def _cross_plane(o, d, t_hit, grid):
 
 
 def trace(scene, tx, params: TraceParams, grid=None, rx_ant=None, record=False, delta=1e-6,
-          candidates=False, threads=None, geo=None) -> TraceResult:
+          candidates=False, threads=None, geo=None, idx=None) -> TraceResult:
     """Trace the (sub)set of lattice rays of one transmitter.
 
     With ``grid`` the coverage map (gain, hits) is accumulated; ``record``
     keeps per-segment hits, origins and directions; ``candidates`` collects the
-    face sequence of every hit prefix of length 1..max_depth.
+    face sequence of every hit prefix of length 1..max_depth.  ``idx``
+    (optional) lists the lattice indices to trace instead of the params'
+    sub-lattice.
     """
     geo = geo or Geometry(scene)
     lam = em.wavelength(geo.freq)
     N = int(params.num_rays)
-    idx = fib.subset(N, params.ray_begin, params.ray_stride)
+    idx = fib.subset(N, params.ray_begin, params.ray_stride) if idx is None else np.asarray(idx, dtype=np.int64)
     n = idx.shape[0]
     d = fib.directions(N, idx)
     o = np.repeat(np.asarray(tx.pos, dtype=np.float64)[None, :], n, axis=0)

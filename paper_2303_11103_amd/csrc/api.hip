@@ -1,0 +1,557 @@
+// C ABI of the gfx950 radio ray tracer (declared in include/rt.h): context
+// and scene handles, host-side argument validation, scratch management and
+// the launch sequences of the coverage, path and gradient computations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rt.h"
+#include "kernels.h"
+#include "scene.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+rt_status fail(rt_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define RT_HIP(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return fail(e_ == hipErrorOutOfMemory ? RT_ERR_OOM : RT_ERR_DEVICE,                        \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                            \
+    } while (0)
+
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kC0 = 299792458.0;
+constexpr int64_t kChunk = int64_t(1) << 24;  // rays per launch sequence (queue memory bound)
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+hipError_t ensure(DevBuf& b, size_t bytes) {
+    if (b.bytes >= bytes) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e == hipSuccess) b.bytes = bytes;
+    return e;
+}
+
+}  // namespace
+
+struct rt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 256;
+    DevBuf queue[2];
+    DevBuf counters;   // uint32 [64]
+    DevBuf table;      // candidate prefix table
+    DevBuf cands;
+    DevBuf rx;         // double [nrx][3]
+    DevBuf rx_ant;     // Antenna [nrx]
+    DevBuf paths;      // unsorted path records
+    int64_t last_candidates = 0;
+};
+
+struct rt_scene {
+    rt_ctx* ctx = nullptr;
+    rt::HostScene host;
+    std::vector<rt_material> mats;
+    DevBuf nodes, tris, shades, faces, face_tris;
+    rt::DevScene dev{};
+};
+
+namespace {
+
+bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+rt_status check_device(const rt_device* d, const char* what, double max_abs) {
+    if (!d) return fail(RT_ERR_ARG, std::string(what) + " is NULL");
+    if (!finite3(d->pos) || !std::isfinite(d->yaw) || !std::isfinite(d->pitch) || !std::isfinite(d->roll))
+        return fail(RT_ERR_ARG, std::string(what) + " has a non-finite position or orientation");
+    if (d->pattern != RT_PATTERN_ISO && d->pattern != RT_PATTERN_TR38901)
+        return fail(RT_ERR_ARG, std::string(what) + " has an unknown antenna pattern");
+    if (d->pol != RT_POL_V) return fail(RT_ERR_ARG, std::string(what) + " has an unsupported polarisation");
+    if (max_abs > 0)
+        for (int i = 0; i < 3; ++i)
+            if (std::fabs(d->pos[i]) > 4.0 * max_abs)
+                return fail(RT_ERR_ARG, std::string(what) + " lies more than 4x the scene extent from the origin");
+    return RT_OK;
+}
+
+rt_status check_params(const rt_trace_params* p) {
+    if (!p) return fail(RT_ERR_ARG, "params is NULL");
+    if (!(p->freq_hz > 0) || !std::isfinite(p->freq_hz)) return fail(RT_ERR_ARG, "freq_hz must be positive");
+    if (p->max_depth < 0 || p->max_depth > 8) return fail(RT_ERR_ARG, "max_depth must be in [0, 8]");
+    if (p->num_rays < 1 || p->num_rays > (int64_t(1) << 40)) return fail(RT_ERR_ARG, "num_rays must be in [1, 2^40]");
+    if (!(p->t_min >= 0) || !std::isfinite(p->t_min)) return fail(RT_ERR_ARG, "t_min must be finite and >= 0");
+    if (p->ray_begin < 0 || p->ray_begin >= p->num_rays) return fail(RT_ERR_ARG, "ray_begin must be in [0, N)");
+    if (p->ray_stride < 1) return fail(RT_ERR_ARG, "ray_stride must be >= 1");
+    int64_t count = (p->num_rays - p->ray_begin + p->ray_stride - 1) / p->ray_stride;
+    if (count >= (int64_t(1) << 31)) return fail(RT_ERR_ARG, "more than 2^31 - 1 traced rays per call");
+    return RT_OK;
+}
+
+int64_t traced_count(const rt_trace_params* p) {
+    return (p->num_rays - p->ray_begin + p->ray_stride - 1) / p->ray_stride;
+}
+
+void rot(double yaw, double pitch, double roll, double R[9]) {
+    double cy = std::cos(yaw), sy = std::sin(yaw), cp = std::cos(pitch), sp = std::sin(pitch);
+    double cr = std::cos(roll), sr = std::sin(roll);
+    // Rz(yaw) Ry(pitch) Rx(roll)
+    R[0] = cy * cp; R[1] = cy * sp * sr - sy * cr; R[2] = cy * sp * cr + sy * sr;
+    R[3] = sy * cp; R[4] = sy * sp * sr + cy * cr; R[5] = sy * sp * cr - cy * sr;
+    R[6] = -sp;     R[7] = cp * sr;                R[8] = cp * cr;
+}
+
+rt::Antenna make_antenna(const rt_device* d) {
+    rt::Antenna a{};
+    rot(d->yaw, d->pitch, d->roll, a.Rd);
+    for (int i = 0; i < 9; ++i) a.R[i] = (float)a.Rd[i];
+    a.pattern = d->pattern;
+    return a;
+}
+
+rt::MatTable make_mats(const rt_scene* s, double freq) {
+    rt::MatTable t{};
+    const double w = 2.0 * M_PI * freq;
+    for (size_t i = 0; i < s->mats.size(); ++i) {
+        rt::Mat& m = t.m[i];
+        const double er = s->mats[i].eps_r, sg = s->mats[i].sigma;
+        m.pec = std::isinf(sg) ? 1 : 0;
+        m.eta_re_d = er;
+        m.eta_im_d = m.pec ? 0.0 : -sg / (kEps0 * w);
+        m.eta_re = (float)m.eta_re_d;
+        m.eta_im = (float)m.eta_im_d;
+    }
+    return t;
+}
+
+rt_status check_materials(const rt_material* mats, int32_t nm) {
+    if (!mats || nm < 1 || nm > rt::kMaxMaterials)
+        return fail(RT_ERR_ARG, "number of materials must be in [1, " + std::to_string(rt::kMaxMaterials) + "]");
+    for (int32_t i = 0; i < nm; ++i) {
+        if (!(mats[i].eps_r > 0) || !std::isfinite(mats[i].eps_r))
+            return fail(RT_ERR_ARG, "material " + std::to_string(i) + ": eps_r must be finite and positive");
+        if (!(mats[i].sigma >= 0) || std::isnan(mats[i].sigma))
+            return fail(RT_ERR_ARG, "material " + std::to_string(i) + ": sigma must be >= 0 (or +inf)");
+    }
+    return RT_OK;
+}
+
+// Band permutation for coherent ray order: F = largest Fibonacci number
+// <= sqrt(64 pi count), G the one before it (0 disables).
+void band_perm(int64_t count, int64_t stride, int64_t& F, int64_t& G) {
+    F = G = 0;
+    if (stride != 1 || count < 256) return;
+    double target = std::sqrt(64.0 * M_PI * (double)count);
+    int64_t a = 1, b = 2;
+    while ((double)(a + b) <= target) {
+        int64_t c = a + b;
+        a = b;
+        b = c;
+    }
+    F = b;
+    G = a;
+}
+
+int grid_for(const rt_ctx* c) { return c->num_cu * 8; }
+
+// Runs the shoot-and-bounce launches for all rays of one transmitter.
+rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx, const rt_device* rx_ant,
+                  const rt_grid* g, int mode, float* gain, uint32_t* hits, uint64_t* stats, int32_t* rec_tri,
+                  double* rec_t, uint64_t* table, uint64_t table_mask, uint32_t* overflow) {
+    const int64_t count = traced_count(p);
+    const int64_t chunk = std::min(count, kChunk);
+    RT_HIP(ensure(c->queue[0], (size_t)chunk * sizeof(rt::RayState)));
+    RT_HIP(ensure(c->queue[1], (size_t)chunk * sizeof(rt::RayState)));
+    RT_HIP(ensure(c->counters, 64 * sizeof(uint32_t)));
+    rt::MatTable mats = make_mats(s, p->freq_hz);
+    rt::SbrArgs a{};
+    a.sc = s->dev;
+    a.num_rays = p->num_rays;
+    a.begin = p->ray_begin;
+    a.stride = p->ray_stride;
+    a.count = count;
+    band_perm(count, p->ray_stride, a.perm_f, a.perm_g);
+    a.tmin = p->t_min;
+    for (int i = 0; i < 3; ++i) a.tx[i] = tx->pos[i];
+    a.tx_ant = make_antenna(tx);
+    if (rx_ant) a.rx_ant = make_antenna(rx_ant);
+    if (g) {
+        a.gx0 = g->x0;
+        a.gy0 = g->y0;
+        a.gcell = g->cell;
+        a.gz = g->z;
+        a.gnx = g->nx;
+        a.gny = g->ny;
+        const double lam = kC0 / p->freq_hz;
+        a.wscale = (float)((lam / (4.0 * M_PI)) * (lam / (4.0 * M_PI)) * (4.0 * M_PI / (double)p->num_rays) /
+                           (g->cell * g->cell));
+    }
+    a.gain = gain;
+    a.hits = hits;
+    a.max_depth = p->max_depth;
+    a.stats = stats;
+    a.rec_tri = rec_tri;
+    a.rec_t = rec_t;
+    a.table = table;
+    a.table_mask = table_mask;
+    a.overflow = overflow;
+    uint32_t* cnt = (uint32_t*)c->counters.p;
+    for (int64_t pos0 = 0; pos0 < count; pos0 += chunk) {
+        a.pos0 = pos0;
+        a.chunk = std::min(chunk, count - pos0);
+        RT_HIP(hipMemsetAsync(cnt, 0, 64 * sizeof(uint32_t), c->stream));
+        for (int k = 0; k <= p->max_depth; ++k) {
+            a.depth = k;
+            a.in = k ? (const rt::RayState*)c->queue[(k - 1) & 1].p : nullptr;
+            a.in_count = k ? cnt + (k - 1) : nullptr;
+            a.out = (rt::RayState*)c->queue[k & 1].p;
+            a.out_count = cnt + k;
+            RT_HIP(rt::launch_sbr_bounce(a, mats, mode, grid_for(c), c->stream));
+        }
+    }
+    return RT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rt_last_error(void) { return g_err.c_str(); }
+
+rt_status rt_create(rt_ctx** out, int32_t device) {
+    if (!out) return fail(RT_ERR_ARG, "out is NULL");
+    int n = 0;
+    RT_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(RT_ERR_ARG, "no such HIP device");
+    RT_HIP(hipSetDevice(device));
+    rt_ctx* c = new rt_ctx();
+    c->device = device;
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0) c->num_cu = cu;
+    *out = c;
+    return RT_OK;
+}
+
+rt_status rt_destroy(rt_ctx* c) {
+    if (!c) return RT_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (DevBuf* b : {&c->queue[0], &c->queue[1], &c->counters, &c->table, &c->cands, &c->rx, &c->rx_ant, &c->paths})
+        if (b->p) (void)hipFree(b->p);
+    delete c;
+    return RT_OK;
+}
+
+rt_status rt_set_stream(rt_ctx* c, void* stream) {
+    if (!c) return fail(RT_ERR_ARG, "ctx is NULL");
+    c->stream = (hipStream_t)stream;
+    return RT_OK;
+}
+
+rt_status rt_synchronize(rt_ctx* c) {
+    if (!c) return fail(RT_ERR_ARG, "ctx is NULL");
+    RT_HIP(hipSetDevice(c->device));
+    RT_HIP(hipStreamSynchronize(c->stream));
+    return RT_OK;
+}
+
+rt_status rt_scene_create(rt_ctx* c, const float* V, int64_t nv, const int32_t* F, int64_t nt,
+                          const int32_t* tri_mat, const rt_material* mats, int32_t nm, rt_scene** out) {
+    if (!c || !V || !F || !tri_mat || !out) return fail(RT_ERR_ARG, "NULL argument");
+    if (nv < 3) return fail(RT_ERR_ARG, "need at least 3 vertices");
+    rt_status st = check_materials(mats, nm);
+    if (st != RT_OK) return st;
+    rt_scene* s = new rt_scene();
+    s->ctx = c;
+    std::string err;
+    if (rt::build_scene(V, nv, F, nt, tri_mat, nm, s->host, err) != 0) {
+        delete s;
+        return fail(RT_ERR_ARG, err);
+    }
+    s->mats.assign(mats, mats + nm);
+    hipError_t e = hipSetDevice(c->device);
+    auto up = [&](DevBuf& b, const void* src, size_t bytes) {
+        if (e != hipSuccess) return;
+        e = ensure(b, std::max<size_t>(bytes, 64));
+        if (e == hipSuccess && bytes) e = hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice);
+    };
+    const rt::HostScene& h = s->host;
+    up(s->nodes, h.nodes.data(), h.nodes.size() * sizeof(rt::Node));
+    up(s->tris, h.tris.data(), h.tris.size() * sizeof(rt::Tri));
+    up(s->shades, h.shades.data(), h.shades.size() * sizeof(rt::Shade));
+    up(s->faces, h.faces.data(), h.faces.size() * sizeof(rt::Face));
+    up(s->face_tris, h.face_tris.data(), h.face_tris.size() * sizeof(int32_t));
+    if (e != hipSuccess) {
+        rt_scene_destroy(s);
+        return fail(e == hipErrorOutOfMemory ? RT_ERR_OOM : RT_ERR_DEVICE, hipGetErrorString(e));
+    }
+    s->dev.nodes = (const rt::Node*)s->nodes.p;
+    s->dev.tris = (const rt::Tri*)s->tris.p;
+    s->dev.shades = (const rt::Shade*)s->shades.p;
+    s->dev.faces = (const rt::Face*)s->faces.p;
+    s->dev.face_tris = (const int32_t*)s->face_tris.p;
+    s->dev.num_faces = h.num_faces;
+    s->dev.nt = (int32_t)nt;
+    *out = s;
+    return RT_OK;
+}
+
+rt_status rt_scene_set_materials(rt_scene* s, const rt_material* mats, int32_t nm) {
+    if (!s) return fail(RT_ERR_ARG, "scene is NULL");
+    rt_status st = check_materials(mats, nm);
+    if (st != RT_OK) return st;
+    if ((size_t)nm != s->mats.size()) return fail(RT_ERR_ARG, "material count differs from the scene's");
+    s->mats.assign(mats, mats + nm);
+    return RT_OK;
+}
+
+rt_status rt_scene_info(const rt_scene* s, rt_scene_info_t* out) {
+    if (!s || !out) return fail(RT_ERR_ARG, "NULL argument");
+    out->num_triangles = (int64_t)s->host.tris.size();
+    out->num_faces = s->host.num_faces;
+    out->num_materials = (int32_t)s->mats.size();
+    out->bvh_nodes = (int64_t)s->host.nodes.size();
+    out->bvh_depth = s->host.depth;
+    out->reserved = 0;
+    out->build_ms = s->host.build_ms;
+    return RT_OK;
+}
+
+rt_status rt_scene_face_ids(const rt_scene* s, int32_t* ids) {
+    if (!s || !ids) return fail(RT_ERR_ARG, "NULL argument");
+    std::memcpy(ids, s->host.face_of_input.data(), s->host.face_of_input.size() * sizeof(int32_t));
+    return RT_OK;
+}
+
+rt_status rt_scene_destroy(rt_scene* s) {
+    if (!s) return RT_OK;
+    if (s->ctx) (void)hipSetDevice(s->ctx->device);
+    for (DevBuf* b : {&s->nodes, &s->tris, &s->shades, &s->faces, &s->face_tris})
+        if (b->p) (void)hipFree(b->p);
+    delete s;
+    return RT_OK;
+}
+
+rt_status rt_fibonacci_directions(rt_ctx* c, int64_t N, int64_t begin, int64_t stride, int64_t count, double* dirs) {
+    if (!c || (!dirs && count > 0)) return fail(RT_ERR_ARG, "NULL argument");
+    if (N < 1 || begin < 0 || stride < 1 || count < 0) return fail(RT_ERR_ARG, "invalid lattice range");
+    if (count > 0 && begin + (count - 1) * stride >= N) return fail(RT_ERR_ARG, "ray index beyond N");
+    RT_HIP(hipSetDevice(c->device));
+    RT_HIP(rt::launch_fib_dirs(N, begin, stride, count, dirs, c->stream));
+    return RT_OK;
+}
+
+rt_status rt_trace_record(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx, int32_t* hit_tri,
+                          double* hit_t) {
+    if (!c || !s || !hit_tri || !hit_t) return fail(RT_ERR_ARG, "NULL argument");
+    rt_status st = check_params(p);
+    if (st != RT_OK) return st;
+    if ((st = check_device(tx, "tx", s->host.max_abs)) != RT_OK) return st;
+    RT_HIP(hipSetDevice(c->device));
+    const int64_t n = traced_count(p) * (p->max_depth + 1);
+    RT_HIP(hipMemsetD32Async((hipDeviceptr_t)hit_tri, (int)-2, (size_t)n, c->stream));
+    RT_HIP(hipMemsetAsync(hit_t, 0xff, (size_t)n * sizeof(double), c->stream));  // NaN until written
+    return run_sbr(c, s, p, tx, nullptr, nullptr, rt::kModeRecord, nullptr, nullptr, nullptr, hit_tri, hit_t,
+                   nullptr, 0, nullptr);
+}
+
+rt_status rt_coverage_map(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx,
+                          const rt_device* rx_ant, const rt_grid* g, float* gain, uint32_t* hits, float* gain_db,
+                          uint64_t* ray_bounces) {
+    if (!c || !s || !g || !gain || !hits) return fail(RT_ERR_ARG, "NULL argument");
+    rt_status st = check_params(p);
+    if (st != RT_OK) return st;
+    if ((st = check_device(tx, "tx", s->host.max_abs)) != RT_OK) return st;
+    if ((st = check_device(rx_ant, "rx_ant", 0)) != RT_OK) return st;
+    if (g->nx < 1 || g->ny < 1 || (int64_t)g->nx * g->ny > (int64_t(1) << 31))
+        return fail(RT_ERR_ARG, "grid size must be positive and below 2^31 cells");
+    if (!(g->cell > 0) || !std::isfinite(g->cell) || !std::isfinite(g->x0) || !std::isfinite(g->y0) ||
+        !std::isfinite(g->z))
+        return fail(RT_ERR_ARG, "grid origin, cell size and height must be finite, cell > 0");
+    RT_HIP(hipSetDevice(c->device));
+    const int64_t cells = (int64_t)g->nx * g->ny;
+    RT_HIP(hipMemsetAsync(gain, 0, (size_t)cells * sizeof(float), c->stream));
+    RT_HIP(hipMemsetAsync(hits, 0, (size_t)cells * sizeof(uint32_t), c->stream));
+    if (ray_bounces) RT_HIP(hipMemsetAsync(ray_bounces, 0, (size_t)(p->max_depth + 1) * sizeof(uint64_t), c->stream));
+    st = run_sbr(c, s, p, tx, rx_ant, g, rt::kModeCoverage, gain, hits, ray_bounces, nullptr, nullptr, nullptr, 0,
+                 nullptr);
+    if (st != RT_OK) return st;
+    if (gain_db) RT_HIP(rt::launch_finalize_db(gain, gain_db, cells, c->stream));
+    return RT_OK;
+}
+
+rt_status rt_compute_paths(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx, int32_t ntx,
+                           const rt_device* rx, int32_t nrx, float* a, float* T, float* tau, float* aod, float* aoa,
+                           int32_t* depth, int32_t* faces, int32_t* num_paths) {
+    if (!c || !s || !tx || !rx || !a || !T || !tau || !aod || !aoa || !depth || !faces || !num_paths)
+        return fail(RT_ERR_ARG, "NULL argument");
+    rt_status st = check_params(p);
+    if (st != RT_OK) return st;
+    if (ntx < 1 || nrx < 1) return fail(RT_ERR_ARG, "need at least one tx and one rx");
+    if (p->max_paths_per_rx < 1 || p->max_paths_per_rx > 256)
+        return fail(RT_ERR_ARG, "max_paths_per_rx must be in [1, 256]");
+    for (int i = 0; i < ntx; ++i)
+        if ((st = check_device(tx + i, "tx", s->host.max_abs)) != RT_OK) return st;
+    for (int i = 0; i < nrx; ++i)
+        if ((st = check_device(rx + i, "rx", s->host.max_abs)) != RT_OK) return st;
+    RT_HIP(hipSetDevice(c->device));
+    const int P = p->max_paths_per_rx;
+    const int fd = std::max(p->max_depth, 1);
+    const int64_t count = traced_count(p);
+    // candidate prefix table: power of two >= 2 * (rays * depth), capped at 2^26
+    uint64_t want = std::max<uint64_t>(1024, 2ull * (uint64_t)count * (uint64_t)std::max(p->max_depth, 1));
+    uint64_t cap = 1024;
+    while (cap < want && cap < (1ull << 26)) cap <<= 1;
+    RT_HIP(ensure(c->table, cap * sizeof(uint64_t)));
+    RT_HIP(ensure(c->counters, 64 * sizeof(uint32_t)));
+    const uint32_t max_cand = (uint32_t)std::min<uint64_t>(cap, 1ull << 24);
+    RT_HIP(ensure(c->cands, (size_t)max_cand * sizeof(rt::Cand)));
+    RT_HIP(ensure(c->rx, (size_t)nrx * 3 * sizeof(double)));
+    RT_HIP(ensure(c->rx_ant, (size_t)nrx * sizeof(rt::Antenna)));
+    const size_t per = (size_t)nrx * P;
+    const size_t rec_bytes = per * (2 + 8 + 1 + 2 + 2) * sizeof(float) + per * (1 + fd) * sizeof(int32_t) +
+                             (size_t)nrx * sizeof(uint32_t) + 2 * sizeof(uint32_t);
+    RT_HIP(ensure(c->paths, rec_bytes));
+    std::vector<double> rxp(3 * (size_t)nrx);
+    std::vector<rt::Antenna> rxa(nrx);
+    for (int i = 0; i < nrx; ++i) {
+        for (int k = 0; k < 3; ++k) rxp[3 * i + k] = rx[i].pos[k];
+        rxa[i] = make_antenna(rx + i);
+    }
+    RT_HIP(hipMemcpy(c->rx.p, rxp.data(), rxp.size() * sizeof(double), hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(c->rx_ant.p, rxa.data(), rxa.size() * sizeof(rt::Antenna), hipMemcpyHostToDevice));
+    char* base = (char*)c->paths.p;
+    rt::PathArgs pa{};
+    pa.sc = s->dev;
+    pa.freq = p->freq_hz;
+    pa.lambda = kC0 / p->freq_hz;
+    pa.rx = (const double*)c->rx.p;
+    pa.rx_ant = (const rt::Antenna*)c->rx_ant.p;
+    pa.nrx = nrx;
+    pa.cands = (const rt::Cand*)c->cands.p;
+    pa.max_depth = p->max_depth;
+    pa.P = P;
+    pa.fd = fd;
+    pa.a = (float*)base; base += per * 2 * sizeof(float);
+    pa.T = (float*)base; base += per * 8 * sizeof(float);
+    pa.tau = (float*)base; base += per * sizeof(float);
+    pa.aod = (float*)base; base += per * 2 * sizeof(float);
+    pa.aoa = (float*)base; base += per * 2 * sizeof(float);
+    pa.depth = (int32_t*)base; base += per * sizeof(int32_t);
+    pa.faces = (int32_t*)base; base += per * fd * sizeof(int32_t);
+    pa.counts = (uint32_t*)base; base += (size_t)nrx * sizeof(uint32_t);
+    uint32_t* ncand = (uint32_t*)base;       // [0] candidates, [1] table overflow
+    pa.ncand = ncand;
+    rt::MatTable mats = make_mats(s, p->freq_hz);
+    int worst = 0;
+    std::vector<int32_t> counts_h(nrx);
+    for (int t = 0; t < ntx; ++t) {
+        RT_HIP(hipMemsetAsync(c->table.p, 0xff, cap * sizeof(uint64_t), c->stream));
+        RT_HIP(hipMemsetAsync(ncand, 0, 2 * sizeof(uint32_t), c->stream));
+        RT_HIP(hipMemsetAsync(pa.counts, 0, (size_t)nrx * sizeof(uint32_t), c->stream));
+        if (p->max_depth > 0) {
+            st = run_sbr(c, s, p, tx + t, nullptr, nullptr, rt::kModeCandidates, nullptr, nullptr, nullptr, nullptr,
+                         nullptr, (uint64_t*)c->table.p, cap - 1, ncand + 1);
+            if (st != RT_OK) return st;
+            RT_HIP(rt::launch_extract_candidates((const uint64_t*)c->table.p, cap, p->max_depth,
+                                                 (rt::Cand*)c->cands.p, ncand, max_cand, c->stream));
+        }
+        uint32_t hc[2] = {0, 0};
+        RT_HIP(hipMemcpyAsync(hc, ncand, sizeof(hc), hipMemcpyDeviceToHost, c->stream));
+        RT_HIP(hipStreamSynchronize(c->stream));
+        if (hc[1]) return fail(RT_ERR_CAPACITY, "candidate table overflow: too many distinct face sequences");
+        if (hc[0] > max_cand) return fail(RT_ERR_CAPACITY, "more than 2^24 candidate face sequences");
+        c->last_candidates = hc[0];
+        for (int k = 0; k < 3; ++k) pa.tx[k] = tx[t].pos[k];
+        pa.tx_ant = make_antenna(tx + t);
+        const int64_t items = (int64_t)nrx * ((int64_t)hc[0] + 1);
+        RT_HIP(rt::launch_image_paths(pa, mats, items, c->stream));
+        const size_t off = (size_t)t * per;
+        RT_HIP(rt::launch_sort_paths(pa, nrx, a + 2 * off, T + 8 * off, tau + off, aod + 2 * off, aoa + 2 * off,
+                                     depth + off, faces + (size_t)fd * off, num_paths + (size_t)t * nrx, c->stream));
+        RT_HIP(hipMemcpyAsync(counts_h.data(), num_paths + (size_t)t * nrx, (size_t)nrx * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, c->stream));
+        RT_HIP(hipStreamSynchronize(c->stream));
+        for (int i = 0; i < nrx; ++i) worst = std::max(worst, counts_h[i]);
+    }
+    if (worst > P)
+        return fail(RT_ERR_CAPACITY, "a receiver has " + std::to_string(worst) +
+                                         " paths; raise max_paths_per_rx to at least that");
+    return RT_OK;
+}
+
+rt_status rt_last_candidate_count(rt_ctx* c, int64_t* count) {
+    if (!c || !count) return fail(RT_ERR_ARG, "NULL argument");
+    *count = c->last_candidates;
+    return RT_OK;
+}
+
+rt_status rt_paths_power_grad(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx,
+                              const rt_device* rx, int32_t nrx, int32_t P, const int32_t* depth,
+                              const int32_t* faces, const double* dL_dP, double* grad) {
+    if (!c || !s || !rx || !depth || !faces || !dL_dP || !grad) return fail(RT_ERR_ARG, "NULL argument");
+    rt_status st = check_params(p);
+    if (st != RT_OK) return st;
+    if ((st = check_device(tx, "tx", s->host.max_abs)) != RT_OK) return st;
+    if (nrx < 1 || P < 1 || P > 256) return fail(RT_ERR_ARG, "nrx must be >= 1 and P in [1, 256]");
+    for (int i = 0; i < nrx; ++i)
+        if ((st = check_device(rx + i, "rx", s->host.max_abs)) != RT_OK) return st;
+    RT_HIP(hipSetDevice(c->device));
+    RT_HIP(ensure(c->rx, (size_t)nrx * 3 * sizeof(double)));
+    RT_HIP(ensure(c->rx_ant, (size_t)nrx * sizeof(rt::Antenna)));
+    std::vector<double> rxp(3 * (size_t)nrx);
+    std::vector<rt::Antenna> rxa(nrx);
+    for (int i = 0; i < nrx; ++i) {
+        for (int k = 0; k < 3; ++k) rxp[3 * i + k] = rx[i].pos[k];
+        rxa[i] = make_antenna(rx + i);
+    }
+    RT_HIP(hipMemcpyAsync(c->rx.p, rxp.data(), rxp.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    RT_HIP(hipMemcpyAsync(c->rx_ant.p, rxa.data(), rxa.size() * sizeof(rt::Antenna), hipMemcpyHostToDevice,
+                          c->stream));
+    RT_HIP(hipStreamSynchronize(c->stream));  // host staging vectors go out of scope
+    const int nm = (int)s->mats.size();
+    RT_HIP(hipMemsetAsync(grad, 0, (size_t)(2 * nm + 5) * sizeof(double), c->stream));
+    rt::GradArgs g{};
+    g.sc = s->dev;
+    g.freq = p->freq_hz;
+    g.lambda = kC0 / p->freq_hz;
+    for (int k = 0; k < 3; ++k) g.tx[k] = tx->pos[k];
+    g.yaw = tx->yaw;
+    g.pitch = tx->pitch;
+    g.roll = tx->roll;
+    g.tx_pattern = tx->pattern;
+    g.rx = (const double*)c->rx.p;
+    g.rx_ant = (const rt::Antenna*)c->rx_ant.p;
+    g.nrx = nrx;
+    g.P = P;
+    g.fd = std::max(p->max_depth, 1);
+    g.depth = depth;
+    g.faces = faces;
+    g.dL_dP = dL_dP;
+    g.grad = grad;
+    g.nm = nm;
+    RT_HIP(rt::launch_power_grad(g, make_mats(s, p->freq_hz), c->stream));
+    return RT_OK;
+}
+
+}  // extern "C"

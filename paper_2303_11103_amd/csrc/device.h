@@ -1,0 +1,209 @@
+// Device-side math for the gfx950 kernels: small vector and complex types,
+// antenna field patterns, Fresnel coefficients and the polarised field update
+// at a specular reflection.
+//
+// Physics (paper Sec. II: materials are (eps_r, sigma) with mu_r = 1 and the
+// polarised field components are transformed at every interaction; the
+// formulas are the textbook ones):
+//   eta     = eps_r - j sigma / (eps0 w)                (time dependence e^{+jwt})
+//   s       = sqrt(eta - sin^2 theta_i), principal branch
+//   r_perp  = (cos - s) / (cos + s),  r_par = (eta cos - s) / (eta cos + s)
+//   d'      = d - 2 (d.n) n,  e_perp = d x n / |d x n|,
+//   e_par_i = e_perp x d,  e_par_r = e_perp x d'
+//   E'      = r_perp (E.e_perp) e_perp + r_par (E.e_par_i) e_par_r
+// Antennas (Sec. II: yaw/pitch/roll orientation, preconfigured patterns):
+//   R = Rz(yaw) Ry(pitch) Rx(roll); local direction R^T d -> (theta, phi);
+//   field F = R (C_theta theta_hat + C_phi phi_hat); vertical polarisation
+//   (C_phi = 0); isotropic C_theta = 1; TR 38.901 Table 7.3-1 element:
+//   A = -min(-(A_V + A_H), 30), A_V = -min(12((theta-90)/65)^2, 30),
+//   A_H = -min(12(phi/65)^2, 30) (degrees), C_theta = 10^((8 + A)/20).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "layout.h"
+
+namespace rt {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kPatIso = 0;
+constexpr int kPatTR38901 = 1;
+constexpr int kMaxMaterials = 32;
+
+struct MatTable {
+    Mat m[kMaxMaterials];
+};
+
+// Antenna: orientation matrix (row-major) and pattern, in float and double.
+struct Antenna {
+    float R[9];
+    int32_t pattern;
+    int32_t pad;
+    double Rd[9];
+};
+
+// ---------------------------------------------------------------- float vec / complex
+struct f3 {
+    float x, y, z;
+};
+__device__ __forceinline__ f3 mk(float x, float y, float z) { return f3{x, y, z}; }
+__device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ f3 cross(f3 a, f3 b) {
+    return f3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ f3 scale(f3 a, float s) { return f3{a.x * s, a.y * s, a.z * s}; }
+
+struct cf {
+    float re, im;
+};
+__device__ __forceinline__ cf cadd(cf a, cf b) { return cf{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cf csub(cf a, cf b) { return cf{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cf cmul(cf a, cf b) { return cf{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cf cmulr(cf a, float s) { return cf{a.re * s, a.im * s}; }
+__device__ __forceinline__ cf cdiv(cf a, cf b) {
+    float den = b.re * b.re + b.im * b.im;
+    return cf{(a.re * b.re + a.im * b.im) / den, (a.im * b.re - a.re * b.im) / den};
+}
+__device__ __forceinline__ cf csqrt(cf z) {  // principal branch, cancellation-free
+    float r = hypotf(z.re, z.im);
+    if (z.re >= 0.0f) {
+        float re = sqrtf(0.5f * (r + z.re));
+        return cf{re, re > 0.0f ? z.im / (2.0f * re) : 0.0f};
+    }
+    float im = sqrtf(0.5f * (r - z.re));
+    return cf{fabsf(z.im) / (2.0f * im), copysignf(im, z.im)};
+}
+
+// ---------------------------------------------------------------- double vec / complex
+struct d3 {
+    double x, y, z;
+};
+__device__ __forceinline__ double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ d3 cross(d3 a, d3 b) {
+    return d3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ d3 sub(d3 a, d3 b) { return d3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ d3 add(d3 a, d3 b) { return d3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ d3 scale(d3 a, double s) { return d3{a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ double norm(d3 a) { return sqrt(dot(a, a)); }
+
+struct cd {
+    double re, im;
+};
+__device__ __forceinline__ cd cadd(cd a, cd b) { return cd{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cd csub(cd a, cd b) { return cd{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cd cmul(cd a, cd b) { return cd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cd cmulr(cd a, double s) { return cd{a.re * s, a.im * s}; }
+__device__ __forceinline__ cd cdiv(cd a, cd b) {
+    double den = b.re * b.re + b.im * b.im;
+    return cd{(a.re * b.re + a.im * b.im) / den, (a.im * b.re - a.re * b.im) / den};
+}
+__device__ __forceinline__ cd csqrt(cd z) {
+    double r = hypot(z.re, z.im);
+    if (z.re >= 0.0) {
+        double re = sqrt(0.5 * (r + z.re));
+        return cd{re, re > 0.0 ? z.im / (2.0 * re) : 0.0};
+    }
+    double im = sqrt(0.5 * (r - z.re));
+    return cd{fabs(z.im) / (2.0 * im), copysign(im, z.im)};
+}
+
+// ---------------------------------------------------------------- antennas
+__device__ __forceinline__ float tr38901_amp(float cos_t, float lx, float ly) {
+    constexpr float kDeg = 57.29577951308232f;
+    float th = acosf(fminf(fmaxf(cos_t, -1.0f), 1.0f)) * kDeg;
+    float ph = atan2f(ly, lx) * kDeg;
+    float av = -fminf(12.0f * ((th - 90.0f) / 65.0f) * ((th - 90.0f) / 65.0f), 30.0f);
+    float ah = -fminf(12.0f * (ph / 65.0f) * (ph / 65.0f), 30.0f);
+    float a = -fminf(-(av + ah), 30.0f);
+    return exp10f((8.0f + a) * 0.05f);
+}
+
+// Field vector of antenna `ant` towards global unit direction d.
+__device__ __forceinline__ f3 antenna_field(const Antenna& ant, f3 d) {
+    const float* R = ant.R;
+    float lx = R[0] * d.x + R[3] * d.y + R[6] * d.z;
+    float ly = R[1] * d.x + R[4] * d.y + R[7] * d.z;
+    float lz = R[2] * d.x + R[5] * d.y + R[8] * d.z;
+    float rho = sqrtf(lx * lx + ly * ly);
+    float cph = 1.0f, sph = 0.0f;
+    if (rho > 0.0f) {
+        cph = lx / rho;
+        sph = ly / rho;
+    }
+    float c = ant.pattern == kPatTR38901 ? tr38901_amp(lz, lx, ly) : 1.0f;
+    float tx = c * lz * cph, ty = c * lz * sph, tz = -c * rho;
+    return f3{R[0] * tx + R[1] * ty + R[2] * tz, R[3] * tx + R[4] * ty + R[5] * tz, R[6] * tx + R[7] * ty + R[8] * tz};
+}
+
+__device__ __forceinline__ double tr38901_amp_d(double cos_t, double lx, double ly) {
+    constexpr double kDeg = 180.0 / kPi;
+    double th = acos(fmin(fmax(cos_t, -1.0), 1.0)) * kDeg;
+    double ph = atan2(ly, lx) * kDeg;
+    double av = -fmin(12.0 * ((th - 90.0) / 65.0) * ((th - 90.0) / 65.0), 30.0);
+    double ah = -fmin(12.0 * (ph / 65.0) * (ph / 65.0), 30.0);
+    double a = -fmin(-(av + ah), 30.0);
+    return exp10((8.0 + a) / 20.0);
+}
+
+__device__ __forceinline__ d3 antenna_field(const Antenna& ant, d3 d) {
+    const double* R = ant.Rd;
+    double lx = R[0] * d.x + R[3] * d.y + R[6] * d.z;
+    double ly = R[1] * d.x + R[4] * d.y + R[7] * d.z;
+    double lz = R[2] * d.x + R[5] * d.y + R[8] * d.z;
+    double rho = sqrt(lx * lx + ly * ly);
+    double cph = 1.0, sph = 0.0;
+    if (rho > 0.0) {
+        cph = lx / rho;
+        sph = ly / rho;
+    }
+    double c = ant.pattern == kPatTR38901 ? tr38901_amp_d(lz, lx, ly) : 1.0;
+    double tx = c * lz * cph, ty = c * lz * sph, tz = -c * rho;
+    return d3{R[0] * tx + R[1] * ty + R[2] * tz, R[3] * tx + R[4] * ty + R[5] * tz, R[6] * tx + R[7] * ty + R[8] * tz};
+}
+
+// ---------------------------------------------------------------- Fresnel
+__device__ __forceinline__ void fresnel(const Mat& m, float cos_i, cf& r_perp, cf& r_par) {
+    if (m.pec) {
+        r_perp = cf{-1.0f, 0.0f};
+        r_par = cf{1.0f, 0.0f};
+        return;
+    }
+    cf eta{m.eta_re, m.eta_im};
+    float sin2 = 1.0f - cos_i * cos_i;
+    cf s = csqrt(cf{eta.re - sin2, eta.im});
+    cf c{cos_i, 0.0f};
+    r_perp = cdiv(csub(c, s), cadd(c, s));
+    cf ec = cmulr(eta, cos_i);
+    r_par = cdiv(csub(ec, s), cadd(ec, s));
+}
+
+__device__ __forceinline__ void fresnel(const Mat& m, double cos_i, cd& r_perp, cd& r_par) {
+    if (m.pec) {
+        r_perp = cd{-1.0, 0.0};
+        r_par = cd{1.0, 0.0};
+        return;
+    }
+    cd eta{m.eta_re_d, m.eta_im_d};
+    double sin2 = 1.0 - cos_i * cos_i;
+    cd s = csqrt(cd{eta.re - sin2, eta.im});
+    cd c{cos_i, 0.0};
+    r_perp = cdiv(csub(c, s), cadd(c, s));
+    cd ec = cmulr(eta, cos_i);
+    r_par = cdiv(csub(ec, s), cadd(ec, s));
+}
+
+// Unit vector perpendicular to the plane of incidence; any unit vector
+// orthogonal to d at normal incidence (the result does not depend on it).
+__device__ __forceinline__ d3 perp_basis(d3 d, d3 n) {
+    d3 e = cross(d, n);
+    double l = norm(e);
+    if (l < 1e-12) {
+        double ax = fabs(d.x), ay = fabs(d.y), az = fabs(d.z);
+        d3 a = (ax <= ay && ax <= az) ? d3{1, 0, 0} : ((ay <= az) ? d3{0, 1, 0} : d3{0, 0, 1});
+        e = sub(a, scale(d, dot(a, d)));
+        l = norm(e);
+    }
+    return scale(e, 1.0 / l);
+}
+
+}  // namespace rt

@@ -1,0 +1,127 @@
+// Launch interface between the C ABI (api.hip) and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "layout.h"
+
+namespace rt {
+
+// State of one live ray between two bounces (96 bytes, read/written coalesced
+// by consecutive lanes).
+struct alignas(16) RayState {
+    double o[3];    // origin (fp64)
+    double d[3];    // unit direction (fp64)
+    float E[6];     // field, complex Cartesian (re, im) per axis
+    int32_t excl;   // face of the last reflection (-1 at the transmitter)
+    int32_t prefix; // candidate-table slot of the face sequence so far (-1 none)
+    int32_t ray;    // lattice position j: ray index = begin + j * stride
+    int32_t pad;
+};
+static_assert(sizeof(RayState) == 96, "ray state size");
+
+constexpr uint64_t kEmptyKey = ~0ull;
+
+struct DevScene {
+    const Node* nodes;
+    const Tri* tris;
+    const Shade* shades;
+    const Face* faces;
+    const int32_t* face_tris;
+    int32_t num_faces;
+    int32_t nt;
+};
+
+struct SbrArgs {
+    DevScene sc;
+    int64_t num_rays;   // lattice size N
+    int64_t begin, stride;
+    int64_t count;      // traced rays (positions 0..count-1)
+    int64_t pos0, chunk; // positions handled by this launch sequence: [pos0, pos0 + chunk)
+    int64_t perm_f, perm_g;  // band permutation (Fibonacci numbers F_m, F_{m-1}); 0 = identity
+    double tmin;
+    double tx[3];
+    Antenna tx_ant, rx_ant;
+    // coverage
+    double gx0, gy0, gcell, gz;
+    int32_t gnx, gny;
+    float wscale;       // (lambda/4pi)^2 (4pi/N) / cell^2
+    float* gain;
+    uint32_t* hits;
+    // queues
+    int32_t depth, max_depth;
+    const RayState* in;
+    const uint32_t* in_count;
+    RayState* out;
+    uint32_t* out_count;
+    uint64_t* stats;    // [max_depth + 1] traced rays per depth (nullable)
+    // record mode
+    int32_t* rec_tri;
+    double* rec_t;
+    // candidate mode
+    uint64_t* table;
+    uint64_t table_mask;
+    uint32_t* overflow;
+};
+
+enum : int { kModeCoverage = 1, kModeRecord = 2, kModeCandidates = 4 };
+
+hipError_t launch_sbr_bounce(const SbrArgs& a, const MatTable& mats, int mode, int grid, hipStream_t s);
+hipError_t launch_fib_dirs(int64_t N, int64_t begin, int64_t stride, int64_t count, double* out, hipStream_t s);
+hipError_t launch_finalize_db(const float* gain, float* db, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------- paths
+struct Cand {
+    int32_t depth;
+    int32_t faces[8];
+};
+
+struct PathArgs {
+    DevScene sc;
+    double freq, lambda;
+    double tx[3];
+    Antenna tx_ant;
+    const double* rx;        // [nrx][3]
+    const Antenna* rx_ant;   // [nrx]
+    int32_t nrx;
+    const Cand* cands;
+    const uint32_t* ncand;   // device count
+    int32_t max_depth;
+    int32_t P;               // slots per rx
+    uint32_t* counts;        // [nrx] paths found
+    // unsorted path records
+    float* a;      // [nrx][P][2]
+    float* T;      // [nrx][P][8]
+    float* tau;    // [nrx][P]
+    float* aod;    // [nrx][P][2]
+    float* aoa;    // [nrx][P][2]
+    int32_t* depth;   // [nrx][P]
+    int32_t* faces;   // [nrx][P][FD]
+    int32_t fd;       // faces stride = max(max_depth, 1)
+};
+
+hipError_t launch_extract_candidates(const uint64_t* table, uint64_t cap, int32_t max_depth, Cand* out,
+                                     uint32_t* count, uint32_t max_out, hipStream_t s);
+hipError_t launch_image_paths(const PathArgs& a, const MatTable& mats, int64_t max_items, hipStream_t s);
+hipError_t launch_sort_paths(const PathArgs& a, int32_t nrx, float* a_out, float* T_out, float* tau_out,
+                             float* aod_out, float* aoa_out, int32_t* depth_out, int32_t* faces_out,
+                             int32_t* num_paths_out, hipStream_t s);
+
+struct GradArgs {
+    DevScene sc;
+    double freq, lambda;
+    double tx[3];
+    double yaw, pitch, roll;
+    int32_t tx_pattern;
+    const double* rx;
+    const Antenna* rx_ant;
+    int32_t nrx, P, fd;
+    const int32_t* depth;   // [nrx][P]
+    const int32_t* faces;   // [nrx][P][fd]
+    const double* dL_dP;    // [nrx]
+    double* grad;           // [2 nm + 5]
+    int32_t nm;
+};
+hipError_t launch_power_grad(const GradArgs& a, const MatTable& mats, hipStream_t s);
+
+}  // namespace rt

@@ -1,0 +1,372 @@
+// Host-side scene preparation: triangle records, face grouping and a binned
+// SAH bounding volume hierarchy laid out for the GPU traversal kernels.
+//
+// The paper models surfaces as triangle meshes whose primitives are
+// intersected by rays (Sec. II) and identifies candidate paths by ordered
+// lists of primitives (Sec. II-B).  Here a primitive of a candidate is a face:
+// a maximal set of triangles in one plane with one material, since the image
+// method depends only on the plane and the material of each interaction.
+#include "scene.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+namespace rt {
+namespace {
+
+struct Box {
+    double lo[3] = {INFINITY, INFINITY, INFINITY};
+    double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    void grow(const double* p) {
+        for (int i = 0; i < 3; ++i) {
+            lo[i] = std::min(lo[i], p[i]);
+            hi[i] = std::max(hi[i], p[i]);
+        }
+    }
+    void grow(const Box& b) {
+        for (int i = 0; i < 3; ++i) {
+            lo[i] = std::min(lo[i], b.lo[i]);
+            hi[i] = std::max(hi[i], b.hi[i]);
+        }
+    }
+    double area() const {
+        double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+        if (!(dx >= 0) || !(dy >= 0) || !(dz >= 0)) return 0.0;
+        return 2.0 * (dx * dy + dy * dz + dz * dx);
+    }
+};
+
+struct Prim {
+    Box box;
+    double c[3];
+    int32_t tri;
+};
+
+struct BuildNode {
+    Box box;
+    int32_t left = -1, right = -1;  // BuildNode indices, -1 for leaves
+    int32_t first = 0, count = 0;   // leaf range in prims
+};
+
+class Builder {
+public:
+    Builder(std::vector<Prim>& prims) : prims_(prims) {}
+
+    int32_t build(int32_t first, int32_t count, int depth) {
+        int32_t id = (int32_t)nodes_.size();
+        nodes_.emplace_back();
+        Box b, cb;
+        for (int32_t i = first; i < first + count; ++i) {
+            b.grow(prims_[i].box);
+            cb.grow(prims_[i].c);
+        }
+        nodes_[id].box = b;
+        max_depth_ = std::max(max_depth_, depth);
+        if (count <= 2) return leaf(id, first, count);
+        int force_median = (depth + (int)std::ceil(std::log2((double)count)) >= kMaxDepth - 1);
+        int axis = 0;
+        double ext[3];
+        for (int i = 0; i < 3; ++i) ext[i] = cb.hi[i] - cb.lo[i];
+        if (ext[1] > ext[axis]) axis = 1;
+        if (ext[2] > ext[axis]) axis = 2;
+        int32_t mid = -1;
+        if (!force_median && ext[axis] > 0.0) mid = sah_split(first, count, cb, b, count <= kMaxLeaf);
+        if (mid == -2) return leaf(id, first, count);
+        if (mid < 0) {  // object median along the widest centroid axis
+            mid = first + count / 2;
+            std::nth_element(prims_.begin() + first, prims_.begin() + mid, prims_.begin() + first + count,
+                             [axis](const Prim& x, const Prim& y) {
+                                 return x.c[axis] < y.c[axis] || (x.c[axis] == y.c[axis] && x.tri < y.tri);
+                             });
+        }
+        int32_t l = build(first, mid - first, depth + 1);
+        int32_t r = build(mid, first + count - mid, depth + 1);
+        nodes_[id].left = l;
+        nodes_[id].right = r;
+        return id;
+    }
+
+    std::vector<BuildNode>& nodes() { return nodes_; }
+    int max_depth() const { return max_depth_; }
+
+private:
+    int32_t leaf(int32_t id, int32_t first, int32_t count) {
+        nodes_[id].first = first;
+        nodes_[id].count = count;
+        return id;
+    }
+
+    // Binned SAH over 16 bins per axis.  Returns the split position, -2 when
+    // a leaf is cheaper (only allowed when count <= kMaxLeaf), -1 when no
+    // valid split exists.
+    int32_t sah_split(int32_t first, int32_t count, const Box& cb, const Box& b, bool leaf_ok) {
+        constexpr int kBins = 16;
+        constexpr double kTrav = 1.0, kIsect = 1.5;
+        double best = INFINITY;
+        int best_axis = -1, best_bin = -1;
+        for (int ax = 0; ax < 3; ++ax) {
+            double lo = cb.lo[ax], ext = cb.hi[ax] - cb.lo[ax];
+            if (!(ext > 0.0)) continue;
+            Box bins[kBins];
+            int cnt[kBins] = {0};
+            for (int32_t i = first; i < first + count; ++i) {
+                int k = (int)((prims_[i].c[ax] - lo) / ext * kBins);
+                k = std::min(std::max(k, 0), kBins - 1);
+                bins[k].grow(prims_[i].box);
+                cnt[k]++;
+            }
+            double right_area[kBins];
+            int right_cnt[kBins];
+            Box acc;
+            int n = 0;
+            for (int k = kBins - 1; k > 0; --k) {
+                acc.grow(bins[k]);
+                n += cnt[k];
+                right_area[k] = acc.area();
+                right_cnt[k] = n;
+            }
+            Box lacc;
+            int ln = 0;
+            for (int k = 0; k < kBins - 1; ++k) {
+                lacc.grow(bins[k]);
+                ln += cnt[k];
+                if (ln == 0 || right_cnt[k + 1] == 0) continue;
+                double cost = lacc.area() * ln + right_area[k + 1] * right_cnt[k + 1];
+                if (cost < best) {
+                    best = cost;
+                    best_axis = ax;
+                    best_bin = k;
+                }
+            }
+        }
+        if (best_axis < 0) return -1;
+        double parent = b.area();
+        double split_cost = kTrav + kIsect * best / std::max(parent, 1e-300);
+        if (leaf_ok && kIsect * count <= split_cost) return -2;
+        double lo = cb.lo[best_axis], ext = cb.hi[best_axis] - cb.lo[best_axis];
+        auto it = std::partition(prims_.begin() + first, prims_.begin() + first + count, [&](const Prim& p) {
+            int k = (int)((p.c[best_axis] - lo) / ext * kBins);
+            k = std::min(std::max(k, 0), kBins - 1);
+            return k <= best_bin;
+        });
+        int32_t mid = (int32_t)(it - prims_.begin());
+        if (mid == first || mid == first + count) return -1;
+        return mid;
+    }
+
+    std::vector<Prim>& prims_;
+    std::vector<BuildNode> nodes_;
+    int max_depth_ = 0;
+};
+
+float round_down(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = std::nextafter(f, -INFINITY);
+    return f;
+}
+float round_up(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = std::nextafter(f, INFINITY);
+    return f;
+}
+
+void cross(const double* a, const double* b, double* o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+double norm(const double* a) { return std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
+
+}  // namespace
+
+int build_scene(const float* V, int64_t nv, const int32_t* F, int64_t nt, const int32_t* tri_mat, int32_t nm,
+                HostScene& out, std::string& err) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (nt <= 0 || nt >= (int64_t(1) << 26)) {
+        err = "number of triangles must be in [1, 2^26)";
+        return -1;
+    }
+    double max_abs = 0.0;
+    for (int64_t i = 0; i < 3 * nv; ++i) {
+        if (!std::isfinite(V[i])) {
+            err = "vertex coordinate " + std::to_string(i / 3) + " is not finite";
+            return -1;
+        }
+        max_abs = std::max(max_abs, (double)std::fabs(V[i]));
+    }
+    out = HostScene();
+    out.max_abs = std::max(max_abs, 64.0);
+    out.pad = out.max_abs * std::ldexp(1.0, -20);
+
+    // ---- triangle records and canonical planes (fp64 from exact float inputs)
+    std::vector<Tri> tri(nt);
+    std::vector<Shade> shade(nt);
+    std::vector<Prim> prims(nt);
+    std::vector<double> offs(nt);
+    for (int64_t k = 0; k < nt; ++k) {
+        int32_t i0 = F[3 * k], i1 = F[3 * k + 1], i2 = F[3 * k + 2];
+        if (i0 < 0 || i1 < 0 || i2 < 0 || i0 >= nv || i1 >= nv || i2 >= nv) {
+            err = "triangle " + std::to_string(k) + " has a vertex index outside [0, nv)";
+            return -1;
+        }
+        if (tri_mat[k] < 0 || tri_mat[k] >= nm) {
+            err = "triangle " + std::to_string(k) + " has a material index outside [0, nm)";
+            return -1;
+        }
+        double p0[3], p1[3], p2[3];
+        for (int i = 0; i < 3; ++i) {
+            p0[i] = V[3 * i0 + i];
+            p1[i] = V[3 * i1 + i];
+            p2[i] = V[3 * i2 + i];
+        }
+        Tri& t = tri[k];
+        for (int i = 0; i < 3; ++i) {
+            t.v0[i] = p0[i];
+            t.e1[i] = p1[i] - p0[i];
+            t.e2[i] = p2[i] - p0[i];
+        }
+        t.thr = 1e-12 * norm(t.e1) * norm(t.e2);
+        t.orig = (int32_t)k;
+        double n[3];
+        cross(t.e1, t.e2, n);
+        double a = norm(n);
+        if (!(a > 0.0)) {
+            err = "triangle " + std::to_string(k) + " has zero area";
+            return -1;
+        }
+        for (int i = 0; i < 3; ++i) n[i] /= a;
+        int first = 0;
+        while (first < 2 && !(std::fabs(n[first]) > 1e-6)) ++first;
+        if (n[first] < 0)
+            for (int i = 0; i < 3; ++i) n[i] = -n[i];
+        for (int i = 0; i < 3; ++i) shade[k].n[i] = n[i];
+        shade[k].mat = tri_mat[k];
+        offs[k] = n[0] * p0[0] + n[1] * p0[1] + n[2] * p0[2];
+        Prim& p = prims[k];
+        p.box.grow(p0);
+        p.box.grow(p1);
+        p.box.grow(p2);
+        for (int i = 0; i < 3; ++i) p.c[i] = (p0[i] + p1[i] + p2[i]) / 3.0;
+        p.tri = (int32_t)k;
+    }
+
+    // ---- faces: (material, rint(n * 2^30), rint(c * 2^30)), numbered by first triangle
+    const double q = std::ldexp(1.0, 30);
+    std::map<std::tuple<int32_t, int64_t, int64_t, int64_t, int64_t>, int32_t> ids;
+    out.face_of_input.resize(nt);
+    std::vector<int32_t> face_first;
+    for (int64_t k = 0; k < nt; ++k) {
+        auto key = std::make_tuple(tri_mat[k], (int64_t)std::nearbyint(shade[k].n[0] * q),
+                                   (int64_t)std::nearbyint(shade[k].n[1] * q),
+                                   (int64_t)std::nearbyint(shade[k].n[2] * q), (int64_t)std::nearbyint(offs[k] * q));
+        auto it = ids.find(key);
+        int32_t f;
+        if (it == ids.end()) {
+            f = (int32_t)ids.size();
+            ids.emplace(key, f);
+            face_first.push_back((int32_t)k);
+        } else {
+            f = it->second;
+        }
+        out.face_of_input[k] = f;
+        tri[k].face = f;
+        shade[k].face = f;
+    }
+    out.num_faces = (int32_t)face_first.size();
+
+    // ---- BVH
+    Builder builder(prims);
+    builder.build(0, (int32_t)nt, 0);
+    auto& bn = builder.nodes();
+    out.depth = builder.max_depth();
+    if (out.depth > kMaxDepth) {  // the traversal stack holds kMaxDepth + 2 entries
+        err = "BVH deeper than the traversal stack";
+        return -1;
+    }
+
+    // reorder triangles by leaf order
+    out.tris.resize(nt);
+    out.shades.resize(nt);
+    std::vector<int32_t> new_of_old(nt);
+    for (int64_t i = 0; i < nt; ++i) {
+        out.tris[i] = tri[prims[i].tri];
+        out.shades[i] = shade[prims[i].tri];
+        new_of_old[prims[i].tri] = (int32_t)i;
+    }
+
+    // flatten: every inner build node becomes a GPU node holding its two
+    // children's bounds; a root leaf gets an inner wrapper.
+    auto child_ref = [&](int32_t b, auto& self) -> int32_t {
+        const BuildNode& n = bn[b];
+        if (n.left < 0) return make_leaf(n.first, n.count);
+        int32_t id = (int32_t)out.nodes.size();
+        out.nodes.emplace_back();
+        int32_t l = self(n.left, self);
+        int32_t r = self(n.right, self);
+        Node& g = out.nodes[id];
+        const Box& L = bn[n.left].box;
+        const Box& R = bn[n.right].box;
+        double p = out.pad;
+        g.a[0] = round_down(L.lo[0] - p); g.a[1] = round_up(L.hi[0] + p);
+        g.a[2] = round_down(L.lo[1] - p); g.a[3] = round_up(L.hi[1] + p);
+        g.b[0] = round_down(R.lo[0] - p); g.b[1] = round_up(R.hi[0] + p);
+        g.b[2] = round_down(R.lo[1] - p); g.b[3] = round_up(R.hi[1] + p);
+        g.c[0] = round_down(L.lo[2] - p); g.c[1] = round_up(L.hi[2] + p);
+        g.c[2] = round_down(R.lo[2] - p); g.c[3] = round_up(R.hi[2] + p);
+        g.child[0] = l;
+        g.child[1] = r;
+        g.pad[0] = g.pad[1] = 0;
+        return id;
+    };
+    if (bn[0].left < 0) {
+        Node g;
+        const Box& L = bn[0].box;
+        double p = out.pad;
+        g.a[0] = round_down(L.lo[0] - p); g.a[1] = round_up(L.hi[0] + p);
+        g.a[2] = round_down(L.lo[1] - p); g.a[3] = round_up(L.hi[1] + p);
+        g.c[0] = round_down(L.lo[2] - p); g.c[1] = round_up(L.hi[2] + p);
+        // both children are the same leaf (the second visit finds nothing new)
+        for (int i = 0; i < 4; ++i) g.b[i] = g.a[i];
+        g.c[2] = g.c[0];
+        g.c[3] = g.c[1];
+        g.child[0] = g.child[1] = make_leaf(bn[0].first, bn[0].count);
+        g.pad[0] = g.pad[1] = 0;
+        out.nodes.push_back(g);
+        out.depth = 1;
+    } else {
+        child_ref(0, child_ref);
+    }
+
+    // ---- faces with their triangles (reordered indices)
+    out.faces.resize(out.num_faces);
+    std::vector<int32_t> cnt(out.num_faces, 0);
+    for (int64_t k = 0; k < nt; ++k) cnt[out.face_of_input[k]]++;
+    int32_t acc = 0;
+    for (int32_t f = 0; f < out.num_faces; ++f) {
+        Face& fc = out.faces[f];
+        int32_t k = face_first[f];
+        for (int i = 0; i < 3; ++i) {
+            fc.n[i] = shade[k].n[i];
+            fc.q[i] = tri[k].v0[i];
+        }
+        fc.mat = tri_mat[k];
+        fc.first = acc;
+        fc.count = cnt[f];
+        fc.pad = 0;
+        acc += cnt[f];
+    }
+    out.face_tris.resize(nt);
+    std::vector<int32_t> fill(out.num_faces, 0);
+    for (int64_t k = 0; k < nt; ++k) {
+        int32_t f = out.face_of_input[k];
+        out.face_tris[out.faces[f].first + fill[f]++] = new_of_old[k];
+    }
+    out.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return 0;
+}
+
+}  // namespace rt

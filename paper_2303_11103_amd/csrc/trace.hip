@@ -1,0 +1,242 @@
+// Shoot-and-bounce kernels for gfx950 (paper Sec. II-B: rays shot in
+// Fibonacci-lattice directions propagate through the scene with specular
+// reflections until the maximum depth; Sec. II-A: coverage maps of path
+// gain; Sec. II: per-interaction transformation of the polarised field).
+//
+// One launch per bounce ("wavefront" organisation):
+//   bounce 0 generates rays in coherence order and traces them;
+//   bounce k > 0 reads the compacted queue of rays that survived bounce k-1.
+// Each launch runs a persistent, wave-strided loop.  Per ray: closest hit
+// (fp32 conservative slab tests on a binary BVH with a per-lane LDS stack,
+// fp64 Moller-Trumbore on triangles), coverage deposit of the segment, then
+// Fresnel reflection of the field and a wave-ballot compaction into the next
+// queue (one atomic per wave).
+#include "traverse.h"
+
+namespace rt {
+namespace {
+
+__device__ __forceinline__ d3 fib_dir(int64_t i, int64_t N) {
+    double z = 1.0 - (2.0 * (double)i + 1.0) / (double)N;
+    double rho = sqrt((1.0 - z) * (1.0 + z));
+    uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+    double phi = 2.0 * kPi * ((double)h * 0x1p-64);
+    double s, c;
+    sincos(phi, &s, &c);
+    return d3{rho * c, rho * s, z};
+}
+
+// Traced position j -> lattice index.  With a band permutation, positions are
+// taken in bands of F consecutive indices (a thin latitude ring); inside a
+// band, rank r maps to offset r * G mod F (G the preceding Fibonacci number),
+// which walks the ring in azimuth order, so 64 consecutive positions form a
+// compact patch of directions.
+__device__ __forceinline__ int64_t ray_index(const SbrArgs& a, int64_t j) {
+    if (a.perm_f > 0) {
+        const int64_t F = a.perm_f;
+        const int64_t full = (a.count / F) * F;
+        if (j < full) {
+            int64_t b = j / F, r = j - b * F;
+            j = b * F + (r * a.perm_g) % F;
+        }
+    }
+    return a.begin + j * a.stride;
+}
+
+__device__ __forceinline__ uint32_t mix32(uint64_t k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return (uint32_t)k;
+}
+
+// Insert (parent slot, face) into the open-addressing table of candidate
+// prefixes; returns the slot, which identifies the face sequence.
+__device__ int32_t cand_insert(uint64_t* table, uint64_t mask, int32_t parent, int32_t face, uint32_t* overflow) {
+    const uint64_t key = ((uint64_t)(uint32_t)(parent + 1) << 32) | (uint32_t)face;
+    uint64_t h = mix32(key) & mask;
+    for (int probe = 0; probe < 256; ++probe) {
+        uint64_t cur = __hip_atomic_load(table + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == key) return (int32_t)h;
+        if (cur == kEmptyKey) {
+            uint64_t prev = atomicCAS((unsigned long long*)(table + h), (unsigned long long)kEmptyKey,
+                                      (unsigned long long)key);
+            if (prev == kEmptyKey || prev == key) return (int32_t)h;
+        }
+        h = (h + 1) & mask;
+    }
+    atomicOr(overflow, 1u);
+    return -2;
+}
+
+template <int MODE, bool FIRST>
+__global__ __launch_bounds__(kBlock) void sbr_bounce(SbrArgs a, MatTable mats) {
+    __shared__ int32_t stack[kStack][kBlock];
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+    const int64_t count = FIRST ? a.chunk : (int64_t)(*a.in_count);
+    if (a.stats && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd((unsigned long long*)&a.stats[a.depth], (unsigned long long)count);
+    for (int64_t base = wave * 64; base < count; base += nwaves * 64) {
+        const int64_t item = base + lane;
+        const bool active = item < count;
+        RayState st;
+        if (active) {
+            if (FIRST) {
+                const int64_t j = a.pos0 + item;
+                const int64_t ri = ray_index(a, j);
+                const d3 d = fib_dir(ri, a.num_rays);
+                st.o[0] = a.tx[0];
+                st.o[1] = a.tx[1];
+                st.o[2] = a.tx[2];
+                st.d[0] = d.x;
+                st.d[1] = d.y;
+                st.d[2] = d.z;
+                const f3 F = antenna_field(a.tx_ant, f3{(float)d.x, (float)d.y, (float)d.z});
+                st.E[0] = F.x;
+                st.E[1] = 0.0f;
+                st.E[2] = F.y;
+                st.E[3] = 0.0f;
+                st.E[4] = F.z;
+                st.E[5] = 0.0f;
+                st.excl = -1;
+                st.prefix = -1;
+                st.ray = (int32_t)((ri - a.begin) / a.stride);  // lattice position (unpermuted)
+                st.pad = 0;
+            } else {
+                st = a.in[item];
+            }
+        }
+        bool alive = false;
+        if (active) {
+            const d3 o{st.o[0], st.o[1], st.o[2]};
+            const d3 d{st.d[0], st.d[1], st.d[2]};
+            double tbest = __builtin_inf();
+            const int best = traverse<false>(a.sc, o, d, st.excl, st.excl, a.tmin, tbest, stack);
+            if (MODE & kModeRecord) {
+                const int64_t at = (int64_t)a.depth * a.count + st.ray;
+                a.rec_tri[at] = best >= 0 ? a.sc.tris[best].orig : -1;
+                a.rec_t[at] = tbest;
+            }
+            if (MODE & kModeCoverage) {
+                const double dz = d.z;
+                if (fabs(dz) >= 1e-12) {
+                    const double tc = (a.gz - o.z) / dz;
+                    if (tc > 0.0 && tc < tbest) {
+                        const double x = o.x + tc * d.x, y = o.y + tc * d.y;
+                        const double fx = floor((x - a.gx0) / a.gcell), fy = floor((y - a.gy0) / a.gcell);
+                        if (fx >= 0.0 && fx < (double)a.gnx && fy >= 0.0 && fy < (double)a.gny) {
+                            const f3 fr = antenna_field(a.rx_ant, f3{(float)-d.x, (float)-d.y, (float)-d.z});
+                            const float ar = fr.x * st.E[0] + fr.y * st.E[2] + fr.z * st.E[4];
+                            const float ai = fr.x * st.E[1] + fr.y * st.E[3] + fr.z * st.E[5];
+                            const float w = a.wscale * (ar * ar + ai * ai) / fabsf((float)dz);
+                            const int64_t cell = (int64_t)fy * a.gnx + (int64_t)fx;
+                            atomicAdd(a.gain + cell, w);
+                            atomicAdd(a.hits + cell, 1u);
+                        }
+                    }
+                }
+            }
+            if (best >= 0 && a.depth < a.max_depth) {
+                alive = true;
+                const Shade sh = a.sc.shades[best];
+                d3 n{sh.n[0], sh.n[1], sh.n[2]};
+                if (dot(d, n) > 0.0) n = scale(n, -1.0);
+                const double cos_i = -dot(d, n);
+                const d3 dr = add(d, scale(n, 2.0 * cos_i));
+                const d3 p = add(o, scale(d, tbest));
+                const d3 ep = perp_basis(d, n);
+                const d3 eli = cross(ep, d);
+                const d3 elr = cross(ep, dr);
+                cf rp, rl;
+                fresnel(mats.m[sh.mat], (float)cos_i, rp, rl);
+                const f3 fep{(float)ep.x, (float)ep.y, (float)ep.z};
+                const f3 feli{(float)eli.x, (float)eli.y, (float)eli.z};
+                const f3 felr{(float)elr.x, (float)elr.y, (float)elr.z};
+                const cf Ex{st.E[0], st.E[1]}, Ey{st.E[2], st.E[3]}, Ez{st.E[4], st.E[5]};
+                const cf ap{fep.x * Ex.re + fep.y * Ey.re + fep.z * Ez.re, fep.x * Ex.im + fep.y * Ey.im + fep.z * Ez.im};
+                const cf al{feli.x * Ex.re + feli.y * Ey.re + feli.z * Ez.re,
+                            feli.x * Ex.im + feli.y * Ey.im + feli.z * Ez.im};
+                const cf sp = cmul(rp, ap), sl = cmul(rl, al);
+                st.E[0] = sp.re * fep.x + sl.re * felr.x;
+                st.E[1] = sp.im * fep.x + sl.im * felr.x;
+                st.E[2] = sp.re * fep.y + sl.re * felr.y;
+                st.E[3] = sp.im * fep.y + sl.im * felr.y;
+                st.E[4] = sp.re * fep.z + sl.re * felr.z;
+                st.E[5] = sp.im * fep.z + sl.im * felr.z;
+                st.o[0] = p.x;
+                st.o[1] = p.y;
+                st.o[2] = p.z;
+                st.d[0] = dr.x;
+                st.d[1] = dr.y;
+                st.d[2] = dr.z;
+                st.excl = sh.face;
+                if (MODE & kModeCandidates) {
+                    if (st.prefix != -2) st.prefix = cand_insert(a.table, a.table_mask, st.prefix, sh.face, a.overflow);
+                }
+            }
+        }
+        // wave-ballot compaction of the survivors into the next queue
+        const uint64_t m = __ballot(alive);
+        if (m) {
+            uint32_t b = 0;
+            if (lane == 0) b = atomicAdd(a.out_count, (uint32_t)__popcll(m));
+            b = __shfl(b, 0);
+            if (alive) a.out[b + __popcll(m & ((1ull << lane) - 1ull))] = st;
+        }
+    }
+}
+
+__global__ void fib_dirs_kernel(int64_t N, int64_t begin, int64_t stride, int64_t count, double* out) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    d3 d = fib_dir(begin + j * stride, N);
+    out[3 * j] = d.x;
+    out[3 * j + 1] = d.y;
+    out[3 * j + 2] = d.z;
+}
+
+__global__ void finalize_db_kernel(const float* __restrict__ g, float* __restrict__ db, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float v = g[i];
+    db[i] = v > 0.0f ? 10.0f * log10f(v) : -__builtin_inff();
+}
+
+template <int MODE>
+hipError_t launch_mode(const SbrArgs& a, const MatTable& mats, int grid, hipStream_t s) {
+    if (a.depth == 0)
+        hipLaunchKernelGGL((sbr_bounce<MODE, true>), dim3(grid), dim3(kBlock), 0, s, a, mats);
+    else
+        hipLaunchKernelGGL((sbr_bounce<MODE, false>), dim3(grid), dim3(kBlock), 0, s, a, mats);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sbr_bounce(const SbrArgs& a, const MatTable& mats, int mode, int grid, hipStream_t s) {
+    switch (mode) {
+        case kModeCoverage: return launch_mode<kModeCoverage>(a, mats, grid, s);
+        case kModeRecord: return launch_mode<kModeRecord>(a, mats, grid, s);
+        case kModeCandidates: return launch_mode<kModeCandidates>(a, mats, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fib_dirs(int64_t N, int64_t begin, int64_t stride, int64_t count, double* out, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(fib_dirs_kernel, dim3((unsigned)blocks), dim3(256), 0, s, N, begin, stride, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_db(const float* gain, float* db, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(finalize_db_kernel, dim3((unsigned)blocks), dim3(256), 0, s, gain, db, n);
+    return hipGetLastError();
+}
+
+}  // namespace rt

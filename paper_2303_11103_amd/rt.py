@@ -1,0 +1,215 @@
+"""Python facade over the C ABI: device tensors come from PyTorch, every step
+of the computation runs in the HIP library.
+
+Device buffers are torch tensors on the context's GPU; work is enqueued on
+torch's current stream for that device.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import check, lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+@dataclass
+class TraceParams:
+    freq_hz: float
+    max_depth: int
+    num_rays: int
+    t_min: float = 1e-4
+    ray_begin: int = 0
+    ray_stride: int = 1
+    max_paths_per_rx: int = 64
+
+    def c(self):
+        return L.rt_trace_params(float(self.freq_hz), int(self.max_depth), int(self.max_paths_per_rx),
+                                 int(self.num_rays), float(self.t_min), int(self.ray_begin), int(self.ray_stride))
+
+    def traced(self) -> int:
+        return (self.num_rays - self.ray_begin + self.ray_stride - 1) // self.ray_stride
+
+
+def device_struct(dev) -> L.rt_device:
+    """rt_device from any object with pos, yaw, pitch, roll, pattern (pol defaults to V)."""
+    d = L.rt_device()
+    for i in range(3):
+        d.pos[i] = float(dev.pos[i])
+    d.yaw, d.pitch, d.roll = float(dev.yaw), float(dev.pitch), float(dev.roll)
+    d.pattern = int(getattr(dev, "pattern", 0))
+    d.pol = int(getattr(dev, "pol", 0))
+    return d
+
+
+def grid_struct(g) -> L.rt_grid:
+    return L.rt_grid(float(g.x0), float(g.y0), float(g.cell), float(g.z), int(g.nx), int(g.ny))
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.device = int(device)
+        self.torch_device = torch.device("cuda", self.device)
+        h = ctypes.c_void_p()
+        check(lib.rt_create(ctypes.byref(h), self.device))
+        self.h = h
+
+    def _bind_stream(self):
+        s = torch.cuda.current_stream(self.torch_device).cuda_stream
+        check(lib.rt_set_stream(self.h, ctypes.c_void_p(s)))
+
+    def synchronize(self):
+        check(lib.rt_synchronize(self.h))
+
+    def close(self):
+        if self.h:
+            lib.rt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Scene:
+    """A triangle mesh with materials on the device (BVH built at creation)."""
+
+    def __init__(self, ctx: Context, V, F, tri_mat, materials):
+        self.ctx = ctx
+        V = np.ascontiguousarray(V, dtype=np.float32)
+        F = np.ascontiguousarray(F, dtype=np.int32)
+        tri_mat = np.ascontiguousarray(tri_mat, dtype=np.int32)
+        mats = np.ascontiguousarray(materials, dtype=np.float32).reshape(-1, 2)
+        marr = (L.rt_material * len(mats))(*[L.rt_material(float(e), float(s)) for e, s in mats])
+        h = ctypes.c_void_p()
+        check(lib.rt_scene_create(ctx.h, V.ctypes.data_as(ctypes.c_void_p), V.shape[0],
+                                  F.ctypes.data_as(ctypes.c_void_p), F.shape[0],
+                                  tri_mat.ctypes.data_as(ctypes.c_void_p), marr, len(mats), ctypes.byref(h)))
+        self.h = h
+        self.nt = int(F.shape[0])
+        self.nm = len(mats)
+
+    @classmethod
+    def from_scenegen(cls, ctx, s):
+        return cls(ctx, s.V, s.F, s.tri_mat, s.materials)
+
+    def set_materials(self, materials):
+        mats = np.ascontiguousarray(materials, dtype=np.float32).reshape(-1, 2)
+        marr = (L.rt_material * len(mats))(*[L.rt_material(float(e), float(s)) for e, s in mats])
+        check(lib.rt_scene_set_materials(self.h, marr, len(mats)))
+
+    def info(self) -> dict:
+        inf = L.rt_scene_info_t()
+        check(lib.rt_scene_info(self.h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in L.rt_scene_info_t._fields_ if k != "reserved"}
+
+    def face_ids(self) -> np.ndarray:
+        out = np.empty(self.nt, dtype=np.int32)
+        check(lib.rt_scene_face_ids(self.h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def close(self):
+        if self.h:
+            lib.rt_scene_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fibonacci_directions(ctx: Context, num_rays, begin=0, stride=1, count=None):
+    if count is None:
+        count = (num_rays - begin + stride - 1) // stride
+    out = torch.empty((count, 3), dtype=torch.float64, device=ctx.torch_device)
+    ctx._bind_stream()
+    check(lib.rt_fibonacci_directions(ctx.h, num_rays, begin, stride, count, _ptr(out)))
+    return out
+
+
+def trace_record(ctx: Context, scene: Scene, params: TraceParams, tx):
+    n = params.traced()
+    tri = torch.empty((params.max_depth + 1, n), dtype=torch.int32, device=ctx.torch_device)
+    t = torch.empty((params.max_depth + 1, n), dtype=torch.float64, device=ctx.torch_device)
+    ctx._bind_stream()
+    p, d = params.c(), device_struct(tx)
+    check(lib.rt_trace_record(ctx.h, scene.h, ctypes.byref(p), ctypes.byref(d), _ptr(tri), _ptr(t)))
+    return tri, t
+
+
+def coverage_map(ctx: Context, scene: Scene, params: TraceParams, tx, grid, rx_ant=None, out=None, want_db=True,
+                 want_stats=True):
+    """Returns dict(gain, hits, gain_db, ray_bounces) of device tensors."""
+    if out is None:
+        out = {"gain": torch.empty((grid.ny, grid.nx), dtype=torch.float32, device=ctx.torch_device),
+               "hits": torch.empty((grid.ny, grid.nx), dtype=torch.int32, device=ctx.torch_device)}
+        if want_db:
+            out["gain_db"] = torch.empty((grid.ny, grid.nx), dtype=torch.float32, device=ctx.torch_device)
+        if want_stats:
+            out["ray_bounces"] = torch.empty(params.max_depth + 1, dtype=torch.int64, device=ctx.torch_device)
+    from types import SimpleNamespace
+    rx_ant = rx_ant or SimpleNamespace(pos=(0.0, 0.0, 0.0), yaw=0.0, pitch=0.0, roll=0.0, pattern=0)
+    ctx._bind_stream()
+    p, t, r, g = params.c(), device_struct(tx), device_struct(rx_ant), grid_struct(grid)
+    check(lib.rt_coverage_map(ctx.h, scene.h, ctypes.byref(p), ctypes.byref(t), ctypes.byref(r), ctypes.byref(g),
+                              _ptr(out["gain"]), _ptr(out["hits"]), _ptr(out.get("gain_db")),
+                              _ptr(out.get("ray_bounces"))))
+    return out
+
+
+def compute_paths(ctx: Context, scene: Scene, params: TraceParams, txs, rxs):
+    """Paths for every (tx, rx); returns dict of device tensors shaped [ntx, nrx, P, ...]."""
+    ntx, nrx, P = len(txs), len(rxs), params.max_paths_per_rx
+    fd = max(params.max_depth, 1)
+    dev = ctx.torch_device
+    o = {
+        "a": torch.empty((ntx, nrx, P, 2), dtype=torch.float32, device=dev),
+        "T": torch.empty((ntx, nrx, P, 2, 2, 2), dtype=torch.float32, device=dev),
+        "tau": torch.empty((ntx, nrx, P), dtype=torch.float32, device=dev),
+        "aod": torch.empty((ntx, nrx, P, 2), dtype=torch.float32, device=dev),
+        "aoa": torch.empty((ntx, nrx, P, 2), dtype=torch.float32, device=dev),
+        "depth": torch.empty((ntx, nrx, P), dtype=torch.int32, device=dev),
+        "faces": torch.empty((ntx, nrx, P, fd), dtype=torch.int32, device=dev),
+        "num_paths": torch.empty((ntx, nrx), dtype=torch.int32, device=dev),
+    }
+    tx_arr = (L.rt_device * ntx)(*[device_struct(t) for t in txs])
+    rx_arr = (L.rt_device * nrx)(*[device_struct(r) for r in rxs])
+    ctx._bind_stream()
+    p = params.c()
+    check(lib.rt_compute_paths(ctx.h, scene.h, ctypes.byref(p), tx_arr, ntx, rx_arr, nrx, _ptr(o["a"]), _ptr(o["T"]),
+                               _ptr(o["tau"]), _ptr(o["aod"]), _ptr(o["aoa"]), _ptr(o["depth"]), _ptr(o["faces"]),
+                               _ptr(o["num_paths"])))
+    return o
+
+
+def last_candidate_count(ctx: Context) -> int:
+    n = ctypes.c_int64()
+    check(lib.rt_last_candidate_count(ctx.h, ctypes.byref(n)))
+    return int(n.value)
+
+
+def paths_power_grad(ctx: Context, scene: Scene, params: TraceParams, tx, rxs, depth, faces, dL_dP):
+    """sum_r dL_dP[r] dP_r/dtheta for theta = (eps_r, sigma) per material, tx xyz, yaw, pitch (float64 tensor)."""
+    nrx = len(rxs)
+    depth = depth.contiguous().to(torch.int32)
+    faces = faces.contiguous().to(torch.int32)
+    dL_dP = dL_dP.contiguous().to(torch.float64)
+    P = depth.shape[-1]
+    grad = torch.empty(2 * scene.nm + 5, dtype=torch.float64, device=ctx.torch_device)
+    rx_arr = (L.rt_device * nrx)(*[device_struct(r) for r in rxs])
+    ctx._bind_stream()
+    p, t = params.c(), device_struct(tx)
+    check(lib.rt_paths_power_grad(ctx.h, scene.h, ctypes.byref(p), ctypes.byref(t), rx_arr, nrx, P, _ptr(depth),
+                                  _ptr(faces), _ptr(dL_dP), _ptr(grad)))
+    return grad

@@ -1,0 +1,157 @@
+"""GPU parity of ray generation, closest-hit tracing and coverage maps
+against the FP64 oracle (all calls go through the C ABI)."""
+import numpy as np
+import pytest
+import torch
+
+import scenegen as sg
+from oracle import fib, geom, sbr
+
+from gpu_common import compare_hits, ctx, lib, oracle_params, params, requires_gpu, scene
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+def test_fibonacci_directions_match_oracle():
+    m = lib()
+    for (N, b, s) in ((1, 0, 1), (1000, 0, 1), (10_000_000, 3, 997), (100_000_000, 99_999_000, 1)):
+        d = m.fibonacci_directions(ctx(), N, b, s).cpu().numpy()
+        ref = fib.directions(N, fib.subset(N, b, s))
+        assert d.shape == ref.shape
+        assert np.max(np.abs(d - ref)) < 4e-15
+
+
+def test_scene_faces_match_oracle_grouping():
+    for s in (sg.make_toy(), sg.make_urban(0), sg.make_city(0, blocks=8)):
+        sc = scene(s)
+        ref, nf = geom.face_ids(s.V, s.F, s.tri_mat)
+        assert np.array_equal(sc.face_ids(), ref)
+        info = sc.info()
+        assert info["num_faces"] == nf and info["num_triangles"] == s.nt
+        assert info["bvh_depth"] <= 30
+
+
+@pytest.mark.parametrize("case", ["toy", "urban_stride", "urban_full_small", "city_stride"])
+def test_hits_match_oracle(case):
+    m = lib()
+    if case == "toy":
+        w = sg.toy_workload()
+        p = params(w)
+    elif case == "urban_stride":
+        w = sg.urban_workload()
+        p = params(w, ray_begin=7, ray_stride=61)       # 163 935 rays of the 1e7 lattice
+    elif case == "urban_full_small":
+        w = sg.urban_workload(num_rays=150_001)          # whole lattice: coherent band order on
+        p = params(w)
+    else:
+        w = sg.city_workload(num_rays=100_000_000, blocks=12)
+        p = params(w, ray_begin=11, ray_stride=2003)     # 49 925 rays of the 1e8 lattice, 5 bounces
+    tri, t = m.trace_record(ctx(), scene(w.scene), p, w.tx[0])
+    orc = sbr.trace(w.scene, w.tx[0], oracle_params(p), record=True)
+    compared, excluded = compare_hits(tri.cpu().numpy(), t.cpu().numpy(), orc)
+    assert compared >= p.traced() and excluded <= max(3, p.traced() // 10000)
+
+
+def test_hits_full_lattice_sampled():
+    """The bench configuration (urban, 1e7 rays, coherent order, 3 bounces):
+    every traced ray is recorded; a random sample is re-traced by the oracle."""
+    m = lib()
+    w = sg.urban_workload()
+    p = params(w)
+    tri, t = m.trace_record(ctx(), scene(w.scene), p, w.tx[0])
+    tri = tri.cpu().numpy()
+    t = t.cpu().numpy()
+    assert np.all(tri[0] >= -1)  # every ray traced its first segment
+    rng = np.random.default_rng(5)
+    pos = np.sort(rng.choice(p.num_rays, size=4000, replace=False))
+    for k in range(len(pos) // 1000):
+        sub = pos[k * 1000:(k + 1) * 1000]
+        # the oracle traces exactly these lattice indices
+        orc = sbr.trace(w.scene, w.tx[0], oracle_params(p), record=True, idx=sub)
+        compare_hits(tri[:, sub], t[:, sub], orc)
+
+
+def _coverage_case(name):
+    if name == "toy":
+        w = sg.toy_workload()
+        return w, params(w)
+    if name == "urban":
+        w = sg.urban_workload(num_rays=400_003)
+        return w, params(w)
+    if name == "urban_tr38901":
+        w = sg.diff_workload(num_rays=300_000)
+        return w, params(w)
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["toy", "urban", "urban_tr38901"])
+def test_coverage_matches_oracle(name):
+    m = lib()
+    w, p = _coverage_case(name)
+    out = m.coverage_map(ctx(), scene(w.scene), p, w.tx[0], w.grid)
+    gain = out["gain"].cpu().numpy().astype(np.float64)
+    hits = out["hits"].cpu().numpy()
+    db = out["gain_db"].cpu().numpy()
+    rb = out["ray_bounces"].cpu().numpy()
+    g_ref, h_ref, n_amb = sbr.coverage(w.scene, w.tx[0], oracle_params(p), w.grid)
+    allowed = 2 * (p.max_depth + 1) * n_amb
+    # hit counts are integers decided in fp64 on both sides
+    assert int((hits != h_ref).sum()) <= allowed
+    # every cell with >= 16 hits within 0.1 dB; in fact all agree to fp32 accumulation error
+    cmp = (h_ref >= 16) & (hits == h_ref)
+    assert cmp.sum() > 50
+    ddb = np.abs(10 * np.log10(gain[cmp]) - 10 * np.log10(g_ref[cmp]))
+    assert ddb.max() < 0.1
+    both = (h_ref > 0) & (hits == h_ref)
+    rel = np.abs(gain[both] - g_ref[both]) / g_ref[both]
+    assert np.quantile(rel, 0.999) < 1e-4 and int((rel > 1e-3).sum()) <= allowed
+    # dB output and empty cells
+    assert np.all(np.isneginf(db[hits == 0]))
+    assert np.allclose(db[hits > 0], 10 * np.log10(gain[hits > 0]), atol=1e-5)
+    # ray-bounce counters: first segment for every ray, then the survivors
+    assert rb[0] == p.traced() and np.all(np.diff(rb) <= 0)
+
+
+def test_coverage_full_lattice_equals_sum_of_sublattices():
+    """Bench configuration (urban, 1e7 rays, depth 3): the full map equals the
+    sum of the maps of 10 disjoint sub-lattices (same kernels, different
+    launch shapes), up to fp32 atomic ordering."""
+    m = lib()
+    w = sg.urban_workload()
+    p = params(w)
+    sc = scene(w.scene)
+    full = m.coverage_map(ctx(), sc, p, w.tx[0], w.grid)
+    g_full = full["gain"].double()
+    h_full = full["hits"].clone()
+    g_sum = torch.zeros_like(g_full)
+    h_sum = torch.zeros_like(h_full)
+    rb = 0
+    for b in range(10):
+        o = m.coverage_map(ctx(), sc, params(w, ray_begin=b, ray_stride=10), w.tx[0], w.grid)
+        g_sum += o["gain"].double()
+        h_sum += o["hits"]
+        rb += int(o["ray_bounces"].sum())
+    assert torch.equal(h_full, h_sum)
+    assert rb == int(full["ray_bounces"].sum())
+    nz = h_full > 0
+    rel = ((g_full - g_sum).abs() / g_sum.clamp_min(1e-30))[nz]
+    assert float(rel.max()) < 1e-4
+    assert int(h_full.sum()) > 1_000_000
+
+
+def test_argument_errors_are_reported():
+    m = lib()
+    from paper_2303_11103_amd._lib import RTError
+    w = sg.toy_workload()
+    sc = scene(w.scene)
+    with pytest.raises(RTError, match="max_depth"):
+        m.coverage_map(ctx(), sc, params(w, max_depth=9), w.tx[0], w.grid)
+    with pytest.raises(RTError, match="ray_stride"):
+        m.coverage_map(ctx(), sc, params(w, ray_stride=0), w.tx[0], w.grid)
+    bad = sg.Device((float("nan"), 0.0, 10.0))
+    with pytest.raises(RTError, match="non-finite"):
+        m.coverage_map(ctx(), sc, params(w), bad, w.grid)
+    with pytest.raises(RTError, match="vertex index"):
+        F = w.scene.F.copy()
+        F[0, 0] = 10_000
+        m.Scene(ctx(), w.scene.V, F, w.scene.tri_mat, w.scene.materials)
