@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Benchmark of the ray tracer's hot path on one MI355X.
+
+Workload (timed step): the coverage map of the urban-canyon scene -- 8x8 box
+buildings (770 triangles, concrete/glass at 3.5 GHz), one isotropic V-pol
+transmitter 2 m above a roof corner, 1e7 Fibonacci-lattice rays, up to 3
+specular reflections, 400x400 cells of 1 m at 1.5 m height.  One step =
+Fibonacci ray generation, closest-hit BVH traversal, coverage deposit,
+Fresnel reflection and queue compaction for every bounce, then the dB map.
+
+Prints one JSON line: value = ray-bounces (closest-hit queries, counted on
+the device) per second; roofline of the shoot-and-bounce kernel family
+(algorithmic FLOPs from counted BVH node visits and triangle tests, divided
+by the kernels' HIP-event durations); the FP64 CPU oracle timed on a
+bounded ray sample of the same workload; and side measurements of the paths
+(image method) and gradient kernels.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BJ_METRIC = "M ray-bounces/s + coverage-map ms vs oracle; surrogate maps/s at <=3 dB RMSE"
+# Algorithmic work per unit ("Roofline"): one BVH inner-node
+# visit = two fp32 slab tests = 12 FMA-equivalent flops each; one triangle
+# test = fp64 Moller-Trumbore, 42 flops; per traced segment the coverage
+# deposit and, for survivors, the Fresnel reflection and field update:
+# 325 flops.
+FLOP_NODE = 24.0
+FLOP_TRI = 42.0
+FLOP_SEGMENT = 325.0
+# MI355X VALU: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s,
+# FMA = 2 flops -> 78.6 TFLOP/s for fp64 and for non-packed fp32 (the build
+# disables packed fp32).
+PEAK_ALU_TFLOPS = 78.6
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(seconds_budget: float = 20.0):
+    """Time the FP64 oracle on a strided sample of the same workload."""
+    import numpy as np
+    import scenegen as sg
+    from oracle import native, sbr
+    w = sg.urban_workload()
+    threads = native.default_threads()
+    stride = 1000
+    # grow the sample until it takes a meaningful time (bounded)
+    while True:
+        p = sbr.TraceParams(num_rays=w.num_rays, max_depth=w.max_depth, ray_begin=0, ray_stride=stride)
+        t0 = time.perf_counter()
+        r = sbr.trace(w.scene, w.tx[0], p, grid=w.grid, record=True, threads=threads)
+        dt = time.perf_counter() - t0
+        segs = int(sum(int((h != -2).sum()) for h in r.hit_tri))
+        if dt > seconds_budget / 4 or stride <= 10:
+            break
+        stride = max(10, int(stride * max(0.1, dt / seconds_budget)))
+    return {"value": segs / dt / 1e6, "unit": "M ray-bounces/s", "cores": threads, "kind": "oracle",
+            "sample": "urban canyon, lattice rays 0, %d, 2*%d, ... of 1e7 (%d rays, %d ray-bounces, depth 3, "
+                      "coverage on), %.1f s" % (stride, stride, len(r.ray_idx), segs, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the paths/gradient side measurements")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the shoot-and-bounce workload of one transmitter runs on a single "
+              "MI355X (see DESIGN.md for how it would shard); got --gpus %d" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import paper_2303_11103_amd as rt
+    from paper_2303_11103_amd._lib import check, lib
+    import scenegen as sg
+
+    dev = torch.device("cuda", 0)
+    w = sg.urban_workload()
+    ctx = rt.Context(0)
+    scene = rt.Scene.from_scenegen(ctx, w.scene)
+    info = scene.info()
+    p = rt.TraceParams(w.scene.freq_hz, w.max_depth, w.num_rays)
+    tx = w.tx[0]
+    out = {"gain": torch.empty((w.grid.ny, w.grid.nx), dtype=torch.float32, device=dev),
+           "hits": torch.empty((w.grid.ny, w.grid.nx), dtype=torch.int32, device=dev),
+           "gain_db": torch.empty((w.grid.ny, w.grid.nx), dtype=torch.float32, device=dev),
+           "ray_bounces": torch.empty(w.max_depth + 1, dtype=torch.int64, device=dev)}
+    log("bench: urban canyon, %d rays, depth %d, BVH %d nodes (build %.1f ms)" % (
+        w.num_rays, w.max_depth, info["bvh_nodes"], info["build_ms"]))
+    for _ in range(args.warmup):
+        rt.coverage_map(ctx, scene, p, tx, w.grid, out=out)
+    torch.cuda.synchronize()
+    log("bench: warmup done")
+
+    nd = w.max_depth + 1
+    check(lib.rt_profile_enable(ctx.h, 1))
+    stream = torch.cuda.current_stream(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        rt.coverage_map(ctx, scene, p, tx, w.grid, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    check(lib.rt_profile_enable(ctx.h, 0))
+    launches = (ctypes.c_int64 * nd)()
+    kms = (ctypes.c_double * nd)()
+    check(lib.rt_profile_read(ctx.h, nd, launches, kms))
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_step_ev = ev0.elapsed_time(ev1) / args.steps
+    rb_depth = out["ray_bounces"].cpu().numpy().astype(np.int64)
+    ray_bounces = int(rb_depth.sum())
+    value = ray_bounces / (ms_step / 1e3) / 1e6
+    log("bench: %.3f ms/step (events %.3f), %d ray-bounces/step -> %.1f M ray-bounces/s" % (
+        ms_step, ms_step_ev, ray_bounces, value))
+
+    # work counters (one extra, untimed run with per-ray counters)
+    work = torch.zeros(3 * nd, dtype=torch.int64, device=dev)
+    g2 = torch.empty_like(out["gain"])
+    h2 = torch.empty_like(out["hits"])
+    pc, tc, rc, gc = p.c(), rt.rt.device_struct(tx), rt.rt.device_struct(w.rx_ant), rt.rt.grid_struct(w.grid)
+    ctx._bind_stream()
+    check(lib.rt_coverage_work(ctx.h, scene.h, ctypes.byref(pc), ctypes.byref(tc), ctypes.byref(rc),
+                               ctypes.byref(gc), ctypes.c_void_p(g2.data_ptr()), ctypes.c_void_p(h2.data_ptr()),
+                               ctypes.c_void_p(work.data_ptr())))
+    wk = work.cpu().numpy().reshape(3, nd)
+    assert np.array_equal(wk[0], rb_depth), (wk[0], rb_depth)
+    flops_depth = FLOP_NODE * wk[1] + FLOP_TRI * wk[2] + FLOP_SEGMENT * wk[0]
+    k_ms = np.asarray(list(kms)) / np.maximum(1, np.asarray(list(launches)))  # per launch, per depth
+    per_launch_flops = flops_depth.sum()
+    per_step_kernel_ms = float(k_ms.sum())
+    achieved = per_launch_flops / (per_step_kernel_ms / 1e3) / 1e12
+    dom = int(np.argmax(k_ms))
+    roofline = {
+        "bound": "alu",
+        "achieved": round(float(achieved), 3),
+        "peak": PEAK_ALU_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(float(achieved / PEAK_ALU_TFLOPS), 4),
+        "traffic": None,
+        "kernel": "sbr_bounce (all %d bounce launches of a step)" % nd,
+        "kernel_ms_per_depth": [round(float(x), 4) for x in k_ms],
+        "dominant_launch": "depth %d, %.3f ms" % (dom, float(k_ms[dom])),
+        "node_visits_per_ray_bounce": round(float(wk[1].sum() / wk[0].sum()), 2),
+        "tri_tests_per_ray_bounce": round(float(wk[2].sum() / wk[0].sum()), 2),
+        "flop_per_ray_bounce": round(float(per_launch_flops / wk[0].sum()), 1),
+    }
+    log("bench: kernels %.3f ms/step, %.2f TFLOP/s algorithmic (%.1f%% of %.1f)" % (
+        per_step_kernel_ms, achieved, 100 * achieved / PEAK_ALU_TFLOPS, PEAK_ALU_TFLOPS))
+
+    result = {
+        "metric": BJ_METRIC,
+        "value": round(value, 2),
+        "unit": "M ray-bounces/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 geometry + f32 field",
+        "data": "synthetic",
+        "config": {"workload": "urban canyon coverage map: 8x8 boxes (770 tris), 1e7 rays, depth 3, "
+                               "400x400 cells of 1 m, 3.5 GHz",
+                   "num_rays": w.num_rays, "max_depth": w.max_depth, "grid": [w.grid.ny, w.grid.nx],
+                   "triangles": int(w.scene.nt)},
+        "coverage_map_ms": round(ms_step, 4),
+        "ray_bounces_per_step": ray_bounces,
+        "roofline": roofline,
+    }
+
+    if not args.no_extras:
+        try:
+            result.update(extras(rt, ctx, scene, w, torch))
+        except Exception as e:  # side measurements must not hide the main line
+            log("bench: extras failed: %r" % (e,))
+            result["extras_error"] = repr(e)
+
+    if not args.no_cpu_baseline:
+        log("bench: timing the FP64 oracle on a ray sample ...")
+        cb = cpu_baseline()
+        cb["vs_gpu"] = round(value / cb["value"], 1)
+        result["cpu_baseline"] = cb
+    print(json.dumps(result), flush=True)
+
+
+def extras(rt, ctx, scene, w, torch):
+    """Paths for the workload's 16 receivers and the power gradient (timed)."""
+    import scenegen as sg
+    res = {}
+    p = rt.TraceParams(w.scene.freq_hz, w.max_depth, w.num_rays, max_paths_per_rx=64)
+    rt.compute_paths(ctx, scene, p, w.tx, w.rx)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    o = rt.compute_paths(ctx, scene, p, w.tx, w.rx)
+    torch.cuda.synchronize()
+    res["paths_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+    res["paths_found"] = int(o["num_paths"].sum())
+    res["path_candidates"] = rt.last_candidate_count(ctx)
+    d = sg.diff_workload()
+    pd = rt.TraceParams(d.scene.freq_hz, d.max_depth, d.num_rays, max_paths_per_rx=64)
+    sd = scene if d.scene.digest() == w.scene.digest() else rt.Scene.from_scenegen(ctx, d.scene)
+    od = rt.compute_paths(ctx, sd, pd, d.tx, d.rx)
+    torch.cuda.synchronize()
+    dL = torch.ones(len(d.rx), dtype=torch.float64, device=ctx.torch_device)
+    rt.paths_power_grad(ctx, sd, pd, d.tx[0], d.rx, od["depth"][0], od["faces"][0], dL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        rt.paths_power_grad(ctx, sd, pd, d.tx[0], d.rx, od["depth"][0], od["faces"][0], dL)
+    torch.cuda.synchronize()
+    res["grad_ms"] = round((time.perf_counter() - t0) * 1e3 / 10, 4)
+    res["grad_paths"] = int((od["depth"][0] >= 0).sum())
+    return res
+
+
+if __name__ == "__main__":
+    main()

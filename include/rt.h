@@ -171,6 +171,22 @@ rt_status rt_coverage_map(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p
                           const rt_device* rx_ant, const rt_grid* grid, float* gain, uint32_t* hits,
                           float* gain_db, uint64_t* ray_bounces);
 
+/* rt_coverage_map that also counts, per depth k, the traced rays, the BVH
+ * inner nodes visited and the triangles tested:
+ *   work [3][max_depth+1] (dev) uint64 (rays, node visits, triangle tests).
+ * The counters add atomics per ray; meant for measuring the work per
+ * ray-bounce, not for production runs. */
+rt_status rt_coverage_work(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p, const rt_device* tx,
+                           const rt_device* rx_ant, const rt_grid* grid, float* gain, uint32_t* hits, uint64_t* work);
+
+/* Launch timing for measurement tools: while enabled, every shoot-and-bounce
+ * launch of this context is bracketed by HIP events on its stream.
+ * rt_profile_read waits for the recorded launches and returns, for depths
+ * k < n, the number of launches and their summed duration in milliseconds
+ * (launches [n], ms [n], host), then clears the record. */
+rt_status rt_profile_enable(rt_ctx* ctx, int32_t enable);
+rt_status rt_profile_read(rt_ctx* ctx, int32_t n, int64_t* launches, double* ms);
+
 /* Paths between ntx transmitters and nrx receivers (Sec. II-A
  * compute_paths; Sec. II-B): for every transmitter the lattice rays are shot
  * (max_depth reflections), the face sequence of every hit prefix becomes a

@@ -69,6 +69,10 @@ SIGNATURES = {
     "rt_trace_record": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), P, P],
     "rt_coverage_map": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), ctypes.POINTER(rt_device),
                         ctypes.POINTER(rt_grid), P, P, P, P],
+    "rt_coverage_work": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), ctypes.POINTER(rt_device),
+                         ctypes.POINTER(rt_grid), P, P, P],
+    "rt_profile_enable": [P, I32],
+    "rt_profile_read": [P, I32, P, P],
     "rt_compute_paths": [P, P, ctypes.POINTER(rt_trace_params), P, I32, P, I32, P, P, P, P, P, P, P, P],
     "rt_last_candidate_count": [P, ctypes.POINTER(I64)],
     "rt_paths_power_grad": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), P, I32, I32, P, P,
@@ -85,7 +89,7 @@ class RTError(RuntimeError):
 
 def load(path: str = LIB_PATH):
     if not os.path.exists(path):
-        raise ImportError("HIP library %s is not built; run `python -m paper_2303_11103_amd.build`" % path)
+        raise ImportError("HIP library %s is not built; run `python paper_2303_11103_amd/build.py`" % path)
     lib = ctypes.CDLL(path)
     for name, args in SIGNATURES.items():
         fn = getattr(lib, name)

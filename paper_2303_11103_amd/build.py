@@ -1,6 +1,6 @@
 """Build the gfx950 shared library (the C ABI declared in include/rt.h).
 
-    python -m paper_2303_11103_amd.build
+    python paper_2303_11103_amd/build.py
 
 compiles every HIP and C++ source under ``csrc/`` with hipcc for gfx950 into
 ``paper_2303_11103_amd/librt_mi355x.so``.  Packed fp32 instructions are

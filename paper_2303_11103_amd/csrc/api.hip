@@ -67,6 +67,15 @@ struct rt_ctx {
     DevBuf rx_ant;     // Antenna [nrx]
     DevBuf paths;      // unsorted path records
     int64_t last_candidates = 0;
+    // launch timing of the shoot-and-bounce kernels
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct Rec {
+        int depth;
+        hipEvent_t start, stop;
+    };
+    std::vector<Rec> recs;
+    size_t ev_used = 0;
 };
 
 struct rt_scene {
@@ -177,7 +186,8 @@ int grid_for(const rt_ctx* c) { return c->num_cu * 8; }
 // Runs the shoot-and-bounce launches for all rays of one transmitter.
 rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx, const rt_device* rx_ant,
                   const rt_grid* g, int mode, float* gain, uint32_t* hits, uint64_t* stats, int32_t* rec_tri,
-                  double* rec_t, uint64_t* table, uint64_t table_mask, uint32_t* overflow) {
+                  double* rec_t, uint64_t* table, uint64_t table_mask, uint32_t* overflow,
+                  uint64_t* work = nullptr) {
     const int64_t count = traced_count(p);
     const int64_t chunk = std::min(count, kChunk);
     RT_HIP(ensure(c->queue[0], (size_t)chunk * sizeof(rt::RayState)));
@@ -210,6 +220,7 @@ rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_dev
     a.hits = hits;
     a.max_depth = p->max_depth;
     a.stats = stats;
+    a.work = work;
     a.rec_tri = rec_tri;
     a.rec_t = rec_t;
     a.table = table;
@@ -226,7 +237,22 @@ rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_dev
             a.in_count = k ? cnt + (k - 1) : nullptr;
             a.out = (rt::RayState*)c->queue[k & 1].p;
             a.out_count = cnt + k;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (c->profiling) {
+                while (c->ev_pool.size() < c->ev_used + 2) {
+                    hipEvent_t e;
+                    RT_HIP(hipEventCreate(&e));
+                    c->ev_pool.push_back(e);
+                }
+                e0 = c->ev_pool[c->ev_used++];
+                e1 = c->ev_pool[c->ev_used++];
+                RT_HIP(hipEventRecord(e0, c->stream));
+            }
             RT_HIP(rt::launch_sbr_bounce(a, mats, mode, grid_for(c), c->stream));
+            if (c->profiling) {
+                RT_HIP(hipEventRecord(e1, c->stream));
+                c->recs.push_back({k, e0, e1});
+            }
         }
     }
     return RT_OK;
@@ -258,6 +284,7 @@ rt_status rt_destroy(rt_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     for (DevBuf* b : {&c->queue[0], &c->queue[1], &c->counters, &c->table, &c->cands, &c->rx, &c->rx_ant, &c->paths})
         if (b->p) (void)hipFree(b->p);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
     return RT_OK;
 }
@@ -375,9 +402,10 @@ rt_status rt_trace_record(rt_ctx* c, rt_scene* s, const rt_trace_params* p, cons
                    nullptr, 0, nullptr);
 }
 
-rt_status rt_coverage_map(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx,
-                          const rt_device* rx_ant, const rt_grid* g, float* gain, uint32_t* hits, float* gain_db,
-                          uint64_t* ray_bounces) {
+namespace {
+rt_status coverage_impl(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx,
+                        const rt_device* rx_ant, const rt_grid* g, float* gain, uint32_t* hits, float* gain_db,
+                        uint64_t* ray_bounces, uint64_t* work) {
     if (!c || !s || !g || !gain || !hits) return fail(RT_ERR_ARG, "NULL argument");
     rt_status st = check_params(p);
     if (st != RT_OK) return st;
@@ -393,10 +421,51 @@ rt_status rt_coverage_map(rt_ctx* c, rt_scene* s, const rt_trace_params* p, cons
     RT_HIP(hipMemsetAsync(gain, 0, (size_t)cells * sizeof(float), c->stream));
     RT_HIP(hipMemsetAsync(hits, 0, (size_t)cells * sizeof(uint32_t), c->stream));
     if (ray_bounces) RT_HIP(hipMemsetAsync(ray_bounces, 0, (size_t)(p->max_depth + 1) * sizeof(uint64_t), c->stream));
-    st = run_sbr(c, s, p, tx, rx_ant, g, rt::kModeCoverage, gain, hits, ray_bounces, nullptr, nullptr, nullptr, 0,
-                 nullptr);
+    if (work) RT_HIP(hipMemsetAsync(work, 0, (size_t)3 * (p->max_depth + 1) * sizeof(uint64_t), c->stream));
+    st = run_sbr(c, s, p, tx, rx_ant, g, work ? (rt::kModeCoverage | rt::kModeStats) : rt::kModeCoverage, gain, hits,
+                 ray_bounces, nullptr, nullptr, nullptr, 0, nullptr, work);
     if (st != RT_OK) return st;
     if (gain_db) RT_HIP(rt::launch_finalize_db(gain, gain_db, cells, c->stream));
+    return RT_OK;
+}
+}  // namespace
+
+rt_status rt_coverage_map(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx,
+                          const rt_device* rx_ant, const rt_grid* g, float* gain, uint32_t* hits, float* gain_db,
+                          uint64_t* ray_bounces) {
+    return coverage_impl(c, s, p, tx, rx_ant, g, gain, hits, gain_db, ray_bounces, nullptr);
+}
+
+rt_status rt_coverage_work(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx,
+                           const rt_device* rx_ant, const rt_grid* g, float* gain, uint32_t* hits, uint64_t* work) {
+    if (!work) return fail(RT_ERR_ARG, "work is NULL");
+    return coverage_impl(c, s, p, tx, rx_ant, g, gain, hits, nullptr, nullptr, work);
+}
+
+rt_status rt_profile_enable(rt_ctx* c, int32_t enable) {
+    if (!c) return fail(RT_ERR_ARG, "ctx is NULL");
+    c->profiling = enable != 0;
+    return RT_OK;
+}
+
+rt_status rt_profile_read(rt_ctx* c, int32_t n, int64_t* launches, double* ms) {
+    if (!c || n < 0 || (n > 0 && (!launches || !ms))) return fail(RT_ERR_ARG, "invalid argument");
+    RT_HIP(hipSetDevice(c->device));
+    for (int i = 0; i < n; ++i) {
+        launches[i] = 0;
+        ms[i] = 0.0;
+    }
+    for (const auto& r : c->recs) {
+        RT_HIP(hipEventSynchronize(r.stop));
+        float t = 0.0f;
+        RT_HIP(hipEventElapsedTime(&t, r.start, r.stop));
+        if (r.depth < n) {
+            launches[r.depth] += 1;
+            ms[r.depth] += t;
+        }
+    }
+    c->recs.clear();
+    c->ev_used = 0;
     return RT_OK;
 }
 

@@ -55,6 +55,7 @@ struct SbrArgs {
     RayState* out;
     uint32_t* out_count;
     uint64_t* stats;    // [max_depth + 1] traced rays per depth (nullable)
+    uint64_t* work;     // stats mode: [3][max_depth + 1] rays, inner-node visits, triangle tests
     // record mode
     int32_t* rec_tri;
     double* rec_t;
@@ -64,7 +65,7 @@ struct SbrArgs {
     uint32_t* overflow;
 };
 
-enum : int { kModeCoverage = 1, kModeRecord = 2, kModeCandidates = 4 };
+enum : int { kModeCoverage = 1, kModeRecord = 2, kModeCandidates = 4, kModeStats = 8 };
 
 hipError_t launch_sbr_bounce(const SbrArgs& a, const MatTable& mats, int mode, int grid, hipStream_t s);
 hipError_t launch_fib_dirs(int64_t N, int64_t begin, int64_t stride, int64_t count, double* out, hipStream_t s);

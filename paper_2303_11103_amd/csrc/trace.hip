@@ -114,7 +114,15 @@ __global__ __launch_bounds__(kBlock) void sbr_bounce(SbrArgs a, MatTable mats) {
             const d3 o{st.o[0], st.o[1], st.o[2]};
             const d3 d{st.d[0], st.d[1], st.d[2]};
             double tbest = __builtin_inf();
-            const int best = traverse<false>(a.sc, o, d, st.excl, st.excl, a.tmin, tbest, stack);
+            TravStats ts;
+            const int best =
+                traverse<false, (MODE & kModeStats) != 0>(a.sc, o, d, st.excl, st.excl, a.tmin, tbest, stack, &ts);
+            if (MODE & kModeStats) {
+                const int nd = a.max_depth + 1;
+                atomicAdd((unsigned long long*)&a.work[a.depth], 1ull);
+                atomicAdd((unsigned long long*)&a.work[nd + a.depth], (unsigned long long)ts.nodes);
+                atomicAdd((unsigned long long*)&a.work[2 * nd + a.depth], (unsigned long long)ts.tris);
+            }
             if (MODE & kModeRecord) {
                 const int64_t at = (int64_t)a.depth * a.count + st.ray;
                 a.rec_tri[at] = best >= 0 ? a.sc.tris[best].orig : -1;
@@ -221,6 +229,7 @@ hipError_t launch_sbr_bounce(const SbrArgs& a, const MatTable& mats, int mode, i
         case kModeCoverage: return launch_mode<kModeCoverage>(a, mats, grid, s);
         case kModeRecord: return launch_mode<kModeRecord>(a, mats, grid, s);
         case kModeCandidates: return launch_mode<kModeCandidates>(a, mats, grid, s);
+        case kModeCoverage | kModeStats: return launch_mode<kModeCoverage | kModeStats>(a, mats, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -62,9 +62,15 @@ __device__ __forceinline__ bool tri_test(const Tri* __restrict__ tris, int k, d3
 }
 
 // Closest hit (ANY = false) or any hit on an open segment (ANY = true).
-template <bool ANY>
+// Work counters of one traversal (inner nodes visited, triangles tested).
+struct TravStats {
+    uint32_t nodes = 0;
+    uint32_t tris = 0;
+};
+
+template <bool ANY, bool STATS = false>
 __device__ __forceinline__ int traverse(const DevScene& sc, d3 o, d3 d, int excl0, int excl1, double tmin,
-                                        double& tbest, int32_t (*stack)[kBlock]) {
+                                        double& tbest, int32_t (*stack)[kBlock], TravStats* ts = nullptr) {
     const int tid = threadIdx.x;
     const float ox = (float)o.x, oy = (float)o.y, oz = (float)o.z;
     const float ix = safe_inv(d.x), iy = safe_inv(d.y), iz = safe_inv(d.z);
@@ -74,6 +80,7 @@ __device__ __forceinline__ int traverse(const DevScene& sc, d3 o, d3 d, int excl
     int node = 0, sp = 0;
     while (true) {
         if (node >= 0) {
+            if (STATS) ts->nodes++;
             const float4* np = reinterpret_cast<const float4*>(sc.nodes + node);
             const float4 A = np[0], B = np[1], C = np[2];
             const int4 ch = reinterpret_cast<const int4*>(np)[3];
@@ -104,6 +111,7 @@ __device__ __forceinline__ int traverse(const DevScene& sc, d3 o, d3 d, int excl
         } else {
             const int code = ~node;
             const int first = code >> kLeafShift, cnt = (code & (kMaxLeaf - 1)) + 1;
+            if (STATS) ts->tris += cnt;
             for (int k = first; k < first + cnt; ++k) {
                 if (tri_test(sc.tris, k, o, d, excl0, excl1, tmin, tbest, ANY)) {
                     best = k;
