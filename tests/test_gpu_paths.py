@@ -121,8 +121,9 @@ def test_los_only_depth_zero():
 def test_power_gradient_matches_finite_differences(pattern):
     m = lib()
     w = sg.diff_workload(num_rays=100_000)
-    if pattern == "iso":
+    if pattern == "iso":  # untilted isotropic V-pol: rotating about z leaves its field unchanged
         w.tx[0].pattern = sg.PATTERN_ISO
+        w.tx[0].pitch = 0.0
     w.rx = w.rx[:40]
     p = params(w, max_paths_per_rx=64)
     sc = scene(w.scene)
