@@ -29,14 +29,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 BJ_METRIC = "M ray-bounces/s + coverage-map ms vs oracle; surrogate maps/s at <=3 dB RMSE"
-# Algorithmic work per unit ("Roofline"): one BVH inner-node
-# visit = two fp32 slab tests = 12 FMA-equivalent flops each; one triangle
-# test = fp64 Moller-Trumbore, 42 flops; per traced segment the coverage
-# deposit and, for survivors, the Fresnel reflection and field update:
-# 325 flops.
-FLOP_NODE = 24.0
-FLOP_TRI = 42.0
-FLOP_SEGMENT = 325.0
+# Algorithmic work per unit (floating-point operations the method needs; an
+# FMA counts 2, an add/mul/min/max/compare 1):
+#   BVH inner-node visit = two fp32 ray/box slab tests: 12 FMA + 24 min/max
+#     + 6 for the interval tests = 54;
+#   triangle test = fp64 Moller-Trumbore without division: 46;
+#   every traced segment: coverage-plane crossing, cell index, receive
+#     pattern and |F_rx . E|^2 deposit: 40;
+#   every surviving ray (reflection): Fresnel r_perp/r_par (complex sqrt and
+#     two complex divisions), perpendicular/parallel bases, reflected
+#     direction and hit point, 3-vector complex field update: 160;
+#   every ray at depth 0: Fibonacci direction (z, rho, sincos of the golden
+#     phase) and transmit pattern: 70.
+FLOP_NODE = 54.0
+FLOP_TRI = 46.0
+FLOP_DEPOSIT = 40.0
+FLOP_REFLECT = 160.0
+FLOP_RAYGEN = 70.0
 # MI355X VALU: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s,
 # FMA = 2 flops -> 78.6 TFLOP/s for fp64 and for non-packed fp32 (the build
 # disables packed fp32).
@@ -55,19 +64,19 @@ def cpu_baseline(seconds_budget: float = 20.0):
     w = sg.urban_workload()
     threads = native.default_threads()
     stride = 1000
-    # grow the sample until it takes a meaningful time (bounded)
+    # grow the sample until it takes about seconds_budget (bounded: at most all rays)
     while True:
         p = sbr.TraceParams(num_rays=w.num_rays, max_depth=w.max_depth, ray_begin=0, ray_stride=stride)
         t0 = time.perf_counter()
         r = sbr.trace(w.scene, w.tx[0], p, grid=w.grid, record=True, threads=threads)
         dt = time.perf_counter() - t0
         segs = int(sum(int((h != -2).sum()) for h in r.hit_tri))
-        if dt > seconds_budget / 4 or stride <= 10:
+        if dt > seconds_budget / 3 or stride == 1:
             break
-        stride = max(10, int(stride * max(0.1, dt / seconds_budget)))
+        stride = max(1, int(stride * dt / seconds_budget))
     return {"value": segs / dt / 1e6, "unit": "M ray-bounces/s", "cores": threads, "kind": "oracle",
-            "sample": "urban canyon, lattice rays 0, %d, 2*%d, ... of 1e7 (%d rays, %d ray-bounces, depth 3, "
-                      "coverage on), %.1f s" % (stride, stride, len(r.ray_idx), segs, dt)}
+            "sample": "urban canyon coverage map, lattice rays 0, %d, 2*%d, ... of 1e7 (%d rays, %d ray-bounces, "
+                      "depth 3), %.1f s on %d threads" % (stride, stride, len(r.ray_idx), segs, dt, threads)}
 
 
 def main():
@@ -145,7 +154,9 @@ def main():
                                ctypes.c_void_p(work.data_ptr())))
     wk = work.cpu().numpy().reshape(3, nd)
     assert np.array_equal(wk[0], rb_depth), (wk[0], rb_depth)
-    flops_depth = FLOP_NODE * wk[1] + FLOP_TRI * wk[2] + FLOP_SEGMENT * wk[0]
+    survivors = np.append(wk[0][1:], 0)
+    flops_depth = FLOP_NODE * wk[1] + FLOP_TRI * wk[2] + FLOP_DEPOSIT * wk[0] + FLOP_REFLECT * survivors
+    flops_depth[0] += FLOP_RAYGEN * wk[0][0]
     k_ms = np.asarray(list(kms)) / np.maximum(1, np.asarray(list(launches)))  # per launch, per depth
     per_launch_flops = flops_depth.sum()
     per_step_kernel_ms = float(k_ms.sum())
