@@ -1,0 +1,130 @@
+// Host-side check of the scene builder (paper_2303_11103_amd/csrc/scene.cpp):
+// builds the BVH and faces from a mesh read from a binary file, verifies the
+// structure, and answers closest-hit queries by walking the GPU node layout
+// on the CPU (fp32 boxes, fp64 triangle tests), so that a Python test can
+// compare the answers with the brute-force oracle.
+//
+// input  (binary): int64 nv, nt, nm, nr; float V[nv][3]; int32 F[nt][3];
+//                  int32 mat[nt]; double O[nr][3]; double D[nr][3]
+// output (binary): int32 face_of_input[nt]; int32 hit[nr]; double t[nr]
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "scene.h"
+
+using namespace rt;
+
+static bool inside(const Node& n, int c, const Tri& t) {
+    const float* lo_hi_x = c == 0 ? n.a : n.b;
+    float lx = lo_hi_x[0], hx = lo_hi_x[1], ly = lo_hi_x[2], hy = lo_hi_x[3];
+    float lz = n.c[2 * c], hz = n.c[2 * c + 1];
+    for (int v = 0; v < 3; ++v) {
+        double p[3];
+        for (int i = 0; i < 3; ++i) p[i] = t.v0[i] + (v == 1 ? t.e1[i] : v == 2 ? t.e2[i] : 0.0);
+        if (p[0] < lx || p[0] > hx || p[1] < ly || p[1] > hy || p[2] < lz || p[2] > hz) return false;
+    }
+    return true;
+}
+
+static void check_subtree(const HostScene& s, int32_t ref, const Node& parent, int c, std::vector<int>& seen,
+                          int depth, int& maxd) {
+    if (depth > maxd) maxd = depth;
+    if (ref < 0) {
+        int code = ~ref, first = code >> kLeafShift, cnt = (code & (kMaxLeaf - 1)) + 1;
+        for (int k = first; k < first + cnt; ++k) {
+            if (!inside(parent, c, s.tris[k])) { fprintf(stderr, "triangle outside its box\n"); exit(3); }
+            seen[k]++;
+        }
+        return;
+    }
+    const Node& n = s.nodes[ref];
+    for (int cc = 0; cc < 2; ++cc) check_subtree(s, n.child[cc], n, cc, seen, depth + 1, maxd);
+}
+
+static bool box_hit(const float* lohix, const float* lohiz, const double* o, const double* d, double tmax) {
+    double t0 = 0.0, t1 = tmax;
+    const float lo[3] = {lohix[0], lohix[2], lohiz[0]}, hi[3] = {lohix[1], lohix[3], lohiz[1]};
+    for (int i = 0; i < 3; ++i) {
+        if (d[i] == 0.0) {
+            if (o[i] < lo[i] || o[i] > hi[i]) return false;
+            continue;
+        }
+        double a = (lo[i] - o[i]) / d[i], b = (hi[i] - o[i]) / d[i];
+        if (a > b) std::swap(a, b);
+        t0 = std::max(t0, a);
+        t1 = std::min(t1, b);
+    }
+    return t0 <= t1 * (1 + 1e-12) + 1e-12;
+}
+
+static void closest(const HostScene& s, int32_t ref, const double* o, const double* d, double tmin, int& best,
+                    double& tbest) {
+    if (ref < 0) {
+        int code = ~ref, first = code >> kLeafShift, cnt = (code & (kMaxLeaf - 1)) + 1;
+        for (int k = first; k < first + cnt; ++k) {
+            const Tri& t = s.tris[k];
+            double P[3] = {d[1] * t.e2[2] - d[2] * t.e2[1], d[2] * t.e2[0] - d[0] * t.e2[2], d[0] * t.e2[1] - d[1] * t.e2[0]};
+            double det = t.e1[0] * P[0] + t.e1[1] * P[1] + t.e1[2] * P[2];
+            if (std::fabs(det) < t.thr) continue;
+            double T[3] = {o[0] - t.v0[0], o[1] - t.v0[1], o[2] - t.v0[2]};
+            double u = (T[0] * P[0] + T[1] * P[1] + T[2] * P[2]) / det;
+            double Q[3] = {T[1] * t.e1[2] - T[2] * t.e1[1], T[2] * t.e1[0] - T[0] * t.e1[2], T[0] * t.e1[1] - T[1] * t.e1[0]};
+            double v = (d[0] * Q[0] + d[1] * Q[1] + d[2] * Q[2]) / det;
+            double tt = (t.e2[0] * Q[0] + t.e2[1] * Q[1] + t.e2[2] * Q[2]) / det;
+            if (u >= 0 && v >= 0 && u + v <= 1 && tt > tmin && tt < tbest) { tbest = tt; best = t.orig; }
+        }
+        return;
+    }
+    const Node& n = s.nodes[ref];
+    if (box_hit(n.a, n.c, o, d, tbest)) closest(s, n.child[0], o, d, tmin, best, tbest);
+    if (box_hit(n.b, n.c + 2, o, d, tbest)) closest(s, n.child[1], o, d, tmin, best, tbest);
+}
+
+int main(int argc, char** argv) {
+    if (argc != 3) return 2;
+    FILE* f = fopen(argv[1], "rb");
+    if (!f) return 2;
+    int64_t hdr[4];
+    if (fread(hdr, 8, 4, f) != 4) return 2;
+    int64_t nv = hdr[0], nt = hdr[1], nm = hdr[2], nr = hdr[3];
+    std::vector<float> V(3 * nv);
+    std::vector<int32_t> F(3 * nt), M(nt);
+    std::vector<double> O(3 * nr), D(3 * nr);
+    if (fread(V.data(), 4, V.size(), f) != V.size() || fread(F.data(), 4, F.size(), f) != F.size() ||
+        fread(M.data(), 4, M.size(), f) != M.size() || fread(O.data(), 8, O.size(), f) != O.size() ||
+        fread(D.data(), 8, D.size(), f) != D.size())
+        return 2;
+    fclose(f);
+    HostScene s;
+    std::string err;
+    if (build_scene(V.data(), nv, F.data(), nt, M.data(), (int32_t)nm, s, err) != 0) {
+        fprintf(stderr, "build failed: %s\n", err.c_str());
+        return 4;
+    }
+    std::vector<int> seen(nt, 0);
+    int maxd = 0;
+    const Node& root = s.nodes[0];
+    bool root_leaf = root.child[0] == root.child[1] && root.child[0] < 0;
+    for (int c = 0; c < (root_leaf ? 1 : 2); ++c) check_subtree(s, root.child[c], root, c, seen, 1, maxd);
+    for (int64_t k = 0; k < nt; ++k)
+        if (seen[k] != 1) { fprintf(stderr, "triangle %ld referenced %d times\n", (long)k, seen[k]); return 3; }
+    if (maxd > kMaxDepth + 1) { fprintf(stderr, "depth %d\n", maxd); return 3; }
+    std::vector<int32_t> hit(nr);
+    std::vector<double> th(nr);
+    for (int64_t r = 0; r < nr; ++r) {
+        int best = -1;
+        double tb = INFINITY;
+        closest(s, 0, &O[3 * r], &D[3 * r], 1e-4, best, tb);
+        hit[r] = best;
+        th[r] = tb;
+    }
+    FILE* g = fopen(argv[2], "wb");
+    fwrite(s.face_of_input.data(), 4, nt, g);
+    fwrite(hit.data(), 4, nr, g);
+    fwrite(th.data(), 8, nr, g);
+    fclose(g);
+    printf("nodes %zu depth %d faces %d\n", s.nodes.size(), s.depth, s.num_faces);
+    return 0;
+}

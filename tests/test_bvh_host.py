@@ -1,0 +1,61 @@
+"""Host build of the scene preparation code (C++, compiled with g++ here):
+BVH structure invariants, face grouping equal to the oracle's, and closest
+hits through the BVH equal to the brute-force oracle."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import geom, native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2303_11103_amd", "csrc")
+WORK = os.path.join(ROOT, "_work")
+
+
+@pytest.fixture(scope="module")
+def checker():
+    os.makedirs(WORK, exist_ok=True)
+    exe = os.path.join(WORK, "bvh_check")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", CSRC, os.path.join(CSRC, "scene.cpp"),
+                    os.path.join(ROOT, "tests", "host", "bvh_check.cpp"), "-o", exe], check=True)
+    return exe
+
+
+def _run(exe, s, O, D):
+    inp = os.path.join(WORK, "bvh_in.bin")
+    out = os.path.join(WORK, "bvh_out.bin")
+    with open(inp, "wb") as f:
+        np.asarray([len(s.V), s.nt, len(s.materials), len(O)], dtype=np.int64).tofile(f)
+        np.ascontiguousarray(s.V, dtype=np.float32).tofile(f)
+        np.ascontiguousarray(s.F, dtype=np.int32).tofile(f)
+        np.ascontiguousarray(s.tri_mat, dtype=np.int32).tofile(f)
+        np.ascontiguousarray(O, dtype=np.float64).tofile(f)
+        np.ascontiguousarray(D, dtype=np.float64).tofile(f)
+    r = subprocess.run([exe, inp, out], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    raw = open(out, "rb").read()
+    nt, nr = s.nt, len(O)
+    faces = np.frombuffer(raw[:4 * nt], dtype=np.int32)
+    hit = np.frombuffer(raw[4 * nt:4 * nt + 4 * nr], dtype=np.int32)
+    t = np.frombuffer(raw[4 * nt + 4 * nr:], dtype=np.float64)
+    return faces, hit, t
+
+
+@pytest.mark.parametrize("name", ["toy", "urban", "city"])
+def test_bvh_closest_hits_and_faces_match_oracle(checker, name):
+    s = {"toy": sg.make_toy, "urban": lambda: sg.make_urban(0), "city": lambda: sg.make_city(0, blocks=10)}[name]()
+    lo, hi = (-90, 90) if name == "toy" else (-230, 230) if name == "urban" else (-200, 200)
+    O, D = sg.random_rays(3000, seed=3, lo=lo, hi=hi, zlo=0.5, zhi=80)
+    faces, hit, t = _run(checker, s, O, D)
+    ref_faces, _ = geom.face_ids(s.V, s.F, s.tri_mat)
+    assert np.array_equal(faces, ref_faces)
+    g = geom.Geometry(s)
+    tri, tt, margin = native.closest_hit(O, D, np.full(len(O), -1), 1e-4, g.V, g.F, g.face, want_margin=True)
+    ok = margin >= 1e-6
+    assert ok.mean() > 0.9  # origins inside buildings see floor/ground ties (margin 0)
+    assert np.array_equal(hit[ok], tri[ok])
+    h = ok & (tri >= 0)
+    assert np.max(np.abs(t[h] - tt[h]) / (1 + tt[h])) < 1e-12

@@ -1,0 +1,69 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol that
+include/rt.h declares, mirrors its structs, and rejects bad arguments before
+touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rt.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:rt_status|const char\*)\s+(rt_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2303_11103_amd import _lib
+    names = _declared()
+    assert len(names) >= 15
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    # the binding declares exactly the header's functions
+    assert sorted(_lib.SIGNATURES) == names
+
+
+def test_struct_layouts_match_header():
+    from paper_2303_11103_amd import _lib
+    # sizes implied by the header (natural alignment, x86-64)
+    assert ctypes.sizeof(_lib.rt_material) == 8
+    assert ctypes.sizeof(_lib.rt_device) == 32
+    assert ctypes.sizeof(_lib.rt_trace_params) == 48
+    assert ctypes.sizeof(_lib.rt_grid) == 40
+    assert ctypes.sizeof(_lib.rt_scene_info_t) == 40
+    src = (
+        "#include <stddef.h>\n#include <stdio.h>\n#include \"rt.h\"\n"
+        "int main(){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(rt_material), sizeof(rt_device),"
+        " sizeof(rt_trace_params), sizeof(rt_grid), sizeof(rt_scene_info_t),"
+        " offsetof(rt_trace_params, num_rays), offsetof(rt_grid, nx)); return 0;}\n")
+    tmp = os.path.join(ROOT, "_work")
+    os.makedirs(tmp, exist_ok=True)
+    c = os.path.join(tmp, "layout_check.c")
+    exe = os.path.join(tmp, "layout_check")
+    open(c, "w").write(src)
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+    vals = list(map(int, subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()))
+    assert vals == [8, 32, 48, 40, 40, _lib.rt_trace_params.num_rays.offset, _lib.rt_grid.nx.offset]
+
+
+def test_null_and_invalid_arguments_fail_on_host():
+    from paper_2303_11103_amd import _lib
+    lib = _lib.lib
+    assert lib.rt_create(None, 0) == _lib.RT_ERR_ARG
+    assert b"NULL" in lib.rt_last_error()
+    p = _lib.rt_trace_params(3.5e9, 3, 16, 1000, 1e-4, 0, 1)
+    assert lib.rt_coverage_map(None, None, ctypes.byref(p), None, None, None, None, None, None, None) == \
+        _lib.RT_ERR_ARG
+    assert lib.rt_set_stream(None, None) == _lib.RT_ERR_ARG
+    assert lib.rt_scene_info(None, None) == _lib.RT_ERR_ARG
+    assert lib.rt_profile_enable(None, 1) == _lib.RT_ERR_ARG
+    # destroy functions accept NULL
+    assert lib.rt_destroy(None) == _lib.RT_OK
+    assert lib.rt_scene_destroy(None) == _lib.RT_OK
