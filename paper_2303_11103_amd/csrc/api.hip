@@ -181,7 +181,7 @@ void band_perm(int64_t count, int64_t stride, int64_t& F, int64_t& G) {
     G = a;
 }
 
-int grid_for(const rt_ctx* c) { return c->num_cu * 8; }
+int grid_for(const rt_ctx* c) { return c->num_cu * 4; }
 
 // Runs the shoot-and-bounce launches for all rays of one transmitter.
 rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx, const rt_device* rx_ant,
@@ -339,6 +339,7 @@ rt_status rt_scene_create(rt_ctx* c, const float* V, int64_t nv, const int32_t* 
     s->dev.face_tris = (const int32_t*)s->face_tris.p;
     s->dev.num_faces = h.num_faces;
     s->dev.nt = (int32_t)nt;
+    s->dev.num_nodes = (int32_t)h.nodes.size();
     *out = s;
     return RT_OK;
 }

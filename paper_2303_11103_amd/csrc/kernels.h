@@ -30,6 +30,8 @@ struct DevScene {
     const int32_t* face_tris;
     int32_t num_faces;
     int32_t nt;
+    int32_t num_nodes;
+    int32_t pad;
 };
 
 struct SbrArgs {

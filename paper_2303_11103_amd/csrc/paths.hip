@@ -89,6 +89,8 @@ __device__ bool in_face(const DevScene& sc, int f, d3 X) {
 
 __global__ __launch_bounds__(kBlock) void image_paths_kernel(PathArgs a, MatTable mats, int64_t max_items) {
     __shared__ int32_t stack[kStack][kBlock];
+    __shared__ Node lds_nodes[kLdsNodes];
+    const int n_lds = stage_nodes(a.sc, lds_nodes);
     const int64_t ncand = (int64_t)(*a.ncand);
     const int64_t per_rx = ncand + 1;
     const int64_t total = per_rx * a.nrx;
@@ -144,7 +146,8 @@ __global__ __launch_bounds__(kBlock) void image_paths_kernel(PathArgs a, MatTabl
             const int ea = k == 0 ? -1 : fc[k - 1];
             const int eb = k == K ? -1 : fc[k];
             double tb = 1.0;
-            if (traverse<true>(a.sc, X[k], sub(X[k + 1], X[k]), ea, eb, kOccEps, tb, stack) >= 0) valid = false;
+            if (traverse<true>(a.sc, lds_nodes, n_lds, X[k], sub(X[k + 1], X[k]), ea, eb, kOccEps, tb, stack) >= 0)
+                valid = false;
         }
         if (!valid) continue;
         // ---- coefficients

@@ -298,47 +298,51 @@ int build_scene(const float* V, int64_t nv, const int32_t* F, int64_t nt, const 
         new_of_old[prims[i].tri] = (int32_t)i;
     }
 
-    // flatten: every inner build node becomes a GPU node holding its two
-    // children's bounds; a root leaf gets an inner wrapper.
-    auto child_ref = [&](int32_t b, auto& self) -> int32_t {
-        const BuildNode& n = bn[b];
-        if (n.left < 0) return make_leaf(n.first, n.count);
-        int32_t id = (int32_t)out.nodes.size();
-        out.nodes.emplace_back();
-        int32_t l = self(n.left, self);
-        int32_t r = self(n.right, self);
-        Node& g = out.nodes[id];
-        const Box& L = bn[n.left].box;
-        const Box& R = bn[n.right].box;
-        double p = out.pad;
-        g.a[0] = round_down(L.lo[0] - p); g.a[1] = round_up(L.hi[0] + p);
-        g.a[2] = round_down(L.lo[1] - p); g.a[3] = round_up(L.hi[1] + p);
-        g.b[0] = round_down(R.lo[0] - p); g.b[1] = round_up(R.hi[0] + p);
-        g.b[2] = round_down(R.lo[1] - p); g.b[3] = round_up(R.hi[1] + p);
-        g.c[0] = round_down(L.lo[2] - p); g.c[1] = round_up(L.hi[2] + p);
-        g.c[2] = round_down(R.lo[2] - p); g.c[3] = round_up(R.hi[2] + p);
-        g.child[0] = l;
-        g.child[1] = r;
-        g.pad[0] = g.pad[1] = 0;
-        return id;
+    // flatten in breadth-first order (the first nodes are the top levels, which
+    // the kernels stage in LDS): every inner build node becomes a GPU node
+    // holding its two children's bounds; a root leaf gets an inner wrapper.
+    const double p = out.pad;
+    auto set_box = [&](float* xy, float* z, const Box& B) {
+        xy[0] = round_down(B.lo[0] - p); xy[1] = round_up(B.hi[0] + p);
+        xy[2] = round_down(B.lo[1] - p); xy[3] = round_up(B.hi[1] + p);
+        z[0] = round_down(B.lo[2] - p);  z[1] = round_up(B.hi[2] + p);
     };
     if (bn[0].left < 0) {
         Node g;
-        const Box& L = bn[0].box;
-        double p = out.pad;
-        g.a[0] = round_down(L.lo[0] - p); g.a[1] = round_up(L.hi[0] + p);
-        g.a[2] = round_down(L.lo[1] - p); g.a[3] = round_up(L.hi[1] + p);
-        g.c[0] = round_down(L.lo[2] - p); g.c[1] = round_up(L.hi[2] + p);
+        set_box(g.a, g.c, bn[0].box);
         // both children are the same leaf (the second visit finds nothing new)
-        for (int i = 0; i < 4; ++i) g.b[i] = g.a[i];
-        g.c[2] = g.c[0];
-        g.c[3] = g.c[1];
+        set_box(g.b, g.c + 2, bn[0].box);
         g.child[0] = g.child[1] = make_leaf(bn[0].first, bn[0].count);
         g.pad[0] = g.pad[1] = 0;
         out.nodes.push_back(g);
         out.depth = 1;
     } else {
-        child_ref(0, child_ref);
+        std::vector<int32_t> order;      // build-node ids of inner nodes in BFS order
+        std::vector<int32_t> gpu_of(bn.size(), -1);
+        order.push_back(0);
+        gpu_of[0] = 0;
+        for (size_t h = 0; h < order.size(); ++h) {
+            const BuildNode& n = bn[order[h]];
+            for (int32_t c : {n.left, n.right}) {
+                if (bn[c].left >= 0) {
+                    gpu_of[c] = (int32_t)order.size();
+                    order.push_back(c);
+                }
+            }
+        }
+        out.nodes.resize(order.size());
+        for (size_t h = 0; h < order.size(); ++h) {
+            const BuildNode& n = bn[order[h]];
+            Node& g = out.nodes[h];
+            set_box(g.a, g.c, bn[n.left].box);
+            set_box(g.b, g.c + 2, bn[n.right].box);
+            int32_t kids[2] = {n.left, n.right};
+            for (int i = 0; i < 2; ++i) {
+                const BuildNode& ch = bn[kids[i]];
+                g.child[i] = ch.left < 0 ? make_leaf(ch.first, ch.count) : gpu_of[kids[i]];
+            }
+            g.pad[0] = g.pad[1] = 0;
+        }
     }
 
     // ---- faces with their triangles (reordered indices)

@@ -71,30 +71,67 @@ __device__ int32_t cand_insert(uint64_t* table, uint64_t mask, int32_t parent, i
     return -2;
 }
 
+// Ray state in registers; loaded from / stored to the 96-byte queue record
+// with 16-byte vector accesses.
+struct Ray {
+    d3 o, d;
+    float E[6];
+    int32_t excl, prefix, ray;
+};
+
+__device__ __forceinline__ void load_ray(const RayState* __restrict__ p, Ray& r) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+    const double2 a0 = q[0], a1 = q[1], a2 = q[2];
+    const float4 f0 = reinterpret_cast<const float4*>(p)[3];
+    const int4 f1 = reinterpret_cast<const int4*>(p)[4];
+    const int4 f2 = reinterpret_cast<const int4*>(p)[5];
+    r.o = d3{a0.x, a0.y, a1.x};
+    r.d = d3{a1.y, a2.x, a2.y};
+    r.E[0] = f0.x;
+    r.E[1] = f0.y;
+    r.E[2] = f0.z;
+    r.E[3] = f0.w;
+    r.E[4] = __int_as_float(f1.x);
+    r.E[5] = __int_as_float(f1.y);
+    r.excl = f1.z;
+    r.prefix = f1.w;
+    r.ray = f2.x;
+}
+
+__device__ __forceinline__ void store_ray(RayState* __restrict__ p, const Ray& r) {
+    double2* q = reinterpret_cast<double2*>(p);
+    q[0] = double2{r.o.x, r.o.y};
+    q[1] = double2{r.o.z, r.d.x};
+    q[2] = double2{r.d.y, r.d.z};
+    reinterpret_cast<float4*>(p)[3] = float4{r.E[0], r.E[1], r.E[2], r.E[3]};
+    reinterpret_cast<int4*>(p)[4] = int4{__float_as_int(r.E[4]), __float_as_int(r.E[5]), r.excl, r.prefix};
+    reinterpret_cast<int4*>(p)[5] = int4{r.ray, 0, 0, 0};
+}
+
 template <int MODE, bool FIRST>
-__global__ __launch_bounds__(kBlock) void sbr_bounce(SbrArgs a, MatTable mats) {
-    __shared__ int32_t stack[kStack][kBlock];
+__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void sbr_bounce(SbrArgs a,
+                                                                                                    MatTable mats) {
+    __shared__ int32_t stack[kStack][kTraceBlock];
+    __shared__ Node lds_nodes[kLdsNodes];
+    const int n_lds = stage_nodes(a.sc, lds_nodes);
     const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+    const int64_t wave = ((int64_t)blockIdx.x * kTraceBlock + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * kTraceBlock) >> 6;
     const int64_t count = FIRST ? a.chunk : (int64_t)(*a.in_count);
-    if (a.stats && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd((unsigned long long*)&a.stats[a.depth], (unsigned long long)count);
+    if (a.stats && blockIdx.x == 0 && threadIdx.x == 0)
+        atomicAdd((unsigned long long*)&a.stats[a.depth], (unsigned long long)count);
     for (int64_t base = wave * 64; base < count; base += nwaves * 64) {
         const int64_t item = base + lane;
         const bool active = item < count;
-        RayState st;
+        Ray st;
+        bool alive = false;
         if (active) {
             if (FIRST) {
                 const int64_t j = a.pos0 + item;
                 const int64_t ri = ray_index(a, j);
-                const d3 d = fib_dir(ri, a.num_rays);
-                st.o[0] = a.tx[0];
-                st.o[1] = a.tx[1];
-                st.o[2] = a.tx[2];
-                st.d[0] = d.x;
-                st.d[1] = d.y;
-                st.d[2] = d.z;
-                const f3 F = antenna_field(a.tx_ant, f3{(float)d.x, (float)d.y, (float)d.z});
+                st.d = fib_dir(ri, a.num_rays);
+                st.o = d3{a.tx[0], a.tx[1], a.tx[2]};
+                const f3 F = antenna_field(a.tx_ant, f3{(float)st.d.x, (float)st.d.y, (float)st.d.z});
                 st.E[0] = F.x;
                 st.E[1] = 0.0f;
                 st.E[2] = F.y;
@@ -104,19 +141,15 @@ __global__ __launch_bounds__(kBlock) void sbr_bounce(SbrArgs a, MatTable mats) {
                 st.excl = -1;
                 st.prefix = -1;
                 st.ray = (int32_t)((ri - a.begin) / a.stride);  // lattice position (unpermuted)
-                st.pad = 0;
             } else {
-                st = a.in[item];
+                load_ray(a.in + item, st);
             }
-        }
-        bool alive = false;
-        if (active) {
-            const d3 o{st.o[0], st.o[1], st.o[2]};
-            const d3 d{st.d[0], st.d[1], st.d[2]};
+            const d3 o = st.o;
+            const d3 d = st.d;
             double tbest = __builtin_inf();
             TravStats ts;
-            const int best =
-                traverse<false, (MODE & kModeStats) != 0>(a.sc, o, d, st.excl, st.excl, a.tmin, tbest, stack, &ts);
+            const int best = traverse<false, (MODE & kModeStats) != 0, kTraceBlock>(
+                a.sc, lds_nodes, n_lds, o, d, st.excl, st.excl, a.tmin, tbest, stack, &ts);
             if (MODE & kModeStats) {
                 const int nd = a.max_depth + 1;
                 atomicAdd((unsigned long long*)&a.work[a.depth], 1ull);
@@ -174,12 +207,8 @@ __global__ __launch_bounds__(kBlock) void sbr_bounce(SbrArgs a, MatTable mats) {
                 st.E[3] = sp.im * fep.y + sl.im * felr.y;
                 st.E[4] = sp.re * fep.z + sl.re * felr.z;
                 st.E[5] = sp.im * fep.z + sl.im * felr.z;
-                st.o[0] = p.x;
-                st.o[1] = p.y;
-                st.o[2] = p.z;
-                st.d[0] = dr.x;
-                st.d[1] = dr.y;
-                st.d[2] = dr.z;
+                st.o = p;
+                st.d = dr;
                 st.excl = sh.face;
                 if (MODE & kModeCandidates) {
                     if (st.prefix != -2) st.prefix = cand_insert(a.table, a.table_mask, st.prefix, sh.face, a.overflow);
@@ -192,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void sbr_bounce(SbrArgs a, MatTable mats) {
             uint32_t b = 0;
             if (lane == 0) b = atomicAdd(a.out_count, (uint32_t)__popcll(m));
             b = __shfl(b, 0);
-            if (alive) a.out[b + __popcll(m & ((1ull << lane) - 1ull))] = st;
+            if (alive) store_ray(a.out + b + __popcll(m & ((1ull << lane) - 1ull)), st);
         }
     }
 }
@@ -216,9 +245,9 @@ __global__ void finalize_db_kernel(const float* __restrict__ g, float* __restric
 template <int MODE>
 hipError_t launch_mode(const SbrArgs& a, const MatTable& mats, int grid, hipStream_t s) {
     if (a.depth == 0)
-        hipLaunchKernelGGL((sbr_bounce<MODE, true>), dim3(grid), dim3(kBlock), 0, s, a, mats);
+        hipLaunchKernelGGL((sbr_bounce<MODE, true>), dim3(grid), dim3(kTraceBlock), 0, s, a, mats);
     else
-        hipLaunchKernelGGL((sbr_bounce<MODE, false>), dim3(grid), dim3(kBlock), 0, s, a, mats);
+        hipLaunchKernelGGL((sbr_bounce<MODE, false>), dim3(grid), dim3(kTraceBlock), 0, s, a, mats);
     return hipGetLastError();
 }
 

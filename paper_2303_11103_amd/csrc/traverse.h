@@ -7,8 +7,10 @@
 
 namespace rt {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 256;       // block size of kernels that do not stage nodes
+constexpr int kTraceBlock = 512;  // block size of the shoot-and-bounce kernels
 constexpr int kStack = kMaxDepth + 2;
+constexpr int kLdsNodes = 256;    // top BVH nodes (breadth-first order) staged in LDS
 constexpr float kDn = 1.0f - 1e-6f;  // conservative slab interval factors
 constexpr float kUp = 1.0f + 1e-6f;
 
@@ -68,9 +70,22 @@ struct TravStats {
     uint32_t tris = 0;
 };
 
-template <bool ANY, bool STATS = false>
-__device__ __forceinline__ int traverse(const DevScene& sc, d3 o, d3 d, int excl0, int excl1, double tmin,
-                                        double& tbest, int32_t (*stack)[kBlock], TravStats* ts = nullptr) {
+// Copies the first min(num_nodes, kLdsNodes) nodes into LDS (whole block).
+__device__ __forceinline__ int stage_nodes(const DevScene& sc, Node* lds) {
+    const int n = sc.num_nodes < kLdsNodes ? sc.num_nodes : kLdsNodes;
+    const float4* src = reinterpret_cast<const float4*>(sc.nodes);
+    float4* dst = reinterpret_cast<float4*>(lds);
+    for (int i = threadIdx.x; i < 4 * n; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+    return n;
+}
+
+// Nodes with index < n_lds are read from the LDS copy, the others from
+// global memory (L2-resident for the scenes here).
+template <bool ANY, bool STATS = false, int BS = kBlock>
+__device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_nodes, int n_lds, d3 o, d3 d, int excl0,
+                                        int excl1, double tmin, double& tbest, int32_t (*stack)[BS],
+                                        TravStats* ts = nullptr) {
     const int tid = threadIdx.x;
     const float ox = (float)o.x, oy = (float)o.y, oz = (float)o.z;
     const float ix = safe_inv(d.x), iy = safe_inv(d.y), iz = safe_inv(d.z);
@@ -81,9 +96,21 @@ __device__ __forceinline__ int traverse(const DevScene& sc, d3 o, d3 d, int excl
     while (true) {
         if (node >= 0) {
             if (STATS) ts->nodes++;
-            const float4* np = reinterpret_cast<const float4*>(sc.nodes + node);
-            const float4 A = np[0], B = np[1], C = np[2];
-            const int4 ch = reinterpret_cast<const int4*>(np)[3];
+            float4 A, B, C;
+            int4 ch;
+            if (node < n_lds) {
+                const float4* np = reinterpret_cast<const float4*>(lds_nodes + node);
+                A = np[0];
+                B = np[1];
+                C = np[2];
+                ch = reinterpret_cast<const int4*>(np)[3];
+            } else {
+                const float4* np = reinterpret_cast<const float4*>(sc.nodes + node);
+                A = np[0];
+                B = np[1];
+                C = np[2];
+                ch = reinterpret_cast<const int4*>(np)[3];
+            }
             float a0 = fmaf(A.x, ix, -oix), a1 = fmaf(A.y, ix, -oix);
             float b0 = fmaf(A.z, iy, -oiy), b1 = fmaf(A.w, iy, -oiy);
             float c0 = fmaf(C.x, iz, -oiz), c1 = fmaf(C.y, iz, -oiz);
