@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/rt.h"
+#include "rt.h"
 #include "kernels.h"
 #include "scene.h"
 
