@@ -227,6 +227,58 @@ rt_status rt_paths_power_grad(rt_ctx* ctx, rt_scene* scene, const rt_trace_param
                               const rt_device* rx, int32_t nrx, int32_t P, const int32_t* depth,
                               const int32_t* faces, const double* dL_dP, double* grad);
 
+/* ------------------------------------------------------------------ surrogate */
+
+/* Learned coverage-map surrogate (the paper motivates neural propagation
+ * models, Sec. I, and closes Sec. III-A with learning as a calibration
+ * tool; it specifies no network).  Function: inputs v = (tx x, y, z, cell
+ * x, y), normalised as (v - in_center) / in_half; Fourier features
+ * [sin 2 pi B v, cos 2 pi B v] with B (64 x 5) drawn N(0, ff_scale^2);
+ * 4 hidden layers of 256 with the tanh-form GELU; linear head giving the
+ * path gain in dB.  Parameters (fp32, rt_mlp_param_count() of them):
+ * W1[256][128] b1[256] W2[256][256] b2 W3 b3 W4 b4 w5[256] b5[1].
+ * Matrix products run on bf16 MFMA with fp32 accumulation; training uses
+ * Adam (beta 0.9/0.999, eps 1e-8) on fp32 master weights and the masked
+ * mean squared error sum m (y - t)^2 / sum m. */
+typedef struct rt_mlp rt_mlp;
+typedef struct {
+    int32_t batch;        /* rows per call: multiple of 1024 (scratch is sized for it) */
+    float ff_scale;       /* standard deviation of the Fourier matrix entries */
+    uint64_t seed;        /* initialisation seed */
+    float in_center[5];
+    float in_half[5];
+} rt_mlp_config;
+
+rt_status rt_mlp_param_count(int64_t* n);
+/* Allocate and initialise (weights U(-1/sqrt(fan_in), 1/sqrt(fan_in)),
+ * biases 0). */
+rt_status rt_mlp_create(rt_ctx* ctx, const rt_mlp_config* cfg, rt_mlp** out);
+rt_status rt_mlp_destroy(rt_mlp* mlp);
+/* Copy parameters [P] and Fourier matrix [64][5] (dev) out of / into the
+ * handle; set also clears the Adam moments. */
+rt_status rt_mlp_get_params(rt_mlp* mlp, float* params, float* ff);
+rt_status rt_mlp_set_params(rt_mlp* mlp, const float* params, const float* ff);
+/* Predictions y [n] (dev) for inputs v [n][5] (dev); n a multiple of 128,
+ * at most batch. */
+rt_status rt_mlp_forward(rt_mlp* mlp, const float* v, int64_t n, float* y);
+/* Gradient of the masked MSE (targets t [n], mask m [n] in {0, 1}, dev):
+ * grad [P] (dev); loss (dev, nullable) [1]. */
+rt_status rt_mlp_grad(rt_mlp* mlp, const float* v, const float* t, const float* m, int64_t n, float* grad,
+                      float* loss);
+/* One Adam step with learning rate lr on the batch; loss (dev, nullable). */
+rt_status rt_mlp_train_step(rt_mlp* mlp, const float* v, const float* t, const float* m, int64_t n, float lr,
+                            float* loss);
+/* Draw n training rows from a stack of T coverage maps (dev): maps [T][ny][nx]
+ * in dB, mask [T][ny][nx] (1 = usable cell), tx [T][3]; rows are taken by a
+ * counter-based hash of (seed, step, row) among masked-in cells (up to 8
+ * draws, else the row gets m = 0).  Writes v [n][5], t [n], m [n] (dev). */
+rt_status rt_mlp_sample_batch(rt_mlp* mlp, const float* maps, const uint8_t* mask, const float* tx, int32_t T,
+                              const rt_grid* grid, uint64_t seed, uint64_t step, float* v, float* t, float* m,
+                              int64_t n);
+/* Predicted maps [T][ny][nx] (dev, dB) for transmitters tx [T][3] (dev) on the
+ * grid's cell centres. */
+rt_status rt_mlp_predict_maps(rt_mlp* mlp, const float* tx, int32_t T, const rt_grid* grid, float* maps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,118 @@
+"""Float64 Fourier-feature MLP with a hand-written backward pass.
+
+Test infrastructure: see the package docstring.
+
+The paper motivates machine learning for faster propagation prediction
+(Sec. I, and the remarks closing Sec. III-A) but specifies no network.  The
+surrogate here is fixed as follows (the GPU kernels implement the same
+function in bf16/fp32):
+
+* input v in R^5: transmitter (x, y, z) and cell centre (x, y), each mapped
+  affinely to about [-1, 1] by (p - centre) / half_extent;
+* Fourier features gamma(v) = [sin(2 pi B v), cos(2 pi B v)], B in R^{64x5};
+* 4 hidden layers of width 256, h_l = gelu(W_l h_{l-1} + b_l), with the tanh
+  form gelu(x) = x / 2 (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3)));
+* linear head y = w_5 . h_4 + b_5 (path gain in dB);
+* loss = sum_i m_i (y_i - t_i)^2 / sum_i m_i (mask m_i in {0, 1}).
+
+Parameter vector layout (float32 on the GPU, float64 here):
+W1[256][128], b1[256], W2[256][256], b2, W3, b3, W4, b4, w5[256], b5[1].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+N_IN = 5
+N_FREQ = 64
+HIDDEN = 256
+LAYERS = 4
+C_GELU = np.sqrt(2.0 / np.pi)
+
+
+def layer_shapes():
+    shapes = []
+    fan_in = 2 * N_FREQ
+    for _ in range(LAYERS):
+        shapes.append(((HIDDEN, fan_in), (HIDDEN,)))
+        fan_in = HIDDEN
+    shapes.append(((1, HIDDEN), (1,)))
+    return shapes
+
+
+def param_count():
+    return sum(int(np.prod(w)) + int(np.prod(b)) for w, b in layer_shapes())
+
+
+def unpack(theta):
+    theta = np.asarray(theta, dtype=np.float64)
+    out, k = [], 0
+    for w, b in layer_shapes():
+        nw, nb = int(np.prod(w)), int(np.prod(b))
+        out.append((theta[k:k + nw].reshape(w), theta[k + nw:k + nw + nb]))
+        k += nw + nb
+    assert k == theta.size
+    return out
+
+
+def gelu(x):
+    return 0.5 * x * (1.0 + np.tanh(C_GELU * (x + 0.044715 * x ** 3)))
+
+
+def gelu_grad(x):
+    u = C_GELU * (x + 0.044715 * x ** 3)
+    t = np.tanh(u)
+    du = C_GELU * (1.0 + 3 * 0.044715 * x ** 2)
+    return 0.5 * (1.0 + t) + 0.5 * x * (1.0 - t * t) * du
+
+
+def features(v, Bf):
+    proj = 2.0 * np.pi * (np.asarray(v, dtype=np.float64) @ np.asarray(Bf, dtype=np.float64).T)
+    return np.concatenate([np.sin(proj), np.cos(proj)], axis=1)
+
+
+def forward(theta, v, Bf, feats=None):
+    """Prediction and the cache for ``backward``."""
+    layers = unpack(theta)
+    h = features(v, Bf) if feats is None else np.asarray(feats, dtype=np.float64)
+    cache = [h]
+    for W, b in layers[:-1]:
+        z = h @ W.T + b
+        h = gelu(z)
+        cache.append((z, h))
+    w5, b5 = layers[-1]
+    y = h @ w5[0] + b5[0]
+    return y, cache
+
+
+def loss(y, t, m):
+    m = np.asarray(m, dtype=np.float64)
+    return float(np.sum(m * (y - t) ** 2) / np.sum(m))
+
+
+def backward(theta, cache, y, t, m):
+    """d loss / d theta (float64, same layout as theta)."""
+    layers = unpack(theta)
+    m = np.asarray(m, dtype=np.float64)
+    g = 2.0 * m * (y - t) / np.sum(m)                   # d loss / d y
+    grads = []
+    h4 = cache[-1][1]
+    w5 = layers[-1][0]
+    grads.append((g @ h4, np.array([g.sum()])))          # w5, b5
+    dh = np.outer(g, w5[0])
+    for li in range(LAYERS - 1, -1, -1):
+        z, _ = cache[li + 1]
+        h_prev = cache[li] if li == 0 else cache[li][1]
+        dz = dh * gelu_grad(z)
+        W = layers[li][0]
+        grads.append((dz.T @ h_prev, dz.sum(axis=0)))
+        dh = dz @ W
+    grads = grads[::-1]
+    flat = []
+    for (gw, gb) in grads:
+        flat.append(np.asarray(gw).reshape(-1))
+        flat.append(np.asarray(gb).reshape(-1))
+    return np.concatenate(flat)
+
+
+def normalize(points, centre, half):
+    return (np.asarray(points, dtype=np.float64) - np.asarray(centre)) / np.asarray(half)

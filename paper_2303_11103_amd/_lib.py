@@ -43,6 +43,11 @@ class rt_grid(ctypes.Structure):
                 ("nx", ctypes.c_int32), ("ny", ctypes.c_int32)]
 
 
+class rt_mlp_config(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("ff_scale", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("in_center", ctypes.c_float * 5), ("in_half", ctypes.c_float * 5)]
+
+
 class rt_scene_info_t(ctypes.Structure):
     _fields_ = [("num_triangles", ctypes.c_int64), ("num_faces", ctypes.c_int32), ("num_materials", ctypes.c_int32),
                 ("bvh_nodes", ctypes.c_int64), ("bvh_depth", ctypes.c_int32), ("reserved", ctypes.c_int32),
@@ -77,6 +82,16 @@ SIGNATURES = {
     "rt_last_candidate_count": [P, ctypes.POINTER(I64)],
     "rt_paths_power_grad": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), P, I32, I32, P, P,
                             P, P],
+    "rt_mlp_param_count": [ctypes.POINTER(I64)],
+    "rt_mlp_create": [P, ctypes.POINTER(rt_mlp_config), ctypes.POINTER(P)],
+    "rt_mlp_destroy": [P],
+    "rt_mlp_get_params": [P, P, P],
+    "rt_mlp_set_params": [P, P, P],
+    "rt_mlp_forward": [P, P, I64, P],
+    "rt_mlp_grad": [P, P, P, P, I64, P, P],
+    "rt_mlp_train_step": [P, P, P, P, I64, ctypes.c_float, P],
+    "rt_mlp_sample_batch": [P, P, P, P, I32, ctypes.POINTER(rt_grid), ctypes.c_uint64, ctypes.c_uint64, P, P, P, I64],
+    "rt_mlp_predict_maps": [P, P, I32, ctypes.POINTER(rt_grid), P],
 }
 _RESTYPE = {"rt_last_error": ctypes.c_char_p}
 

@@ -260,6 +260,11 @@ rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_dev
 
 }  // namespace
 
+// accessors used by the surrogate's C ABI (mlp_api.hip)
+rt_status rt_internal_fail(rt_status code, const char* msg) { return fail(code, msg); }
+hipStream_t rt_internal_stream(rt_ctx* c) { return c->stream; }
+int rt_internal_device(rt_ctx* c) { return c->device; }
+
 extern "C" {
 
 const char* rt_last_error(void) { return g_err.c_str(); }

@@ -1,0 +1,335 @@
+// C ABI of the MLP surrogate (declared in include/rt.h): handle with fp32
+// master weights, Adam state, bf16 weight copies and per-batch scratch; the
+// launch sequences of forward, gradient, training step, batch sampling and
+// map prediction.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "rt.h"
+
+rt_status rt_internal_fail(rt_status code, const char* msg);
+hipStream_t rt_internal_stream(rt_ctx* c);
+int rt_internal_device(rt_ctx* c);
+
+namespace {
+
+#define MLP_HIP(call)                                                                                 \
+    do {                                                                                              \
+        hipError_t e_ = (call);                                                                       \
+        if (e_ != hipSuccess)                                                                         \
+            return rt_internal_fail(e_ == hipErrorOutOfMemory ? RT_ERR_OOM : RT_ERR_DEVICE,           \
+                                    (std::string(#call) + ": " + hipGetErrorString(e_)).c_str());     \
+    } while (0)
+
+constexpr int kHidden = 256;
+constexpr int kSplits = 64;
+
+rt::MlpLayout make_layout() {
+    rt::MlpLayout L{};
+    int64_t off = 0, bf = 0;
+    const int fan[5] = {2 * rt::kFreq, kHidden, kHidden, kHidden, kHidden};
+    const int outs[5] = {kHidden, kHidden, kHidden, kHidden, 1};
+    for (int l = 0; l < 5; ++l) {
+        L.fan_in[l] = fan[l];
+        L.w_off[l] = off;
+        L.w_size[l] = (int64_t)fan[l] * outs[l];
+        off += L.w_size[l];
+        L.b_off[l] = off;
+        off += outs[l];
+        if (l < 4) {
+            L.bf_off[l] = bf;
+            bf += L.w_size[l];
+        }
+    }
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct rt_mlp {
+    rt_ctx* ctx = nullptr;
+    rt_mlp_config cfg{};
+    rt::MlpLayout lay{};
+    rt::MlpNorm norm{};
+    int64_t nbf = 0;
+    float *params = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr, *ff = nullptr;
+    __bf16 *wbf = nullptr, *wtbf = nullptr;
+    // batch scratch (rows = cfg.batch)
+    __bf16 *feats = nullptr, *Z[4] = {}, *H[4] = {}, *dZa = nullptr, *dZb = nullptr, *T1 = nullptr, *T2 = nullptr;
+    float *part = nullptr, *scal = nullptr, *pred = nullptr, *vin = nullptr;  // scal: [0] mask sum, [1] loss
+    int64_t step = 0;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+template <typename T>
+hipError_t alloc(rt_mlp* h, T** p, size_t n) {
+    hipError_t e = hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
+    if (e == hipSuccess) h->allocs.push_back(*p);
+    return e;
+}
+
+rt_status check_rows(const rt_mlp* h, int64_t n) {
+    if (n < 128 || n > h->cfg.batch || n % 128)
+        return rt_internal_fail(RT_ERR_ARG, "row count must be a multiple of 128 in [128, batch]");
+    return RT_OK;
+}
+
+// Forward pass over n rows whose raw inputs are in v (device, [n][5]).
+rt_status forward(rt_mlp* h, const float* v, int64_t n, hipStream_t s) {
+    MLP_HIP(rt::launch_features(v, n, h->ff, h->norm, h->feats, s));
+    const __bf16* in = h->feats;
+    for (int l = 0; l < 4; ++l) {
+        rt::GemmArgs g{};
+        g.A = in;
+        g.lda = h->lay.fan_in[l];
+        g.B = h->wbf + h->lay.bf_off[l];
+        g.ldb = h->lay.fan_in[l];
+        g.M = (int)n;
+        g.N = kHidden;
+        g.K = h->lay.fan_in[l];
+        g.ksplit = g.K;
+        g.epi = rt::kEpiBiasGelu;
+        g.bias = h->params + h->lay.b_off[l];
+        g.outZ = h->Z[l];
+        g.outH = h->H[l];
+        MLP_HIP(rt::launch_gemm_nt(g, 1, s));
+        in = h->H[l];
+    }
+    return RT_OK;
+}
+
+// Gradient of the masked MSE over n rows into h->grad (zeroed first); loss
+// into h->scal[1].
+rt_status gradient(rt_mlp* h, const float* v, const float* t, const float* m, int64_t n, hipStream_t s) {
+    rt_status st = forward(h, v, n, s);
+    if (st != RT_OK) return st;
+    const rt::MlpLayout& L = h->lay;
+    MLP_HIP(hipMemsetAsync(h->grad, 0, (size_t)L.total * sizeof(float), s));
+    MLP_HIP(hipMemsetAsync(h->scal, 0, 2 * sizeof(float), s));
+    MLP_HIP(rt::launch_mask_sum(m, n, h->scal, s));
+    MLP_HIP(rt::launch_head(h->H[3], h->Z[3], h->params + L.w_off[4], h->params + L.b_off[4], t, m, n, h->scal,
+                            h->pred, h->scal + 1, h->dZa, h->grad + L.w_off[4], h->grad + L.b_off[4], s));
+    __bf16* dz = h->dZa;
+    __bf16* dz_next = h->dZb;
+    for (int l = 3; l >= 0; --l) {
+        const int K = L.fan_in[l];
+        MLP_HIP(rt::launch_colsum(dz, n, h->grad + L.b_off[l], s));
+        // dW_l = dZ_l^T H_{l-1}: both operands transposed so that rows are the reduction axis
+        MLP_HIP(rt::launch_transpose(dz, n, kHidden, h->T1, s));
+        const __bf16* hp = l ? h->H[l - 1] : h->feats;
+        MLP_HIP(rt::launch_transpose(hp, n, K, h->T2, s));
+        int S = kSplits;
+        while (S > 1 && (n / S) % 32) S >>= 1;
+        rt::GemmArgs g{};
+        g.A = h->T1;
+        g.lda = (int)n;
+        g.B = h->T2;
+        g.ldb = (int)n;
+        g.M = kHidden;
+        g.N = K;
+        g.K = (int)n;
+        g.ksplit = (int)(n / S);
+        g.epi = rt::kEpiStoreF32;
+        g.outF = h->part;
+        MLP_HIP(rt::launch_gemm_nt(g, S, s));
+        MLP_HIP(rt::launch_reduce_splits(h->part, S, (int64_t)kHidden * K, h->grad + L.w_off[l], s));
+        if (l > 0) {
+            rt::GemmArgs d{};
+            d.A = dz;
+            d.lda = kHidden;
+            d.B = h->wtbf + L.bf_off[l];
+            d.ldb = kHidden;
+            d.M = (int)n;
+            d.N = K;
+            d.K = kHidden;
+            d.ksplit = kHidden;
+            d.epi = rt::kEpiGeluGrad;
+            d.Zprev = h->Z[l - 1];
+            d.outZ = dz_next;
+            MLP_HIP(rt::launch_gemm_nt(d, 1, s));
+            std::swap(dz, dz_next);
+        }
+    }
+    return RT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rt_status rt_mlp_param_count(int64_t* n) {
+    if (!n) return rt_internal_fail(RT_ERR_ARG, "NULL argument");
+    *n = make_layout().total;
+    return RT_OK;
+}
+
+rt_status rt_mlp_create(rt_ctx* c, const rt_mlp_config* cfg, rt_mlp** out) {
+    if (!c || !cfg || !out) return rt_internal_fail(RT_ERR_ARG, "NULL argument");
+    if (cfg->batch < 128 || cfg->batch % 1024 || cfg->batch > (1 << 22))
+        return rt_internal_fail(RT_ERR_ARG, "batch must be a multiple of 1024 in [1024, 2^22]");
+    for (int i = 0; i < 5; ++i)
+        if (!(cfg->in_half[i] > 0) || !std::isfinite(cfg->in_center[i]))
+            return rt_internal_fail(RT_ERR_ARG, "input normalisation needs finite centres and positive half-ranges");
+    if (!(cfg->ff_scale > 0)) return rt_internal_fail(RT_ERR_ARG, "ff_scale must be positive");
+    MLP_HIP(hipSetDevice(rt_internal_device(c)));
+    rt_mlp* h = new rt_mlp();
+    h->ctx = c;
+    h->cfg = *cfg;
+    h->lay = make_layout();
+    for (int i = 0; i < 5; ++i) {
+        h->norm.center[i] = cfg->in_center[i];
+        h->norm.inv_half[i] = 1.0f / cfg->in_half[i];
+    }
+    const int64_t P = h->lay.total, B = cfg->batch;
+    h->nbf = h->lay.bf_off[3] + h->lay.w_size[3];
+    hipError_t e = hipSuccess;
+    auto A = [&](auto** p, size_t n) {
+        if (e == hipSuccess) e = alloc(h, p, n);
+    };
+    A(&h->params, P);
+    A(&h->grad, P);
+    A(&h->m1, P);
+    A(&h->m2, P);
+    A(&h->ff, rt::kFreq * 5);
+    A(&h->wbf, h->nbf);
+    A(&h->wtbf, h->nbf);
+    A(&h->feats, B * 2 * rt::kFreq);
+    for (int l = 0; l < 4; ++l) {
+        A(&h->Z[l], B * kHidden);
+        A(&h->H[l], B * kHidden);
+    }
+    A(&h->dZa, B * kHidden);
+    A(&h->dZb, B * kHidden);
+    A(&h->T1, B * kHidden);
+    A(&h->T2, B * kHidden);
+    A(&h->part, (size_t)kSplits * kHidden * kHidden);
+    A(&h->scal, 4);
+    A(&h->pred, B);
+    A(&h->vin, B * 5);
+    hipStream_t s = rt_internal_stream(c);
+    if (e == hipSuccess) e = hipMemsetAsync(h->m1, 0, P * sizeof(float), s);
+    if (e == hipSuccess) e = hipMemsetAsync(h->m2, 0, P * sizeof(float), s);
+    if (e == hipSuccess) e = rt::launch_mlp_init(h->params, h->ff, cfg->seed, cfg->ff_scale, h->lay, s);
+    if (e == hipSuccess) e = rt::launch_refresh_bf16(h->params, h->lay, h->wbf, h->wtbf, s);
+    if (e != hipSuccess) {
+        rt_mlp_destroy(h);
+        return rt_internal_fail(e == hipErrorOutOfMemory ? RT_ERR_OOM : RT_ERR_DEVICE, hipGetErrorString(e));
+    }
+    *out = h;
+    return RT_OK;
+}
+
+rt_status rt_mlp_destroy(rt_mlp* h) {
+    if (!h) return RT_OK;
+    (void)hipSetDevice(rt_internal_device(h->ctx));
+    (void)hipStreamSynchronize(rt_internal_stream(h->ctx));
+    for (void* p : h->allocs) (void)hipFree(p);
+    delete h;
+    return RT_OK;
+}
+
+rt_status rt_mlp_get_params(rt_mlp* h, float* params, float* ff) {
+    if (!h || !params || !ff) return rt_internal_fail(RT_ERR_ARG, "NULL argument");
+    hipStream_t s = rt_internal_stream(h->ctx);
+    MLP_HIP(hipMemcpyAsync(params, h->params, h->lay.total * sizeof(float), hipMemcpyDeviceToDevice, s));
+    MLP_HIP(hipMemcpyAsync(ff, h->ff, rt::kFreq * 5 * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return RT_OK;
+}
+
+rt_status rt_mlp_set_params(rt_mlp* h, const float* params, const float* ff) {
+    if (!h || !params || !ff) return rt_internal_fail(RT_ERR_ARG, "NULL argument");
+    hipStream_t s = rt_internal_stream(h->ctx);
+    MLP_HIP(hipMemcpyAsync(h->params, params, h->lay.total * sizeof(float), hipMemcpyDeviceToDevice, s));
+    MLP_HIP(hipMemcpyAsync(h->ff, ff, rt::kFreq * 5 * sizeof(float), hipMemcpyDeviceToDevice, s));
+    MLP_HIP(hipMemsetAsync(h->m1, 0, h->lay.total * sizeof(float), s));
+    MLP_HIP(hipMemsetAsync(h->m2, 0, h->lay.total * sizeof(float), s));
+    h->step = 0;
+    MLP_HIP(rt::launch_refresh_bf16(h->params, h->lay, h->wbf, h->wtbf, s));
+    return RT_OK;
+}
+
+rt_status rt_mlp_forward(rt_mlp* h, const float* v, int64_t n, float* y) {
+    if (!h || !v || !y) return rt_internal_fail(RT_ERR_ARG, "NULL argument");
+    rt_status st = check_rows(h, n);
+    if (st != RT_OK) return st;
+    hipStream_t s = rt_internal_stream(h->ctx);
+    MLP_HIP(hipSetDevice(rt_internal_device(h->ctx)));
+    if ((st = forward(h, v, n, s)) != RT_OK) return st;
+    const rt::MlpLayout& L = h->lay;
+    MLP_HIP(rt::launch_head(h->H[3], h->Z[3], h->params + L.w_off[4], h->params + L.b_off[4], nullptr, nullptr, n,
+                            nullptr, y, nullptr, nullptr, nullptr, nullptr, s));
+    return RT_OK;
+}
+
+rt_status rt_mlp_grad(rt_mlp* h, const float* v, const float* t, const float* m, int64_t n, float* grad,
+                      float* loss) {
+    if (!h || !v || !t || !m || !grad) return rt_internal_fail(RT_ERR_ARG, "NULL argument");
+    rt_status st = check_rows(h, n);
+    if (st != RT_OK) return st;
+    hipStream_t s = rt_internal_stream(h->ctx);
+    MLP_HIP(hipSetDevice(rt_internal_device(h->ctx)));
+    if ((st = gradient(h, v, t, m, n, s)) != RT_OK) return st;
+    MLP_HIP(hipMemcpyAsync(grad, h->grad, h->lay.total * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (loss) MLP_HIP(hipMemcpyAsync(loss, h->scal + 1, sizeof(float), hipMemcpyDeviceToDevice, s));
+    return RT_OK;
+}
+
+rt_status rt_mlp_train_step(rt_mlp* h, const float* v, const float* t, const float* m, int64_t n, float lr,
+                            float* loss) {
+    if (!h || !v || !t || !m) return rt_internal_fail(RT_ERR_ARG, "NULL argument");
+    if (!(lr > 0) || !std::isfinite(lr)) return rt_internal_fail(RT_ERR_ARG, "lr must be positive");
+    rt_status st = check_rows(h, n);
+    if (st != RT_OK) return st;
+    hipStream_t s = rt_internal_stream(h->ctx);
+    MLP_HIP(hipSetDevice(rt_internal_device(h->ctx)));
+    if ((st = gradient(h, v, t, m, n, s)) != RT_OK) return st;
+    h->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, (double)h->step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, (double)h->step)));
+    MLP_HIP(rt::launch_adam(h->params, h->grad, h->m1, h->m2, h->lay.total, lr, b1, b2, 1e-8f, c1, c2, s));
+    MLP_HIP(rt::launch_refresh_bf16(h->params, h->lay, h->wbf, h->wtbf, s));
+    if (loss) MLP_HIP(hipMemcpyAsync(loss, h->scal + 1, sizeof(float), hipMemcpyDeviceToDevice, s));
+    return RT_OK;
+}
+
+rt_status rt_mlp_sample_batch(rt_mlp* h, const float* maps, const uint8_t* mask, const float* tx, int32_t T,
+                              const rt_grid* g, uint64_t seed, uint64_t step, float* v, float* t, float* m,
+                              int64_t n) {
+    if (!h || !maps || !mask || !tx || !g || !v || !t || !m) return rt_internal_fail(RT_ERR_ARG, "NULL argument");
+    if (T < 1 || n < 1 || g->nx < 1 || g->ny < 1) return rt_internal_fail(RT_ERR_ARG, "empty map stack or batch");
+    hipStream_t s = rt_internal_stream(h->ctx);
+    MLP_HIP(rt::launch_sample(maps, mask, tx, T, g->x0, g->y0, g->cell, g->nx, g->ny, seed, step, v, t, m, n, s));
+    return RT_OK;
+}
+
+rt_status rt_mlp_predict_maps(rt_mlp* h, const float* tx, int32_t T, const rt_grid* g, float* maps) {
+    if (!h || !tx || !g || !maps) return rt_internal_fail(RT_ERR_ARG, "NULL argument");
+    if (T < 1 || g->nx < 1 || g->ny < 1) return rt_internal_fail(RT_ERR_ARG, "empty map stack");
+    hipStream_t s = rt_internal_stream(h->ctx);
+    MLP_HIP(hipSetDevice(rt_internal_device(h->ctx)));
+    const int64_t total = (int64_t)T * g->nx * g->ny;
+    const int64_t B = h->cfg.batch;
+    const rt::MlpLayout& L = h->lay;
+    for (int64_t r0 = 0; r0 < total; r0 += B) {
+        const int64_t rows = std::min(B, total - r0);
+        const int64_t padded = (rows + 127) / 128 * 128;
+        MLP_HIP(rt::launch_map_inputs(tx, T, g->x0, g->y0, g->cell, g->nx, g->ny, r0, rows, h->vin, s));
+        if (padded > rows) MLP_HIP(hipMemsetAsync(h->vin + 5 * rows, 0, (padded - rows) * 5 * sizeof(float), s));
+        rt_status st = forward(h, h->vin, padded, s);
+        if (st != RT_OK) return st;
+        MLP_HIP(rt::launch_head(h->H[3], h->Z[3], h->params + L.w_off[4], h->params + L.b_off[4], nullptr, nullptr,
+                                rows, nullptr, maps + r0, nullptr, nullptr, nullptr, nullptr, s));
+    }
+    return RT_OK;
+}
+
+}  // extern "C"

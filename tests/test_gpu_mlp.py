@@ -1,0 +1,130 @@
+"""GPU parity of the surrogate MLP kernels (bf16 MFMA, fp32 accumulation)
+against the float64 oracle MLP fed the same bf16-rounded weights and
+features."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as omlp
+
+from gpu_common import ctx, requires_gpu
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+def bf16(x):
+    """Round to bfloat16 (nearest even) and back, in float64."""
+    a = np.asarray(x, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _mlp(batch=1024, seed=3, ff_scale=2.0):
+    from paper_2303_11103_amd.surrogate import MLP
+    return MLP(ctx(), batch=batch, ff_scale=ff_scale, seed=seed)
+
+
+def _oracle_inputs(m, v):
+    p, ff = m.get_params()
+    theta = p.cpu().double().numpy()
+    layers = omlp.unpack(theta)
+    # the GPU multiplies bf16 copies of W1..W4 (biases and head stay fp32)
+    q = []
+    for li, (W, b) in enumerate(layers):
+        q.append(bf16(W).reshape(-1) if li < 4 else W.reshape(-1))
+        q.append(b)
+    theta_q = np.concatenate(q)
+    ffn = ff.cpu().double().numpy()
+    feats = bf16(omlp.features(np.asarray(v, dtype=np.float32).astype(np.float64), ffn))
+    return theta, theta_q, ffn, feats
+
+
+def test_forward_matches_oracle():
+    m = _mlp()
+    rng = np.random.default_rng(0)
+    v = rng.uniform(-1, 1, size=(512, 5)).astype(np.float32)
+    y = m.forward(torch.tensor(v, device="cuda")).cpu().double().numpy()
+    _, theta_q, ffn, feats = _oracle_inputs(m, v)
+    yo, _ = omlp.forward(theta_q, v, ffn, feats=feats)
+    scale = np.max(np.abs(yo))
+    assert scale > 1e-3
+    assert np.max(np.abs(y - yo)) <= 2e-2 * scale
+
+
+def test_gradient_matches_oracle():
+    m = _mlp(seed=5)
+    rng = np.random.default_rng(1)
+    n = 1024
+    v = rng.uniform(-1, 1, size=(n, 5)).astype(np.float32)
+    t = rng.normal(scale=2.0, size=n).astype(np.float32)
+    msk = (rng.random(n) < 0.7).astype(np.float32)
+    dev = "cuda"
+    g, loss = m.grad(torch.tensor(v, device=dev), torch.tensor(t, device=dev), torch.tensor(msk, device=dev))
+    g = g.cpu().double().numpy()
+    _, theta_q, ffn, feats = _oracle_inputs(m, v)
+    yo, cache = omlp.forward(theta_q, v, ffn, feats=feats)
+    go = omlp.backward(theta_q, cache, yo, t.astype(np.float64), msk.astype(np.float64))
+    lo = omlp.loss(yo, t, msk)
+    assert abs(float(loss) - lo) <= 2e-2 * lo
+    cos = float(np.dot(g, go) / (np.linalg.norm(g) * np.linalg.norm(go)))
+    assert cos >= 0.999, cos
+    # per parameter block (W_l, b_l, ...) the largest deviation within 2% of the block's scale
+    k = 0
+    for W, b in omlp.layer_shapes():
+        for shape in (W, b):
+            sz = int(np.prod(shape))
+            blk, ref = g[k:k + sz], go[k:k + sz]
+            assert np.max(np.abs(blk - ref)) <= 2e-2 * np.max(np.abs(ref)) + 1e-12, (k, shape)
+            k += sz
+
+
+def test_training_reduces_loss_on_a_smooth_field():
+    m = _mlp(batch=4096, seed=7, ff_scale=1.0)
+    rng = np.random.default_rng(2)
+    dev = "cuda"
+    losses = []
+    for s in range(300):
+        v = rng.uniform(-1, 1, size=(4096, 5)).astype(np.float32)
+        t = (10 * np.sin(2 * v[:, 3]) + 5 * np.cos(3 * v[:, 4]) - 0.5 * v[:, 2]).astype(np.float32)
+        msk = np.ones(4096, dtype=np.float32)
+        loss = m.train_step(torch.tensor(v, device=dev), torch.tensor(t, device=dev), torch.tensor(msk, device=dev),
+                            2e-3)
+        losses.append(float(loss))
+    assert losses[-1] < 0.02 * losses[0], (losses[0], losses[-1])
+
+
+def test_sample_batch_and_predict_maps():
+    import scenegen as sg
+    m = _mlp(batch=1024, seed=9)
+    grid = sg.Grid(-10.0, -20.0, 2.0, 16, 12, 1.5)
+    T = 3
+    dev = "cuda"
+    rng = np.random.default_rng(3)
+    maps = torch.tensor(rng.normal(size=(T, grid.ny, grid.nx)).astype(np.float32), device=dev)
+    mask = torch.tensor((rng.random((T, grid.ny, grid.nx)) < 0.5).astype(np.uint8), device=dev)
+    tx = torch.tensor(rng.uniform(-5, 5, size=(T, 3)).astype(np.float32), device=dev)
+    v, t, mm = m.sample_batch(maps, mask, tx, grid, seed=11, step=4, n=1024)
+    v, t, mm = v.cpu().numpy(), t.cpu().numpy(), mm.cpu().numpy()
+    txn, mapsn, maskn = tx.cpu().numpy(), maps.cpu().numpy(), mask.cpu().numpy()
+    for i in range(1024):
+        k = int(np.argmin(np.abs(txn - v[i, :3]).sum(1)))
+        assert np.array_equal(txn[k], v[i, :3])
+        ix = int(round((v[i, 3] - grid.x0) / grid.cell - 0.5))
+        iy = int(round((v[i, 4] - grid.y0) / grid.cell - 0.5))
+        if mm[i] > 0:
+            assert maskn[k, iy, ix] == 1 and t[i] == mapsn[k, iy, ix]
+    assert mm.mean() > 0.9
+    pred = m.predict_maps(tx, grid).cpu().numpy()
+    # the same inputs through the row-wise forward
+    ys, xs = np.meshgrid(grid.y0 + (np.arange(grid.ny) + 0.5) * grid.cell,
+                         grid.x0 + (np.arange(grid.nx) + 0.5) * grid.cell, indexing="ij")
+    rows = []
+    for k in range(T):
+        rows.append(np.stack([np.full(xs.size, txn[k, 0]), np.full(xs.size, txn[k, 1]), np.full(xs.size, txn[k, 2]),
+                              xs.reshape(-1), ys.reshape(-1)], 1))
+    vv = np.concatenate(rows).astype(np.float32)
+    pad = (-len(vv)) % 128
+    vp = np.concatenate([vv, np.zeros((pad, 5), np.float32)])
+    y = m.forward(torch.tensor(vp, device=dev)).cpu().numpy()[:len(vv)]
+    assert np.allclose(pred.reshape(-1), y, atol=1e-5)

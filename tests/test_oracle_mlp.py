@@ -1,0 +1,53 @@
+"""Pins of the float64 surrogate MLP: its hand-written backward pass against
+central finite differences, and the tanh-form GELU against the erf form."""
+import math
+
+import numpy as np
+
+from oracle import mlp
+
+
+def _problem(seed=0, n=48):
+    rng = np.random.default_rng(seed)
+    theta = rng.normal(scale=0.05, size=mlp.param_count())
+    Bf = rng.normal(scale=2.0, size=(mlp.N_FREQ, mlp.N_IN))
+    v = rng.uniform(-1, 1, size=(n, 5))
+    t = rng.normal(scale=3.0, size=n)
+    m = (rng.random(n) < 0.8).astype(np.float64)
+    return theta, Bf, v, t, m
+
+
+def test_param_count_matches_layout():
+    assert mlp.param_count() == 128 * 256 + 256 + 3 * (256 * 256 + 256) + 256 + 1 == 230_657
+
+
+def test_backward_matches_central_differences():
+    theta, Bf, v, t, m = _problem()
+    y, cache = mlp.forward(theta, v, Bf)
+    g = mlp.backward(theta, cache, y, t, m)
+    rng = np.random.default_rng(1)
+    # 10 random parameters plus one of every layer's bias and the head bias
+    idx = list(rng.choice(theta.size, size=10, replace=False)) + [32768, 33024 + 65536, theta.size - 1]
+    for i in idx:
+        h = 1e-6
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (mlp.loss(mlp.forward(tp, v, Bf)[0], t, m) - mlp.loss(mlp.forward(tm, v, Bf)[0], t, m)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_gelu_tanh_form_close_to_erf_form_and_derivative():
+    x = np.linspace(-6, 6, 2001)
+    erf_form = 0.5 * x * (1 + np.vectorize(math.erf)(x / math.sqrt(2)))
+    assert np.max(np.abs(mlp.gelu(x) - erf_form)) < 1e-3
+    h = 1e-6
+    fd = (mlp.gelu(x + h) - mlp.gelu(x - h)) / (2 * h)
+    assert np.max(np.abs(fd - mlp.gelu_grad(x))) < 1e-8
+
+
+def test_features_are_unit_circle_pairs():
+    theta, Bf, v, t, m = _problem()
+    f = mlp.features(v, Bf)
+    assert f.shape == (v.shape[0], 128)
+    assert np.allclose(f[:, :64] ** 2 + f[:, 64:] ** 2, 1.0)
