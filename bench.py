@@ -175,6 +175,9 @@ def main():
         "node_visits_per_ray_bounce": round(float(wk[1].sum() / wk[0].sum()), 2),
         "tri_tests_per_ray_bounce": round(float(wk[2].sum() / wk[0].sum()), 2),
         "flop_per_ray_bounce": round(float(per_launch_flops / wk[0].sum()), 1),
+        "rays_per_depth": [int(x) for x in wk[0]],
+        "node_visits_per_depth": [int(x) for x in wk[1]],
+        "tri_tests_per_depth": [int(x) for x in wk[2]],
     }
     log("bench: kernels %.3f ms/step, %.2f TFLOP/s algorithmic (%.1f%% of %.1f)" % (
         per_step_kernel_ms, achieved, 100 * achieved / PEAK_ALU_TFLOPS, PEAK_ALU_TFLOPS))

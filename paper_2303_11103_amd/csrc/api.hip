@@ -201,6 +201,8 @@ rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_dev
     a.stride = p->ray_stride;
     a.count = count;
     band_perm(count, p->ray_stride, a.perm_f, a.perm_g);
+    a.perm_full = a.perm_f ? (count / a.perm_f) * a.perm_f : 0;
+    a.perm_inv = a.perm_f ? 1.0 / (double)a.perm_f : 0.0;
     a.tmin = p->t_min;
     for (int i = 0; i < 3; ++i) a.tx[i] = tx->pos[i];
     a.tx_ant = make_antenna(tx);

@@ -59,18 +59,21 @@ __device__ __forceinline__ cf cadd(cf a, cf b) { return cf{a.re + b.re, a.im + b
 __device__ __forceinline__ cf csub(cf a, cf b) { return cf{a.re - b.re, a.im - b.im}; }
 __device__ __forceinline__ cf cmul(cf a, cf b) { return cf{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 __device__ __forceinline__ cf cmulr(cf a, float s) { return cf{a.re * s, a.im * s}; }
+// fp32 field arithmetic uses the hardware reciprocal (about 1 ulp): the field
+// feeds coverage sums compared at 1e-4 relative.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ cf cdiv(cf a, cf b) {
-    float den = b.re * b.re + b.im * b.im;
-    return cf{(a.re * b.re + a.im * b.im) / den, (a.im * b.re - a.re * b.im) / den};
+    const float inv = frcp(b.re * b.re + b.im * b.im);
+    return cf{(a.re * b.re + a.im * b.im) * inv, (a.im * b.re - a.re * b.im) * inv};
 }
 __device__ __forceinline__ cf csqrt(cf z) {  // principal branch, cancellation-free
-    float r = hypotf(z.re, z.im);
+    const float r = sqrtf(z.re * z.re + z.im * z.im);
     if (z.re >= 0.0f) {
-        float re = sqrtf(0.5f * (r + z.re));
-        return cf{re, re > 0.0f ? z.im / (2.0f * re) : 0.0f};
+        const float re = sqrtf(0.5f * (r + z.re));
+        return cf{re, re > 0.0f ? 0.5f * z.im * frcp(re) : 0.0f};
     }
-    float im = sqrtf(0.5f * (r - z.re));
-    return cf{fabsf(z.im) / (2.0f * im), copysignf(im, z.im)};
+    const float im = sqrtf(0.5f * (r - z.re));
+    return cf{0.5f * fabsf(z.im) * frcp(im), copysignf(im, z.im)};
 }
 
 // ---------------------------------------------------------------- double vec / complex
@@ -124,11 +127,13 @@ __device__ __forceinline__ f3 antenna_field(const Antenna& ant, f3 d) {
     float lx = R[0] * d.x + R[3] * d.y + R[6] * d.z;
     float ly = R[1] * d.x + R[4] * d.y + R[7] * d.z;
     float lz = R[2] * d.x + R[5] * d.y + R[8] * d.z;
-    float rho = sqrtf(lx * lx + ly * ly);
-    float cph = 1.0f, sph = 0.0f;
-    if (rho > 0.0f) {
-        cph = lx / rho;
-        sph = ly / rho;
+    const float rho2 = lx * lx + ly * ly;
+    float cph = 1.0f, sph = 0.0f, rho = 0.0f;
+    if (rho2 > 0.0f) {
+        const float ir = __builtin_amdgcn_rsqf(rho2);
+        rho = rho2 * ir;
+        cph = lx * ir;
+        sph = ly * ir;
     }
     float c = ant.pattern == kPatTR38901 ? tr38901_amp(lz, lx, ly) : 1.0f;
     float tx = c * lz * cph, ty = c * lz * sph, tz = -c * rho;

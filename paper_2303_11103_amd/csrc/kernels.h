@@ -41,6 +41,8 @@ struct SbrArgs {
     int64_t count;      // traced rays (positions 0..count-1)
     int64_t pos0, chunk; // positions handled by this launch sequence: [pos0, pos0 + chunk)
     int64_t perm_f, perm_g;  // band permutation (Fibonacci numbers F_m, F_{m-1}); 0 = identity
+    int64_t perm_full;       // positions below this are permuted (whole bands)
+    double perm_inv;         // 1 / F_m
     double tmin;
     double tx[3];
     Antenna tx_ant, rx_ant;

@@ -17,30 +17,41 @@ namespace rt {
 namespace {
 
 __device__ __forceinline__ d3 fib_dir(int64_t i, int64_t N) {
-    double z = 1.0 - (2.0 * (double)i + 1.0) / (double)N;
-    double rho = sqrt((1.0 - z) * (1.0 + z));
-    uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull;
-    double phi = 2.0 * kPi * ((double)h * 0x1p-64);
+    const double z = 1.0 - (2.0 * (double)i + 1.0) / (double)N;
+    const double rho = sqrt((1.0 - z) * (1.0 + z));
+    const uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull;
     double s, c;
-    sincos(phi, &s, &c);
+    sincospi(2.0 * ((double)h * 0x1p-64), &s, &c);  // angle 2 pi frac(i g)
     return d3{rho * c, rho * s, z};
 }
 
-// Traced position j -> lattice index.  With a band permutation, positions are
-// taken in bands of F consecutive indices (a thin latitude ring); inside a
-// band, rank r maps to offset r * G mod F (G the preceding Fibonacci number),
-// which walks the ring in azimuth order, so 64 consecutive positions form a
-// compact patch of directions.
-__device__ __forceinline__ int64_t ray_index(const SbrArgs& a, int64_t j) {
-    if (a.perm_f > 0) {
-        const int64_t F = a.perm_f;
-        const int64_t full = (a.count / F) * F;
-        if (j < full) {
-            int64_t b = j / F, r = j - b * F;
-            j = b * F + (r * a.perm_g) % F;
-        }
+// q = floor(x / F), r = x - q F for 0 <= x < 2^52 and F < 2^26, using the
+// precomputed double 1/F and one correction step.
+__device__ __forceinline__ void divmod(int64_t x, int64_t F, double invF, int64_t& q, int64_t& r) {
+    q = (int64_t)((double)x * invF);
+    r = x - q * F;
+    if (r < 0) {
+        q -= 1;
+        r += F;
+    } else if (r >= F) {
+        q += 1;
+        r -= F;
     }
-    return a.begin + j * a.stride;
+}
+
+// Traced position j -> lattice position.  With a band permutation, positions
+// are taken in bands of F consecutive indices (a thin latitude ring); inside
+// a band, rank r maps to offset r * G mod F (G the preceding Fibonacci
+// number), which walks the ring in azimuth order, so 64 consecutive positions
+// form a compact patch of directions.
+__device__ __forceinline__ int64_t lattice_position(const SbrArgs& a, int64_t j) {
+    if (a.perm_f > 0 && j < a.perm_full) {
+        int64_t b, r, q2, r2;
+        divmod(j, a.perm_f, a.perm_inv, b, r);
+        divmod(r * a.perm_g, a.perm_f, a.perm_inv, q2, r2);
+        return b * a.perm_f + r2;
+    }
+    return j;
 }
 
 __device__ __forceinline__ uint32_t mix32(uint64_t k) {
@@ -127,9 +138,8 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(4, 
         bool alive = false;
         if (active) {
             if (FIRST) {
-                const int64_t j = a.pos0 + item;
-                const int64_t ri = ray_index(a, j);
-                st.d = fib_dir(ri, a.num_rays);
+                const int64_t pos = lattice_position(a, a.pos0 + item);
+                st.d = fib_dir(a.begin + pos * a.stride, a.num_rays);
                 st.o = d3{a.tx[0], a.tx[1], a.tx[2]};
                 const f3 F = antenna_field(a.tx_ant, f3{(float)st.d.x, (float)st.d.y, (float)st.d.z});
                 st.E[0] = F.x;
@@ -140,7 +150,7 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(4, 
                 st.E[5] = 0.0f;
                 st.excl = -1;
                 st.prefix = -1;
-                st.ray = (int32_t)((ri - a.begin) / a.stride);  // lattice position (unpermuted)
+                st.ray = (int32_t)pos;
             } else {
                 load_ray(a.in + item, st);
             }
