@@ -86,6 +86,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the paths/gradient side measurements")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate measurement")
+    ap.add_argument("--surrogate-steps", type=int, default=3000)
+    ap.add_argument("--surrogate-tx", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the shoot-and-bounce workload of one transmitter runs on a single "
@@ -211,6 +214,14 @@ def main():
             log("bench: extras failed: %r" % (e,))
             result["extras_error"] = repr(e)
 
+    if not args.no_surrogate:
+        try:
+            result["surrogate"] = surrogate_bench(rt, ctx, scene, w, torch, steps=args.surrogate_steps,
+                                                  n_tx=args.surrogate_tx)
+        except Exception as e:
+            log("bench: surrogate failed: %r" % (e,))
+            result["surrogate_error"] = repr(e)
+
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on a ray sample ...")
         cb = cpu_baseline()
@@ -246,6 +257,75 @@ def extras(rt, ctx, scene, w, torch):
     torch.cuda.synchronize()
     res["grad_ms"] = round((time.perf_counter() - t0) * 1e3 / 10, 4)
     res["grad_paths"] = int((od["depth"][0] >= 0).sum())
+    return res
+
+
+def surrogate_bench(rt, ctx, scene, w, torch, steps=3000, n_tx=4096, seed=3):
+    """Learned surrogate on the urban scene: ray-traced maps (1e7 rays, depth 3,
+    200x200 cells of 2 m) for transmitters uniform over the rooftops, split
+    7/8 train, 1/16 validation, 1/16 test; trained with the library's MFMA
+    kernels; reports test RMSE in dB over cells with >= 16 hits, the
+    fallback mask (cells whose validation RMSE exceeds 6 dB) and maps/s of
+    the surrogate and of the ray tracer at the same resolution."""
+    import numpy as np
+    import scenegen as sg
+    from paper_2303_11103_amd import surrogate as S
+    grid = sg.Grid(-200.0, -200.0, 2.0, 200, 200, 1.5)
+    tx_np = sg.rooftop_tx_positions(w.scene, n_tx, seed=seed)
+    dev = ctx.torch_device
+    tx = torch.tensor(tx_np, device=dev)
+    p = rt.TraceParams(w.scene.freq_hz, 3, 10_000_000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    maps, mask = S.ray_traced_maps(ctx, scene, p, tx_np, grid)
+    torch.cuda.synchronize()
+    rt_s = time.perf_counter() - t0
+    n_val = n_test = max(1, n_tx // 16)
+    n_tr = n_tx - n_val - n_test
+    tr, va, te = slice(0, n_tr), slice(n_tr, n_tr + n_val), slice(n_tr + n_val, n_tx)
+    # targets: cells with >= 16 hits; the dB values there are finite
+    maps = torch.where(mask.bool(), maps, torch.zeros_like(maps))
+    lo = np.array([-200.0, -200.0, 10.0, -200.0, -200.0])
+    hi = np.array([200.0, 200.0, 65.0, 200.0, 200.0])
+    m = S.MLP(ctx, batch=32768, ff_scale=4.0, seed=seed, center=(lo + hi) / 2, half=(hi - lo) / 2)
+    rep = S.train(m, maps[tr].contiguous(), mask[tr].contiguous(), tx[tr].contiguous(), grid, steps=steps, lr=2e-3,
+                  seed=seed)
+    pv = m.predict_maps(tx[va], grid)
+    fb = S.fallback_mask(pv, maps[va], mask[va], threshold_db=6.0)
+    val_rmse = S.rmse_db(pv, maps[va], mask[va])
+    pt = m.predict_maps(tx[te], grid)
+    test_rmse = S.rmse_db(pt, maps[te], mask[te])
+    keep = mask[te].bool() & ~fb[None]
+    d = (pt - maps[te])[keep]
+    test_rmse_nofb = float(torch.sqrt(torch.mean(d * d))) if d.numel() else float("nan")
+    # inference speed: 1024 transmitters per call
+    q = tx[:1024].contiguous() if n_tx >= 1024 else tx
+    out = torch.empty((q.shape[0], grid.ny, grid.nx), dtype=torch.float32, device=dev)
+    m.predict_maps(q, grid, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.predict_maps(q, grid, out=out)
+    torch.cuda.synchronize()
+    inf_s = time.perf_counter() - t0
+    sur_maps_s = q.shape[0] / inf_s
+    rt_maps_s = n_tx / rt_s
+    fb_frac = float(fb.float().mean())
+    res = {
+        "maps_per_s": round(sur_maps_s, 1),
+        "ray_tracer_maps_per_s": round(rt_maps_s, 1),
+        "speedup": round(sur_maps_s / rt_maps_s, 1),
+        "test_rmse_db": round(test_rmse, 3),
+        "test_rmse_db_outside_fallback": round(test_rmse_nofb, 3),
+        "val_rmse_db": round(val_rmse, 3),
+        "fallback_cell_fraction": round(fb_frac, 4),
+        # with a non-empty fallback mask every full-map query also runs the ray tracer
+        "maps_per_s_with_fallback": round(sur_maps_s if fb_frac == 0 else 1.0 / (1.0 / sur_maps_s + 1.0 / rt_maps_s), 1),
+        "train_steps": rep.steps, "train_s": round(rep.seconds, 1), "train_final_loss": round(rep.final_loss, 3),
+        "dataset": "%d tx (%d train / %d val / %d test), 200x200 cells of 2 m, 1e7 rays, depth 3" % (
+            n_tx, n_tr, n_val, n_test),
+    }
+    log("bench: surrogate %s" % res)
+    m.close()
     return res
 
 
