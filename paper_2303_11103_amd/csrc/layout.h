@@ -6,23 +6,27 @@
 
 namespace rt {
 
-// Binary BVH node holding the bounds of both children (one 64-byte line).
-//   a = (lo0.x, hi0.x, lo0.y, hi0.y)   b = (lo1.x, hi1.x, lo1.y, hi1.y)
-//   c = (lo0.z, hi0.z, lo1.z, hi1.z)   child[0], child[1]
-// child >= 0: index of an inner node; child < 0: leaf ~((first << 5) | (count - 1))
-// over the reordered triangle array, count <= 32.
-struct alignas(64) Node {
-    float a[4];
-    float b[4];
-    float c[4];
-    int32_t child[2];
-    int32_t pad[2];
+// 4-wide BVH node holding the bounds of its (up to) four children, child
+// coordinates interleaved so that one 16-byte load fetches one bound of all
+// four children (two 64-byte lines):
+//   bx[0] = lo.x, bx[1] = hi.x, bx[2] = lo.y, bx[3] = hi.y, bz[0] = lo.z, bz[1] = hi.z
+// child >= 0: index of an inner node; kEmptyChild: unused slot; other
+// negative values: leaf ~((first << 5) | (count - 1)) over the reordered
+// triangle array, count <= 32.
+struct alignas(128) Node {
+    float bx[4][4];
+    float bz[2][4];
+    int32_t child[4];
+    int32_t pad[4];
 };
-static_assert(sizeof(Node) == 64, "node must be one cache line");
+static_assert(sizeof(Node) == 128, "node must be two cache lines");
 
+constexpr int32_t kEmptyChild = (int32_t)0x80000000;
 constexpr int kLeafShift = 5;
 constexpr int kMaxLeaf = 1 << kLeafShift;  // 32
-constexpr int kMaxDepth = 30;              // traversal stack is kMaxDepth + 2 deep
+constexpr int kMaxDepth = 30;              // binary build tree depth bound
+constexpr int kStackEntries = 32;          // traversal stack entries per lane kept in LDS
+constexpr int kStackOverflow = 32;         // further entries per lane in private memory (deep trees)
 
 inline int32_t make_leaf(int32_t first, int32_t count) { return ~((first << kLeafShift) | (count - 1)); }
 

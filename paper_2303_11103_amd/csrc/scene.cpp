@@ -283,8 +283,8 @@ int build_scene(const float* V, int64_t nv, const int32_t* F, int64_t nt, const 
     builder.build(0, (int32_t)nt, 0);
     auto& bn = builder.nodes();
     out.depth = builder.max_depth();
-    if (out.depth > kMaxDepth) {  // the traversal stack holds kMaxDepth + 2 entries
-        err = "BVH deeper than the traversal stack";
+    if (out.depth > kMaxDepth + 1) {
+        err = "BVH build tree deeper than expected";
         return -1;
     }
 
@@ -298,50 +298,95 @@ int build_scene(const float* V, int64_t nv, const int32_t* F, int64_t nt, const 
         new_of_old[prims[i].tri] = (int32_t)i;
     }
 
-    // flatten in breadth-first order (the first nodes are the top levels, which
-    // the kernels stage in LDS): every inner build node becomes a GPU node
-    // holding its two children's bounds; a root leaf gets an inner wrapper.
+    // Collapse the binary build tree into a 4-wide tree: a node adopts up to
+    // four descendants by repeatedly opening the inner child with the largest
+    // surface area.  Nodes are numbered breadth first, so the first ones are
+    // the top levels, which the kernels stage in LDS.
     const double p = out.pad;
-    auto set_box = [&](float* xy, float* z, const Box& B) {
-        xy[0] = round_down(B.lo[0] - p); xy[1] = round_up(B.hi[0] + p);
-        xy[2] = round_down(B.lo[1] - p); xy[3] = round_up(B.hi[1] + p);
-        z[0] = round_down(B.lo[2] - p);  z[1] = round_up(B.hi[2] + p);
+    auto set_box = [&](Node& g, int slot, const Box& B) {
+        g.bx[0][slot] = round_down(B.lo[0] - p);
+        g.bx[1][slot] = round_up(B.hi[0] + p);
+        g.bx[2][slot] = round_down(B.lo[1] - p);
+        g.bx[3][slot] = round_up(B.hi[1] + p);
+        g.bz[0][slot] = round_down(B.lo[2] - p);
+        g.bz[1][slot] = round_up(B.hi[2] + p);
     };
-    if (bn[0].left < 0) {
-        Node g;
-        set_box(g.a, g.c, bn[0].box);
-        // both children are the same leaf (the second visit finds nothing new)
-        set_box(g.b, g.c + 2, bn[0].box);
-        g.child[0] = g.child[1] = make_leaf(bn[0].first, bn[0].count);
-        g.pad[0] = g.pad[1] = 0;
-        out.nodes.push_back(g);
-        out.depth = 1;
-    } else {
-        std::vector<int32_t> order;      // build-node ids of inner nodes in BFS order
+    auto empty_slot = [&](Node& g, int slot) {
+        g.bx[0][slot] = g.bx[2][slot] = g.bz[0][slot] = INFINITY;
+        g.bx[1][slot] = g.bx[3][slot] = g.bz[1][slot] = -INFINITY;
+        g.child[slot] = kEmptyChild;
+    };
+    auto gather = [&](int32_t b) {
+        std::vector<int32_t> kids;
+        if (bn[b].left < 0) {
+            kids.push_back(b);  // a root leaf becomes the only child of the root
+            return kids;
+        }
+        kids = {bn[b].left, bn[b].right};
+        while (kids.size() < 4) {
+            int best = -1;
+            double area = -1.0;
+            for (int i = 0; i < (int)kids.size(); ++i) {
+                const BuildNode& c = bn[kids[i]];
+                if (c.left >= 0 && c.box.area() > area) {
+                    area = c.box.area();
+                    best = i;
+                }
+            }
+            if (best < 0) break;
+            int32_t open = kids[best];
+            kids.erase(kids.begin() + best);
+            kids.insert(kids.begin() + best, bn[open].right);
+            kids.insert(kids.begin() + best, bn[open].left);
+        }
+        return kids;
+    };
+    {
+        std::vector<int32_t> order = {0};            // build nodes that become GPU nodes, BFS order
+        std::vector<std::vector<int32_t>> kids_of;
         std::vector<int32_t> gpu_of(bn.size(), -1);
-        order.push_back(0);
         gpu_of[0] = 0;
         for (size_t h = 0; h < order.size(); ++h) {
-            const BuildNode& n = bn[order[h]];
-            for (int32_t c : {n.left, n.right}) {
-                if (bn[c].left >= 0) {
+            std::vector<int32_t> kids = gather(order[h]);
+            for (int32_t c : kids) {
+                if (bn[c].left >= 0 && c != order[h]) {
                     gpu_of[c] = (int32_t)order.size();
                     order.push_back(c);
                 }
             }
+            kids_of.push_back(kids);
         }
         out.nodes.resize(order.size());
+        std::vector<int> need(order.size(), 0);
         for (size_t h = 0; h < order.size(); ++h) {
-            const BuildNode& n = bn[order[h]];
             Node& g = out.nodes[h];
-            set_box(g.a, g.c, bn[n.left].box);
-            set_box(g.b, g.c + 2, bn[n.right].box);
-            int32_t kids[2] = {n.left, n.right};
-            for (int i = 0; i < 2; ++i) {
-                const BuildNode& ch = bn[kids[i]];
-                g.child[i] = ch.left < 0 ? make_leaf(ch.first, ch.count) : gpu_of[kids[i]];
+            std::memset(&g, 0, sizeof(Node));
+            const auto& kids = kids_of[h];
+            for (int slot = 0; slot < 4; ++slot) {
+                if (slot >= (int)kids.size()) {
+                    empty_slot(g, slot);
+                    continue;
+                }
+                const BuildNode& c = bn[kids[slot]];
+                set_box(g, slot, c.box);
+                g.child[slot] = (c.left < 0 || kids[slot] == order[h]) ? make_leaf(c.first, c.count) : gpu_of[kids[slot]];
             }
-            g.pad[0] = g.pad[1] = 0;
+        }
+        // worst-case stack: along any root-to-leaf path, a visit pushes all but one child
+        for (size_t h = order.size(); h-- > 0;) {
+            int deepest = 0, n = 0;
+            for (int slot = 0; slot < 4; ++slot) {
+                int32_t c = out.nodes[h].child[slot];
+                if (c == kEmptyChild) continue;
+                ++n;
+                if (c >= 0) deepest = std::max(deepest, need[c]);
+            }
+            need[h] = (n - 1) + deepest;
+        }
+        out.stack_need = need[0] + 1;
+        if (out.stack_need > kStackEntries + kStackOverflow) {
+            err = "BVH needs a deeper traversal stack than " + std::to_string(kStackEntries + kStackOverflow);
+            return -1;
         }
     }
 

@@ -15,7 +15,8 @@ struct HostScene {
     std::vector<int32_t> face_tris;   // per face, its triangles (leaf-order indices)
     std::vector<int32_t> face_of_input;
     int32_t num_faces = 0;
-    int depth = 0;
+    int depth = 0;                    // depth of the binary build tree
+    int stack_need = 0;               // worst-case traversal stack entries of the 4-wide tree
     double max_abs = 0.0;             // largest |coordinate| (at least 64 m)
     double pad = 0.0;                 // bounding-box inflation [m]
     double build_ms = 0.0;

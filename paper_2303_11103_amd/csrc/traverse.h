@@ -9,8 +9,8 @@ namespace rt {
 
 constexpr int kBlock = 256;       // block size of kernels that do not stage nodes
 constexpr int kTraceBlock = 512;  // block size of the shoot-and-bounce kernels
-constexpr int kStack = kMaxDepth + 2;
-constexpr int kLdsNodes = 256;    // top BVH nodes (breadth-first order) staged in LDS
+constexpr int kStack = kStackEntries;
+constexpr int kLdsNodes = 128;    // top BVH nodes (breadth-first order) staged in LDS, 16 KB
 constexpr float kDn = 1.0f - 1e-6f;  // conservative slab interval factors
 constexpr float kUp = 1.0f + 1e-6f;
 
@@ -75,13 +75,38 @@ __device__ __forceinline__ int stage_nodes(const DevScene& sc, Node* lds) {
     const int n = sc.num_nodes < kLdsNodes ? sc.num_nodes : kLdsNodes;
     const float4* src = reinterpret_cast<const float4*>(sc.nodes);
     float4* dst = reinterpret_cast<float4*>(lds);
-    for (int i = threadIdx.x; i < 4 * n; i += blockDim.x) dst[i] = src[i];
+    for (int i = threadIdx.x; i < 8 * n; i += blockDim.x) dst[i] = src[i];
     __syncthreads();
     return n;
 }
 
-// Nodes with index < n_lds are read from the LDS copy, the others from
-// global memory (L2-resident for the scenes here).
+// Slab test of one child box: entry distance (or +inf when missed).
+__device__ __forceinline__ float slab(float lx, float hx, float ly, float hy, float lz, float hz, float ix, float iy,
+                                      float iz, float oix, float oiy, float oiz, float tfar) {
+    const float a0 = fmaf(lx, ix, -oix), a1 = fmaf(hx, ix, -oix);
+    const float b0 = fmaf(ly, iy, -oiy), b1 = fmaf(hy, iy, -oiy);
+    const float c0 = fmaf(lz, iz, -oiz), c1 = fmaf(hz, iz, -oiz);
+    const float n = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), 0.0f));
+    const float f = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), tfar));
+    return n * kDn <= f * kUp ? n : __builtin_inff();
+}
+
+__device__ __forceinline__ void cswap(float& ka, int& va, float& kb, int& vb) {
+    if (kb < ka) {
+        const float tk = ka;
+        ka = kb;
+        kb = tk;
+        const int tv = va;
+        va = vb;
+        vb = tv;
+    }
+}
+
+// Closest hit (ANY = false) or any hit on an open segment (ANY = true)
+// through the 4-wide BVH.  Nodes with index < n_lds are read from the LDS
+// copy, the others from global memory.  At an inner node the hit children
+// are ordered by entry distance: the nearest is visited next, the others
+// pushed farthest first.
 template <bool ANY, bool STATS = false, int BS = kBlock>
 __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_nodes, int n_lds, d3 o, d3 d, int excl0,
                                         int excl1, double tmin, double& tbest, int32_t (*stack)[BS],
@@ -93,47 +118,52 @@ __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_node
     float tfar = ANY ? kUp : f_up(tbest);
     int best = -1;
     int node = 0, sp = 0;
+    int32_t ovf[kStackOverflow];  // entries beyond the LDS stack (deep trees only)
+    auto push = [&](int v) {
+        if (sp < kStack) stack[sp][tid] = v;
+        else ovf[sp - kStack] = v;
+        ++sp;
+    };
+    auto pop = [&]() {
+        --sp;
+        return sp < kStack ? stack[sp][tid] : ovf[sp - kStack];
+    };
     while (true) {
         if (node >= 0) {
             if (STATS) ts->nodes++;
-            float4 A, B, C;
+            float4 X0, X1, Y0, Y1, Z0, Z1;
             int4 ch;
             if (node < n_lds) {
                 const float4* np = reinterpret_cast<const float4*>(lds_nodes + node);
-                A = np[0];
-                B = np[1];
-                C = np[2];
-                ch = reinterpret_cast<const int4*>(np)[3];
+                X0 = np[0]; X1 = np[1]; Y0 = np[2]; Y1 = np[3]; Z0 = np[4]; Z1 = np[5];
+                ch = reinterpret_cast<const int4*>(np)[6];
             } else {
                 const float4* np = reinterpret_cast<const float4*>(sc.nodes + node);
-                A = np[0];
-                B = np[1];
-                C = np[2];
-                ch = reinterpret_cast<const int4*>(np)[3];
+                X0 = np[0]; X1 = np[1]; Y0 = np[2]; Y1 = np[3]; Z0 = np[4]; Z1 = np[5];
+                ch = reinterpret_cast<const int4*>(np)[6];
             }
-            float a0 = fmaf(A.x, ix, -oix), a1 = fmaf(A.y, ix, -oix);
-            float b0 = fmaf(A.z, iy, -oiy), b1 = fmaf(A.w, iy, -oiy);
-            float c0 = fmaf(C.x, iz, -oiz), c1 = fmaf(C.y, iz, -oiz);
-            float n0 = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), 0.0f));
-            float f0 = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), tfar));
-            float a2 = fmaf(B.x, ix, -oix), a3 = fmaf(B.y, ix, -oix);
-            float b2 = fmaf(B.z, iy, -oiy), b3 = fmaf(B.w, iy, -oiy);
-            float c2 = fmaf(C.z, iz, -oiz), c3 = fmaf(C.w, iz, -oiz);
-            float n1 = fmaxf(fmaxf(fminf(a2, a3), fminf(b2, b3)), fmaxf(fminf(c2, c3), 0.0f));
-            float f1 = fminf(fminf(fmaxf(a2, a3), fmaxf(b2, b3)), fminf(fmaxf(c2, c3), tfar));
-            bool h0 = n0 * kDn <= f0 * kUp;
-            bool h1 = n1 * kDn <= f1 * kUp;
-            if (h0 && h1) {
-                bool first0 = n0 <= n1;
-                stack[sp++][tid] = first0 ? ch.y : ch.x;
-                node = first0 ? ch.x : ch.y;
-            } else if (h0) {
-                node = ch.x;
-            } else if (h1) {
-                node = ch.y;
+            float k0 = slab(X0.x, X1.x, Y0.x, Y1.x, Z0.x, Z1.x, ix, iy, iz, oix, oiy, oiz, tfar);
+            float k1 = slab(X0.y, X1.y, Y0.y, Y1.y, Z0.y, Z1.y, ix, iy, iz, oix, oiy, oiz, tfar);
+            float k2 = slab(X0.z, X1.z, Y0.z, Y1.z, Z0.z, Z1.z, ix, iy, iz, oix, oiy, oiz, tfar);
+            float k3 = slab(X0.w, X1.w, Y0.w, Y1.w, Z0.w, Z1.w, ix, iy, iz, oix, oiy, oiz, tfar);
+            int c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
+            if (c1 == kEmptyChild) k1 = __builtin_inff();
+            if (c2 == kEmptyChild) k2 = __builtin_inff();
+            if (c3 == kEmptyChild) k3 = __builtin_inff();
+            // sorting network on (entry distance, child)
+            cswap(k0, c0, k1, c1);
+            cswap(k2, c2, k3, c3);
+            cswap(k0, c0, k2, c2);
+            cswap(k1, c1, k3, c3);
+            cswap(k1, c1, k2, c2);
+            if (k3 < __builtin_inff()) push(c3);
+            if (k2 < __builtin_inff()) push(c2);
+            if (k1 < __builtin_inff()) push(c1);
+            if (k0 < __builtin_inff()) {
+                node = c0;
             } else {
                 if (sp == 0) break;
-                node = stack[--sp][tid];
+                node = pop();
             }
         } else {
             const int code = ~node;
@@ -147,7 +177,7 @@ __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_node
                 }
             }
             if (sp == 0) break;
-            node = stack[--sp][tid];
+            node = pop();
         }
     }
     return best;

@@ -17,20 +17,18 @@
 using namespace rt;
 
 static bool inside(const Node& n, int c, const Tri& t) {
-    const float* lo_hi_x = c == 0 ? n.a : n.b;
-    float lx = lo_hi_x[0], hx = lo_hi_x[1], ly = lo_hi_x[2], hy = lo_hi_x[3];
-    float lz = n.c[2 * c], hz = n.c[2 * c + 1];
     for (int v = 0; v < 3; ++v) {
-        double p[3];
-        for (int i = 0; i < 3; ++i) p[i] = t.v0[i] + (v == 1 ? t.e1[i] : v == 2 ? t.e2[i] : 0.0);
-        if (p[0] < lx || p[0] > hx || p[1] < ly || p[1] > hy || p[2] < lz || p[2] > hz) return false;
+        double q[3];
+        for (int i = 0; i < 3; ++i) q[i] = t.v0[i] + (v == 1 ? t.e1[i] : v == 2 ? t.e2[i] : 0.0);
+        if (q[0] < n.bx[0][c] || q[0] > n.bx[1][c] || q[1] < n.bx[2][c] || q[1] > n.bx[3][c] || q[2] < n.bz[0][c] ||
+            q[2] > n.bz[1][c])
+            return false;
     }
     return true;
 }
 
-static void check_subtree(const HostScene& s, int32_t ref, const Node& parent, int c, std::vector<int>& seen,
-                          int depth, int& maxd) {
-    if (depth > maxd) maxd = depth;
+// every triangle of a subtree lies in the box its parent stores for it
+static void check_subtree(const HostScene& s, int32_t ref, const Node& parent, int c, std::vector<int>& seen) {
     if (ref < 0) {
         int code = ~ref, first = code >> kLeafShift, cnt = (code & (kMaxLeaf - 1)) + 1;
         for (int k = first; k < first + cnt; ++k) {
@@ -40,12 +38,17 @@ static void check_subtree(const HostScene& s, int32_t ref, const Node& parent, i
         return;
     }
     const Node& n = s.nodes[ref];
-    for (int cc = 0; cc < 2; ++cc) check_subtree(s, n.child[cc], n, cc, seen, depth + 1, maxd);
+    for (int cc = 0; cc < 4; ++cc) {
+        if (n.child[cc] == kEmptyChild) continue;
+        // the child's own box must contain what its subtree holds
+        check_subtree(s, n.child[cc], n, cc, seen);
+    }
+    (void)parent;
 }
 
-static bool box_hit(const float* lohix, const float* lohiz, const double* o, const double* d, double tmax) {
+static bool box_hit(const Node& n, int c, const double* o, const double* d, double tmax) {
     double t0 = 0.0, t1 = tmax;
-    const float lo[3] = {lohix[0], lohix[2], lohiz[0]}, hi[3] = {lohix[1], lohix[3], lohiz[1]};
+    const float lo[3] = {n.bx[0][c], n.bx[2][c], n.bz[0][c]}, hi[3] = {n.bx[1][c], n.bx[3][c], n.bz[1][c]};
     for (int i = 0; i < 3; ++i) {
         if (d[i] == 0.0) {
             if (o[i] < lo[i] || o[i] > hi[i]) return false;
@@ -78,8 +81,8 @@ static void closest(const HostScene& s, int32_t ref, const double* o, const doub
         return;
     }
     const Node& n = s.nodes[ref];
-    if (box_hit(n.a, n.c, o, d, tbest)) closest(s, n.child[0], o, d, tmin, best, tbest);
-    if (box_hit(n.b, n.c + 2, o, d, tbest)) closest(s, n.child[1], o, d, tmin, best, tbest);
+    for (int c = 0; c < 4; ++c)
+        if (n.child[c] != kEmptyChild && box_hit(n, c, o, d, tbest)) closest(s, n.child[c], o, d, tmin, best, tbest);
 }
 
 int main(int argc, char** argv) {
@@ -104,13 +107,12 @@ int main(int argc, char** argv) {
         return 4;
     }
     std::vector<int> seen(nt, 0);
-    int maxd = 0;
     const Node& root = s.nodes[0];
-    bool root_leaf = root.child[0] == root.child[1] && root.child[0] < 0;
-    for (int c = 0; c < (root_leaf ? 1 : 2); ++c) check_subtree(s, root.child[c], root, c, seen, 1, maxd);
+    for (int c = 0; c < 4; ++c)
+        if (root.child[c] != kEmptyChild) check_subtree(s, root.child[c], root, c, seen);
     for (int64_t k = 0; k < nt; ++k)
         if (seen[k] != 1) { fprintf(stderr, "triangle %ld referenced %d times\n", (long)k, seen[k]); return 3; }
-    if (maxd > kMaxDepth + 1) { fprintf(stderr, "depth %d\n", maxd); return 3; }
+    if (s.stack_need > kStackEntries) { fprintf(stderr, "stack %d\n", s.stack_need); return 3; }
     std::vector<int32_t> hit(nr);
     std::vector<double> th(nr);
     for (int64_t r = 0; r < nr; ++r) {
@@ -125,6 +127,6 @@ int main(int argc, char** argv) {
     fwrite(hit.data(), 4, nr, g);
     fwrite(th.data(), 8, nr, g);
     fclose(g);
-    printf("nodes %zu depth %d faces %d\n", s.nodes.size(), s.depth, s.num_faces);
+    printf("nodes %zu depth %d stack %d faces %d\n", s.nodes.size(), s.depth, s.stack_need, s.num_faces);
     return 0;
 }
