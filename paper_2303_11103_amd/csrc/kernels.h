@@ -176,6 +176,9 @@ hipError_t launch_adam(float* p, const float* g, float* m1, float* m2, int64_t n
 hipError_t launch_sample(const float* maps, const uint8_t* mask, const float* tx, int32_t T, double gx0, double gy0,
                          double gcell, int32_t gnx, int32_t gny, uint64_t seed, uint64_t step, float* v, float* t,
                          float* m, int64_t n, hipStream_t s);
+hipError_t launch_infer_fused(const float* tx, int32_t T, double gx0, double gy0, double gcell, int32_t gnx,
+                              int32_t gny, const float* ff, const MlpNorm& norm, const __bf16* wbf,
+                              const MlpLayout& lay, const float* params, float* out, hipStream_t s);
 hipError_t launch_map_inputs(const float* tx, int32_t T, double gx0, double gy0, double gcell, int32_t gnx,
                              int32_t gny, int64_t row0, int64_t rows, float* v, hipStream_t s);
 

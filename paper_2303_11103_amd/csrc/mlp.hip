@@ -27,15 +27,18 @@ namespace {
 
 constexpr float kGeluC = 0.7978845608028654f;  // sqrt(2 / pi)
 
+// tanh-form GELU written with the logistic function: 0.5 x (1 + tanh u) =
+// x sigma(2u), u = sqrt(2/pi) (x + 0.044715 x^3); hardware exp and reciprocal.
+__device__ __forceinline__ float sigm2(float u) { return __builtin_amdgcn_rcpf(1.0f + __expf(-2.0f * u)); }
 __device__ __forceinline__ float gelu(float x) {
     const float u = kGeluC * (x + 0.044715f * x * x * x);
-    return 0.5f * x * (1.0f + tanhf(u));
+    return x * sigm2(u);
 }
 __device__ __forceinline__ float gelu_grad(float x) {
     const float u = kGeluC * (x + 0.044715f * x * x * x);
-    const float t = tanhf(u);
+    const float s = sigm2(u);
     const float du = kGeluC * (1.0f + 3.0f * 0.044715f * x * x);
-    return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * du;
+    return s + 2.0f * x * s * (1.0f - s) * du;
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -312,6 +315,109 @@ __global__ void map_inputs_kernel(const float* __restrict__ tx, int32_t T, doubl
     v[5 * i + 4] = (float)(gy0 + (iy + 0.5) * gcell);
 }
 
+// Fused inference over map rows (tx, cell): a block of 8 waves owns 128 rows;
+// the activations stay in LDS across the four layers (one 128 x 256 bf16
+// buffer, overwritten in place after a barrier), the weights stream from L2
+// as MFMA B-fragments, wave w computes rows (w / 4) * 64 .. +64 and columns
+// (w % 4) * 64 .. +64 of every layer, and the head reduces each row in four
+// lanes.
+constexpr int kInferRows = 128;
+constexpr int kActLd = 256 + 8;
+
+struct InferArgs {
+    const float* tx;
+    int32_t T;
+    double gx0, gy0, gcell;
+    int32_t gnx, gny;
+    int64_t total;
+    const float* ff;
+    MlpNorm norm;
+    const bf16* wbf;
+    MlpLayout lay;
+    const float* params;
+    float* out;
+};
+
+__global__ __launch_bounds__(512) void infer_fused_kernel(InferArgs a) {
+    __shared__ __attribute__((aligned(16))) bf16 act[kInferRows][kActLd];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int rh = wave >> 2, cq = wave & 3;
+    const int64_t row0 = (int64_t)blockIdx.x * kInferRows;
+    const int64_t cells = (int64_t)a.gnx * a.gny;
+    // Fourier features of the block's rows
+    for (int e = tid; e < kInferRows * kFreq; e += 512) {
+        const int r = e / kFreq, j = e - r * kFreq;
+        int64_t gr = row0 + r;
+        if (gr >= a.total) gr = a.total - 1;
+        const int64_t t = gr / cells, c = gr - t * cells;
+        const int64_t iy = c / a.gnx, ix = c - iy * a.gnx;
+        const float v[5] = {a.tx[3 * t], a.tx[3 * t + 1], a.tx[3 * t + 2], (float)(a.gx0 + (ix + 0.5) * a.gcell),
+                            (float)(a.gy0 + (iy + 0.5) * a.gcell)};
+        float rev = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) rev += a.ff[j * 5 + i] * ((v[i] - a.norm.center[i]) * a.norm.inv_half[i]);
+        float sn, cs;
+        sincospif(2.0f * rev, &sn, &cs);
+        act[r][j] = (bf16)sn;
+        act[r][kFreq + j] = (bf16)cs;
+    }
+    __syncthreads();
+    for (int l = 0; l < 4; ++l) {
+        const int K = a.lay.fan_in[l];
+        const bf16* W = a.wbf + a.lay.bf_off[l];
+        floatx4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        bf16x8 bn[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            bn[j] = *reinterpret_cast<const bf16x8*>(W + (size_t)(cq * 64 + j * 16 + (lane & 15)) * K + (lane >> 4) * 8);
+        for (int k0 = 0; k0 < K; k0 += 32) {
+            bf16x8 bc[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bc[j] = bn[j];
+            if (k0 + 32 < K) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    bn[j] = *reinterpret_cast<const bf16x8*>(W + (size_t)(cq * 64 + j * 16 + (lane & 15)) * K + k0 + 32 +
+                                                             (lane >> 4) * 8);
+            }
+            bf16x8 af[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                af[i] = *reinterpret_cast<const bf16x8*>(&act[rh * 64 + i * 16 + (lane & 15)][k0 + (lane >> 4) * 8]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bc[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();  // every wave has read this layer's input
+        const float* bias = a.params + a.lay.b_off[l];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = cq * 64 + j * 16 + (lane & 15);
+            const float b = bias[col];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) act[rh * 64 + i * 16 + (lane >> 4) * 4 + r][col] = (bf16)gelu(acc[i][j][r] + b);
+        }
+        __syncthreads();
+    }
+    // head: four lanes per row
+    const int r = tid >> 2, part = tid & 3;
+    const float* w5 = a.params + a.lay.w_off[4];
+    float y = 0.0f;
+    for (int k = part * 64; k < part * 64 + 64; ++k) y += w5[k] * (float)act[r][k];
+    y += __shfl_xor(y, 1);
+    y += __shfl_xor(y, 2);
+    const int64_t gr = row0 + r;
+    if (part == 0 && gr < a.total) a.out[gr] = y + a.params[a.lay.b_off[4]];
+}
+
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -382,6 +488,28 @@ hipError_t launch_sample(const float* maps, const uint8_t* mask, const float* tx
                          float* m, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(sample_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, maps, mask, tx, T, gx0, gy0, gcell,
                        gnx, gny, seed, step, v, t, m, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_infer_fused(const float* tx, int32_t T, double gx0, double gy0, double gcell, int32_t gnx,
+                              int32_t gny, const float* ff, const MlpNorm& norm, const __bf16* wbf,
+                              const MlpLayout& lay, const float* params, float* out, hipStream_t s) {
+    InferArgs a;
+    a.tx = tx;
+    a.T = T;
+    a.gx0 = gx0;
+    a.gy0 = gy0;
+    a.gcell = gcell;
+    a.gnx = gnx;
+    a.gny = gny;
+    a.total = (int64_t)T * gnx * gny;
+    a.ff = ff;
+    a.norm = norm;
+    a.wbf = wbf;
+    a.lay = lay;
+    a.params = params;
+    a.out = out;
+    hipLaunchKernelGGL(infer_fused_kernel, dim3(blocks_for(a.total, kInferRows)), dim3(512), 0, s, a);
     return hipGetLastError();
 }
 

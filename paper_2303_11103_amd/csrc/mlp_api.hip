@@ -316,19 +316,8 @@ rt_status rt_mlp_predict_maps(rt_mlp* h, const float* tx, int32_t T, const rt_gr
     if (T < 1 || g->nx < 1 || g->ny < 1) return rt_internal_fail(RT_ERR_ARG, "empty map stack");
     hipStream_t s = rt_internal_stream(h->ctx);
     MLP_HIP(hipSetDevice(rt_internal_device(h->ctx)));
-    const int64_t total = (int64_t)T * g->nx * g->ny;
-    const int64_t B = h->cfg.batch;
-    const rt::MlpLayout& L = h->lay;
-    for (int64_t r0 = 0; r0 < total; r0 += B) {
-        const int64_t rows = std::min(B, total - r0);
-        const int64_t padded = (rows + 127) / 128 * 128;
-        MLP_HIP(rt::launch_map_inputs(tx, T, g->x0, g->y0, g->cell, g->nx, g->ny, r0, rows, h->vin, s));
-        if (padded > rows) MLP_HIP(hipMemsetAsync(h->vin + 5 * rows, 0, (padded - rows) * 5 * sizeof(float), s));
-        rt_status st = forward(h, h->vin, padded, s);
-        if (st != RT_OK) return st;
-        MLP_HIP(rt::launch_head(h->H[3], h->Z[3], h->params + L.w_off[4], h->params + L.b_off[4], nullptr, nullptr,
-                                rows, nullptr, maps + r0, nullptr, nullptr, nullptr, nullptr, s));
-    }
+    MLP_HIP(rt::launch_infer_fused(tx, T, g->x0, g->y0, g->cell, g->nx, g->ny, h->ff, h->norm, h->wbf, h->lay,
+                                   h->params, maps, s));
     return RT_OK;
 }
 

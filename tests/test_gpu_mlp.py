@@ -128,4 +128,4 @@ def test_sample_batch_and_predict_maps():
     pad = (-len(vv)) % 128
     vp = np.concatenate([vv, np.zeros((pad, 5), np.float32)])
     y = m.forward(torch.tensor(vp, device=dev)).cpu().numpy()[:len(vv)]
-    assert np.allclose(pred.reshape(-1), y, atol=1e-5)
+    assert np.allclose(pred.reshape(-1), y, rtol=1e-5, atol=1e-4)
