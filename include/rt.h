@@ -209,6 +209,12 @@ rt_status rt_compute_paths(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* 
                            int32_t ntx, const rt_device* rx, int32_t nrx, float* a, float* T, float* tau,
                            float* aod, float* aoa, int32_t* depth, int32_t* faces, int32_t* num_paths);
 
+/* Received power per (tx, rx), incoherent over the paths (Sec. III-B
+ * optimises an average received power): power [n] (dev) float64 =
+ * sum over slots with depth >= 0 of |a|^2, for a [n][P][2] and depth [n][P]
+ * (dev) as written by rt_compute_paths (n = ntx * nrx). */
+rt_status rt_paths_power(rt_ctx* ctx, const float* a, const int32_t* depth, int64_t n, int32_t P, double* power);
+
 /* Number of distinct candidate face sequences found by the last
  * rt_compute_paths call for its last transmitter. */
 rt_status rt_last_candidate_count(rt_ctx* ctx, int64_t* count);

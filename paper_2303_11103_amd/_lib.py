@@ -80,6 +80,7 @@ SIGNATURES = {
     "rt_profile_read": [P, I32, P, P],
     "rt_compute_paths": [P, P, ctypes.POINTER(rt_trace_params), P, I32, P, I32, P, P, P, P, P, P, P, P],
     "rt_last_candidate_count": [P, ctypes.POINTER(I64)],
+    "rt_paths_power": [P, P, P, I64, I32, P],
     "rt_paths_power_grad": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), P, I32, I32, P, P,
                             P, P],
     "rt_mlp_param_count": [ctypes.POINTER(I64)],

@@ -1,0 +1,47 @@
+"""Differentiable received power: a torch.autograd.Function whose forward
+runs the library's shoot-and-bounce + image-method kernels and whose
+backward runs the hand-written gradient kernel (rt_paths_power_grad) on the
+face sequences kept from the forward pass (geometry and fields are
+recomputed, not stored).
+
+Parameters theta (float64, 2*nm + 5): (eps_r, sigma) of every material, then
+the transmitter's x, y, z, yaw, pitch.  The paper learns materials (Sec.
+III-A) and transmitter orientation (Sec. III-B) from gradients of this kind.
+"""
+from __future__ import annotations
+
+from types import SimpleNamespace
+
+import torch
+
+from . import rt
+
+
+class ReceivedPower(torch.autograd.Function):
+    """P_r = sum_p |a_p|^2 for every receiver r of one transmitter."""
+
+    @staticmethod
+    def forward(fctx, theta, ctx, scene, params, tx, rxs):
+        th = theta.detach().to("cpu", torch.float64).numpy()
+        nm = scene.nm
+        scene.set_materials(th[:2 * nm].reshape(nm, 2))
+        dev = SimpleNamespace(pos=tuple(float(x) for x in th[2 * nm:2 * nm + 3]), yaw=float(th[2 * nm + 3]),
+                              pitch=float(th[2 * nm + 4]), roll=float(tx.roll), pattern=int(tx.pattern))
+        paths = rt.compute_paths(ctx, scene, params, [dev], rxs)
+        power = rt.paths_power(ctx, paths)[0]
+        fctx.save_for_backward(paths["depth"][0].clone(), paths["faces"][0].clone())
+        fctx.rt = (ctx, scene, params, dev, rxs)
+        return power
+
+    @staticmethod
+    def backward(fctx, grad_power):
+        depth, faces = fctx.saved_tensors
+        ctx, scene, params, dev, rxs = fctx.rt
+        g = rt.paths_power_grad(ctx, scene, params, dev, rxs, depth, faces,
+                                grad_power.contiguous().to(torch.float64))
+        return g, None, None, None, None, None
+
+
+def received_power(theta, ctx, scene, params, tx, rxs):
+    """Differentiable P_r (float64 tensor [nrx]) as a function of theta."""
+    return ReceivedPower.apply(theta, ctx, scene, params, tx, rxs)

@@ -577,6 +577,14 @@ rt_status rt_compute_paths(rt_ctx* c, rt_scene* s, const rt_trace_params* p, con
     return RT_OK;
 }
 
+rt_status rt_paths_power(rt_ctx* c, const float* a, const int32_t* depth, int64_t n, int32_t P, double* power) {
+    if (!c || !a || !depth || !power) return fail(RT_ERR_ARG, "NULL argument");
+    if (n < 0 || P < 1 || P > 256) return fail(RT_ERR_ARG, "n must be >= 0 and P in [1, 256]");
+    RT_HIP(hipSetDevice(c->device));
+    RT_HIP(rt::launch_paths_power(a, depth, n, P, power, c->stream));
+    return RT_OK;
+}
+
 rt_status rt_last_candidate_count(rt_ctx* c, int64_t* count) {
     if (!c || !count) return fail(RT_ERR_ARG, "NULL argument");
     *count = c->last_candidates;

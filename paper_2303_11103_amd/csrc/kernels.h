@@ -105,6 +105,7 @@ struct PathArgs {
     int32_t fd;       // faces stride = max(max_depth, 1)
 };
 
+hipError_t launch_paths_power(const float* a, const int32_t* depth, int64_t n, int P, double* power, hipStream_t s);
 hipError_t launch_extract_candidates(const uint64_t* table, uint64_t cap, int32_t max_depth, Cand* out,
                                      uint32_t* count, uint32_t max_out, hipStream_t s);
 hipError_t launch_image_paths(const PathArgs& a, const MatTable& mats, int64_t max_items, hipStream_t s);

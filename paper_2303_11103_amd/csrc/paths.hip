@@ -263,7 +263,28 @@ __global__ void sort_paths_kernel(PathArgs a, int32_t nrx, float* a_out, float* 
     }
 }
 
+// P[r] = sum over the valid slots of |a|^2 (fp64 accumulation of the fp32 a).
+__global__ void paths_power_kernel(const float* __restrict__ a, const int32_t* __restrict__ depth, int64_t n, int P,
+                                   double* __restrict__ power) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double acc = 0.0;
+    for (int j = 0; j < P; ++j) {
+        const int64_t at = r * P + j;
+        if (depth[at] < 0) continue;
+        const double re = a[2 * at], im = a[2 * at + 1];
+        acc += re * re + im * im;
+    }
+    power[r] = acc;
+}
+
 }  // namespace
+
+hipError_t launch_paths_power(const float* a, const int32_t* depth, int64_t n, int P, double* power, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(paths_power_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, depth, n, P, power);
+    return hipGetLastError();
+}
 
 hipError_t launch_extract_candidates(const uint64_t* table, uint64_t cap, int32_t max_depth, Cand* out,
                                      uint32_t* count, uint32_t max_out, hipStream_t s) {

@@ -193,6 +193,16 @@ def compute_paths(ctx: Context, scene: Scene, params: TraceParams, txs, rxs):
     return o
 
 
+def paths_power(ctx: Context, paths):
+    """Received power per (tx, rx): float64 tensor [ntx, nrx] = sum |a|^2 over valid paths."""
+    a, depth = paths["a"], paths["depth"]
+    ntx, nrx, P = depth.shape
+    out = torch.empty((ntx, nrx), dtype=torch.float64, device=a.device)
+    ctx._bind_stream()
+    check(lib.rt_paths_power(ctx.h, _ptr(a), _ptr(depth), ntx * nrx, P, _ptr(out)))
+    return out
+
+
 def last_candidate_count(ctx: Context) -> int:
     n = ctypes.c_int64()
     check(lib.rt_last_candidate_count(ctx.h, ctypes.byref(n)))

@@ -1,0 +1,84 @@
+"""The torch.autograd.Function around the path kernels: its gradient equals
+FP64 central differences of the oracle, and gradient descent through it
+recovers radio materials from received powers (a synthetic analogue of the
+paper's learning of radio materials, Sec. III-A, which starts from
+sigma = 0.1 S/m and eps_r = 3.0)."""
+import numpy as np
+import pytest
+import torch
+
+import scenegen as sg
+from oracle import geom, grad as ograd
+
+from gpu_common import ctx, lib, params, requires_gpu, scene
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+def _theta(w, mats):
+    tx = w.tx[0]
+    return torch.tensor(list(np.asarray(mats, dtype=np.float64).reshape(-1)) + list(tx.pos) + [tx.yaw, tx.pitch],
+                        dtype=torch.float64, device="cuda", requires_grad=True)
+
+
+def test_autograd_loss_gradient_matches_finite_differences():
+    lib()
+    from paper_2303_11103_amd.autograd import received_power
+    w = sg.diff_workload(num_rays=100_000)
+    w.rx = w.rx[:40]
+    p = params(w, max_paths_per_rx=64)
+    sc = scene(w.scene)
+    theta = _theta(w, w.scene.materials)
+    P = received_power(theta, ctx(), sc, p, w.tx[0], w.rx)
+    used = P > 0
+    L = torch.mean(10 * torch.log10(P[used]))
+    L.backward()
+    g_gpu = theta.grad.cpu().numpy()
+    # frozen path sets from the GPU forward pass, FD by the oracle over the same receivers
+    m = lib()
+    o = m.compute_paths(ctx(), sc, p, w.tx, w.rx)
+    depth = o["depth"][0].cpu().numpy()
+    faces = o["faces"][0].cpu().numpy()
+    seqs = [[tuple(int(f) for f in faces[r, j, :depth[r, j]]) for j in range(depth.shape[1]) if depth[r, j] >= 0]
+            for r in range(len(w.rx))]
+    g = geom.Geometry(w.scene)
+    fd, used_o, unstable = ograd.fd_gradient(g, w.tx[0], w.rx, seqs, mask=used.cpu().numpy())
+    assert not unstable.any()
+    scale = np.abs(fd)
+    big = scale > 1e-6 * scale.max()
+    assert np.max(np.abs(g_gpu - fd)[big] / scale[big]) < 1e-3, (g_gpu, fd)
+
+
+def test_material_recovery_by_gradient_descent():
+    lib()
+    from paper_2303_11103_amd.autograd import received_power
+    w = sg.diff_workload(num_rays=200_000)
+    w.tx[0].pattern = sg.PATTERN_ISO
+    w.tx[0].pitch = 0.0
+    p = params(w, max_paths_per_rx=64)
+    sc = scene(w.scene)
+    true = np.asarray(w.scene.materials, dtype=np.float64)
+    with torch.no_grad():
+        P_true = received_power(_theta(w, true), ctx(), sc, p, w.tx[0], w.rx)
+    used = P_true > 0
+    target = 10 * torch.log10(P_true[used])
+    # trainable materials from the paper's initial values
+    mats = np.array([[3.0, 0.1], [3.0, 0.1]])
+    lr = np.array([0.05, 0.01])
+    m1 = np.zeros_like(mats)
+    m2 = np.zeros_like(mats)
+    losses = []
+    for it in range(1, 151):
+        theta = _theta(w, mats)
+        P = received_power(theta, ctx(), sc, p, w.tx[0], w.rx)
+        loss = torch.mean((10 * torch.log10(P[used]) - target) ** 2)
+        loss.backward()
+        gm = theta.grad[:4].cpu().numpy().reshape(2, 2)
+        losses.append(float(loss))
+        m1 = 0.9 * m1 + 0.1 * gm
+        m2 = 0.999 * m2 + 0.001 * gm * gm
+        mats = mats - lr * (m1 / (1 - 0.9 ** it)) / (np.sqrt(m2 / (1 - 0.999 ** it)) + 1e-12)
+        mats = np.maximum(mats, [1.0, 0.0])
+    sc.set_materials(true)  # leave the shared scene as it was
+    assert losses[-1] < 1e-2 * losses[0], (losses[0], losses[-1])
+    assert np.all(np.abs(mats[:, 0] - true[:, 0]) / true[:, 0] < 0.05), mats
