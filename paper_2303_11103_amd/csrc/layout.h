@@ -25,8 +25,11 @@ constexpr int32_t kEmptyChild = (int32_t)0x80000000;
 constexpr int kLeafShift = 5;
 constexpr int kMaxLeaf = 1 << kLeafShift;  // 32
 constexpr int kMaxDepth = 30;              // binary build tree depth bound
-constexpr int kStackEntries = 32;          // traversal stack entries per lane kept in LDS
-constexpr int kStackOverflow = 32;         // further entries per lane in private memory (deep trees)
+#ifndef RT_LDS_STACK
+#define RT_LDS_STACK 32
+#endif
+constexpr int kStackEntries = RT_LDS_STACK;         // traversal stack entries per lane kept in LDS
+constexpr int kStackOverflow = 64 - RT_LDS_STACK;   // further entries per lane in private memory
 
 inline int32_t make_leaf(int32_t first, int32_t count) { return ~((first << kLeafShift) | (count - 1)); }
 

@@ -384,7 +384,7 @@ int build_scene(const float* V, int64_t nv, const int32_t* F, int64_t nt, const 
             need[h] = (n - 1) + deepest;
         }
         out.stack_need = need[0] + 1;
-        if (out.stack_need > kStackEntries + kStackOverflow) {
+        if (out.stack_need > kStackEntries + kStackOverflow) {  // 64 entries in all
             err = "BVH needs a deeper traversal stack than " + std::to_string(kStackEntries + kStackOverflow);
             return -1;
         }

@@ -120,8 +120,11 @@ __device__ __forceinline__ void store_ray(RayState* __restrict__ p, const Ray& r
 }
 
 template <int MODE, bool FIRST>
-__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void sbr_bounce(SbrArgs a,
-                                                                                                    MatTable mats) {
+#ifndef RT_TRACE_WAVES_PER_EU
+#define RT_TRACE_WAVES_PER_EU 4
+#endif
+__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(RT_TRACE_WAVES_PER_EU)))
+void sbr_bounce(SbrArgs a, MatTable mats) {
     __shared__ int32_t stack[kStack][kTraceBlock];
     __shared__ Node lds_nodes[kLdsNodes];
     const int n_lds = stage_nodes(a.sc, lds_nodes);
