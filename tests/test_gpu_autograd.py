@@ -64,7 +64,8 @@ def _fit(w, sc, p, start, lr, steps, used, target, train_mask):
         losses.append(float(loss.detach()))
         m1 = 0.9 * m1 + 0.1 * gm
         m2 = 0.999 * m2 + 0.001 * gm * gm
-        mats = mats - lr * (m1 / (1 - 0.9 ** it)) / (np.sqrt(m2 / (1 - 0.999 ** it)) + 1e-12)
+        step = lr * 0.5 * (1 + np.cos(np.pi * (it - 1) / steps))  # cosine decay
+        mats = mats - step * (m1 / (1 - 0.9 ** it)) / (np.sqrt(m2 / (1 - 0.999 ** it)) + 1e-12)
         mats = np.maximum(mats, [1.0, 0.0])
     return mats, losses
 
@@ -85,7 +86,7 @@ def test_material_recovery_by_gradient_descent():
     try:
         # received powers alone do not separate eps_r from sigma (both set |r|): with sigma
         # known, eps_r of both materials is recovered from the paper's initial value 3.0
-        mats, losses = _fit(w, sc, p, [[3.0, true[0, 1]], [3.0, true[1, 1]]], np.array([0.05, 0.0]), 150, used,
+        mats, losses = _fit(w, sc, p, [[3.0, true[0, 1]], [3.0, true[1, 1]]], np.array([0.1, 0.0]), 200, used,
                             target, np.array([1.0, 0.0]))
         assert losses[-1] < 1e-3 * losses[0], (losses[0], losses[-1])
         assert np.all(np.abs(mats[:, 0] - true[:, 0]) / true[:, 0] < 0.02), mats
