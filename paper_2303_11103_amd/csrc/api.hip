@@ -60,7 +60,7 @@ struct rt_ctx {
     hipStream_t stream = nullptr;
     int num_cu = 256;
     DevBuf queue[2];
-    DevBuf counters;   // uint32 [64]
+    DevBuf counters;   // uint32 [depth + 1][kQueueRegions] queue region counts
     DevBuf table;      // candidate prefix table
     DevBuf cands;
     DevBuf rx;         // double [nrx][3]
@@ -190,9 +190,11 @@ rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_dev
                   uint64_t* work = nullptr) {
     const int64_t count = traced_count(p);
     const int64_t chunk = std::min(count, kChunk);
-    RT_HIP(ensure(c->queue[0], (size_t)chunk * sizeof(rt::RayState)));
-    RT_HIP(ensure(c->queue[1], (size_t)chunk * sizeof(rt::RayState)));
-    RT_HIP(ensure(c->counters, 64 * sizeof(uint32_t)));
+    const int64_t region_cap = rt::sbr_region_capacity(chunk, grid_for(c));
+    const size_t qbytes = (size_t)rt::kQueueRegions * region_cap * sizeof(rt::RayState);
+    RT_HIP(ensure(c->queue[0], qbytes));
+    RT_HIP(ensure(c->queue[1], qbytes));
+    RT_HIP(ensure(c->counters, (size_t)(p->max_depth + 1) * rt::kQueueRegions * sizeof(uint32_t)));
     rt::MatTable mats = make_mats(s, p->freq_hz);
     rt::SbrArgs a{};
     a.sc = s->dev;
@@ -232,13 +234,14 @@ rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_dev
     for (int64_t pos0 = 0; pos0 < count; pos0 += chunk) {
         a.pos0 = pos0;
         a.chunk = std::min(chunk, count - pos0);
-        RT_HIP(hipMemsetAsync(cnt, 0, 64 * sizeof(uint32_t), c->stream));
+        RT_HIP(hipMemsetAsync(cnt, 0, (size_t)(p->max_depth + 1) * rt::kQueueRegions * sizeof(uint32_t), c->stream));
         for (int k = 0; k <= p->max_depth; ++k) {
             a.depth = k;
             a.in = k ? (const rt::RayState*)c->queue[(k - 1) & 1].p : nullptr;
-            a.in_count = k ? cnt + (k - 1) : nullptr;
+            a.in_count = k ? cnt + (size_t)(k - 1) * rt::kQueueRegions : nullptr;
             a.out = (rt::RayState*)c->queue[k & 1].p;
-            a.out_count = cnt + k;
+            a.out_count = cnt + (size_t)k * rt::kQueueRegions;
+            a.region_cap = region_cap;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (c->profiling) {
                 while (c->ev_pool.size() < c->ev_used + 2) {
@@ -500,7 +503,6 @@ rt_status rt_compute_paths(rt_ctx* c, rt_scene* s, const rt_trace_params* p, con
     uint64_t cap = 1024;
     while (cap < want && cap < (1ull << 26)) cap <<= 1;
     RT_HIP(ensure(c->table, cap * sizeof(uint64_t)));
-    RT_HIP(ensure(c->counters, 64 * sizeof(uint32_t)));
     const uint32_t max_cand = (uint32_t)std::min<uint64_t>(cap, 1ull << 24);
     RT_HIP(ensure(c->cands, (size_t)max_cand * sizeof(rt::Cand)));
     RT_HIP(ensure(c->rx, (size_t)nrx * 3 * sizeof(double)));

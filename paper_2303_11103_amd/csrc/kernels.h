@@ -21,6 +21,7 @@ struct alignas(16) RayState {
 static_assert(sizeof(RayState) == 96, "ray state size");
 
 constexpr uint64_t kEmptyKey = ~0ull;
+constexpr int kQueueRegions = 64;
 
 struct DevScene {
     const Node* nodes;
@@ -54,10 +55,14 @@ struct SbrArgs {
     uint32_t* hits;
     // queues
     int32_t depth, max_depth;
+    // The queues are split into kQueueRegions regions of region_cap rays; a
+    // wave appends its survivors to region (wave % kQueueRegions) through
+    // that region's counter, which spreads the queue atomics over 64 addresses.
     const RayState* in;
-    const uint32_t* in_count;
+    const uint32_t* in_count;   // [kQueueRegions] counts of the input regions
     RayState* out;
-    uint32_t* out_count;
+    uint32_t* out_count;        // [kQueueRegions]
+    int64_t region_cap;
     uint64_t* stats;    // [max_depth + 1] traced rays per depth (nullable)
     uint64_t* work;     // stats mode: [3][max_depth + 1] rays, inner-node visits, triangle tests
     // record mode
@@ -71,6 +76,10 @@ struct SbrArgs {
 
 enum : int { kModeCoverage = 1, kModeRecord = 2, kModeCandidates = 4, kModeStats = 8 };
 
+// Rays one queue region must hold for a bounce launch of `grid` blocks over
+// at most `chunk` rays: the waves of a region (every kQueueRegions-th) times
+// their grid-stride iterations times 64 lanes.
+int64_t sbr_region_capacity(int64_t chunk, int grid);
 hipError_t launch_sbr_bounce(const SbrArgs& a, const MatTable& mats, int mode, int grid, hipStream_t s);
 hipError_t launch_fib_dirs(int64_t N, int64_t begin, int64_t stride, int64_t count, double* out, hipStream_t s);
 hipError_t launch_finalize_db(const float* gain, float* db, int64_t n, hipStream_t s);

@@ -131,12 +131,35 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * kTraceBlock + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * kTraceBlock) >> 6;
-    const int64_t count = FIRST ? a.chunk : (int64_t)(*a.in_count);
+    // input regions: lane r of every wave holds the inclusive prefix of the
+    // region counts up to r (registers, so no LDS is taken from the stack)
+    uint32_t incl = 0;
+    if (!FIRST) {
+        incl = a.in_count[lane];
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t v = __shfl_up(incl, off);
+            if (lane >= off) incl += v;
+        }
+    }
+    const int64_t count = FIRST ? a.chunk : (int64_t)__shfl(incl, 63);
     if (a.stats && blockIdx.x == 0 && threadIdx.x == 0)
         atomicAdd((unsigned long long*)&a.stats[a.depth], (unsigned long long)count);
     for (int64_t base = wave * 64; base < count; base += nwaves * 64) {
         const int64_t item = base + lane;
         const bool active = item < count;
+        // region of item: the number of regions whose inclusive prefix is <= item
+        // (a branch-free binary search over the lanes, taken by the whole wave)
+        int region_in = 0;
+        int64_t region_off = 0;
+        if (!FIRST) {
+            for (int s = 32; s >= 1; s >>= 1) {
+                const uint32_t v = __shfl(incl, region_in + s - 1);
+                if ((int64_t)v <= item) region_in += s;
+            }
+            const uint32_t prev = __shfl(incl, region_in > 0 ? region_in - 1 : 0);
+            const uint32_t start = region_in > 0 ? prev : 0u;
+            region_off = item - (int64_t)start;
+        }
         Ray st;
         bool alive = false;
         if (active) {
@@ -155,7 +178,7 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
                 st.prefix = -1;
                 st.ray = (int32_t)pos;
             } else {
-                load_ray(a.in + item, st);
+                load_ray(a.in + region_in * a.region_cap + region_off, st);
             }
             const d3 o = st.o;
             const d3 d = st.d;
@@ -232,9 +255,10 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
         const uint64_t m = __ballot(alive);
         if (m) {
             uint32_t b = 0;
-            if (lane == 0) b = atomicAdd(a.out_count, (uint32_t)__popcll(m));
+            const int region = (int)(wave % kQueueRegions);
+            if (lane == 0) b = atomicAdd(a.out_count + region, (uint32_t)__popcll(m));
             b = __shfl(b, 0);
-            if (alive) store_ray(a.out + b + __popcll(m & ((1ull << lane) - 1ull)), st);
+            if (alive) store_ray(a.out + region * a.region_cap + b + __popcll(m & ((1ull << lane) - 1ull)), st);
         }
     }
 }
@@ -265,6 +289,12 @@ hipError_t launch_mode(const SbrArgs& a, const MatTable& mats, int grid, hipStre
 }
 
 }  // namespace
+
+int64_t sbr_region_capacity(int64_t chunk, int grid) {
+    const int64_t nwaves = (int64_t)grid * (kTraceBlock / 64);
+    const int64_t iters = (chunk + nwaves * 64 - 1) / (nwaves * 64);
+    return ((nwaves + kQueueRegions - 1) / kQueueRegions) * iters * 64;
+}
 
 hipError_t launch_sbr_bounce(const SbrArgs& a, const MatTable& mats, int mode, int grid, hipStream_t s) {
     switch (mode) {
