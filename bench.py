@@ -9,9 +9,10 @@ Fibonacci ray generation, closest-hit BVH traversal, coverage deposit,
 Fresnel reflection and queue compaction for every bounce, then the dB map.
 
 Prints one JSON line: value = ray-bounces (closest-hit queries, counted on
-the device) per second; roofline of the shoot-and-bounce kernel family
+the device) per second; roofline of the depth-0 shoot-and-bounce launch
 (algorithmic FLOPs from counted BVH node visits and triangle tests, divided
-by the kernels' HIP-event durations); the FP64 CPU oracle timed on a
+by its HIP-event duration on the library's stream; all launches reported
+beside it); the FP64 CPU oracle timed on a
 bounded ray sample of the same workload; and side measurements of the paths
 (image method) and gradient kernels.
 
@@ -50,6 +51,39 @@ FLOP_RAYGEN = 70.0
 # FMA = 2 flops -> 78.6 TFLOP/s for fp64 and for non-packed fp32 (the build
 # disables packed fp32).
 PEAK_ALU_TFLOPS = 78.6
+COPY_PROBE_BYTES = 256 << 20
+# Sources that make up the shoot-and-bounce kernel: HBM traffic measured with
+# counters is reported only while they are unchanged.
+KERNEL_SOURCES = ["paper_2303_11103_amd/csrc/" + f for f in
+                  ("trace.hip", "traverse.h", "device.h", "kernels.h", "layout.h", "api.hip")]
+TRAFFIC_PROFILE = "profiles/sbr_bounce_urban_hbm_traffic.md"
+
+
+def kernel_sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per depth-0 launch from the committed counter profile (FETCH_SIZE
+    + WRITE_SIZE, scaled by the copy probe), or None when the profile is missing
+    or was taken on other kernel sources."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("traffic:"):
+            for kv in line[len("traffic:"):].split():
+                k, v = kv.split("=")
+                vals[k] = v
+    if vals.get("sources") != kernel_sources_digest() or "bytes_per_launch" not in vals:
+        return None
+    return float(vals["bytes_per_launch"])
 
 
 def log(msg):
@@ -89,6 +123,9 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate measurement")
     ap.add_argument("--surrogate-steps", type=int, default=3000)
     ap.add_argument("--surrogate-tx", type=int, default=4096)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed region, copy %d MiB once (reference kernel for HBM counters)" % (
+                        256))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the shoot-and-bounce workload of one transmitter runs on a single "
@@ -161,29 +198,45 @@ def main():
     flops_depth = FLOP_NODE * wk[1] + FLOP_TRI * wk[2] + FLOP_DEPOSIT * wk[0] + FLOP_REFLECT * survivors
     flops_depth[0] += FLOP_RAYGEN * wk[0][0]
     k_ms = np.asarray(list(kms)) / np.maximum(1, np.asarray(list(launches)))  # per launch, per depth
-    per_launch_flops = flops_depth.sum()
     per_step_kernel_ms = float(k_ms.sum())
-    achieved = per_launch_flops / (per_step_kernel_ms / 1e3) / 1e12
+    achieved_all = flops_depth.sum() / (per_step_kernel_ms / 1e3) / 1e12
+    # dominant kernel: the depth-0 launch (sbr_bounce<1, true>: ray generation,
+    # first closest hit, deposit, reflection), the longest single launch of a step
     dom = int(np.argmax(k_ms))
+    achieved = flops_depth[0] / (k_ms[0] / 1e3) / 1e12
     roofline = {
         "bound": "alu",
         "achieved": round(float(achieved), 3),
         "peak": PEAK_ALU_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(float(achieved / PEAK_ALU_TFLOPS), 4),
-        "traffic": None,
-        "kernel": "sbr_bounce (all %d bounce launches of a step)" % nd,
-        "kernel_ms_per_depth": [round(float(x), 4) for x in k_ms],
-        "dominant_launch": "depth %d, %.3f ms" % (dom, float(k_ms[dom])),
+        "traffic": traffic_per_launch(),
+        "kernel": "sbr_bounce<coverage, first bounce> (depth-0 launch: %d rays)" % int(wk[0][0]),
+        "kernel_ms": round(float(k_ms[0]), 4),
+        "flop_per_launch": float(flops_depth[0]),
+        "longest_launch": "depth %d, %.3f ms" % (dom, float(k_ms[dom])),
+        "all_launches": {"kernel_ms_per_depth": [round(float(x), 4) for x in k_ms],
+                         "achieved": round(float(achieved_all), 3),
+                         "frac": round(float(achieved_all / PEAK_ALU_TFLOPS), 4)},
         "node_visits_per_ray_bounce": round(float(wk[1].sum() / wk[0].sum()), 2),
         "tri_tests_per_ray_bounce": round(float(wk[2].sum() / wk[0].sum()), 2),
-        "flop_per_ray_bounce": round(float(per_launch_flops / wk[0].sum()), 1),
+        "flop_per_ray_bounce": round(float(flops_depth.sum() / wk[0].sum()), 1),
         "rays_per_depth": [int(x) for x in wk[0]],
         "node_visits_per_depth": [int(x) for x in wk[1]],
         "tri_tests_per_depth": [int(x) for x in wk[2]],
     }
-    log("bench: kernels %.3f ms/step, %.2f TFLOP/s algorithmic (%.1f%% of %.1f)" % (
-        per_step_kernel_ms, achieved, 100 * achieved / PEAK_ALU_TFLOPS, PEAK_ALU_TFLOPS))
+    log("bench: depth-0 launch %.4f ms, %.2f TFLOP/s algorithmic (%.1f%% of %.1f); all launches %.3f ms/step, "
+        "%.2f TFLOP/s" % (k_ms[0], achieved, 100 * achieved / PEAK_ALU_TFLOPS, PEAK_ALU_TFLOPS,
+                          per_step_kernel_ms, achieved_all))
+    if args.copy_probe:
+        # a plain device copy of known size: the HBM counters of the profile runs
+        # are scaled by what they read for it
+        src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     result = {
         "metric": BJ_METRIC,
