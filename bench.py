@@ -121,7 +121,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the paths/gradient side measurements")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate measurement")
-    ap.add_argument("--surrogate-steps", type=int, default=3000)
+    ap.add_argument("--surrogate-steps", type=int, default=20000)
     ap.add_argument("--surrogate-tx", type=int, default=4096)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy %d MiB once (reference kernel for HBM counters)" % (
@@ -313,7 +313,7 @@ def extras(rt, ctx, scene, w, torch):
     return res
 
 
-def surrogate_bench(rt, ctx, scene, w, torch, steps=3000, n_tx=4096, seed=3):
+def surrogate_bench(rt, ctx, scene, w, torch, steps=20000, n_tx=4096, seed=3):
     """Learned surrogate on the urban scene: ray-traced maps (1e7 rays, depth 3,
     200x200 cells of 2 m) for transmitters uniform over the rooftops, split
     7/8 train, 1/16 validation, 1/16 test; trained with the library's MFMA
@@ -340,7 +340,10 @@ def surrogate_bench(rt, ctx, scene, w, torch, steps=3000, n_tx=4096, seed=3):
     maps = torch.where(mask.bool(), maps, torch.zeros_like(maps))
     lo = np.array([-200.0, -200.0, 10.0, -200.0, -200.0])
     hi = np.array([200.0, 200.0, 65.0, 200.0, 200.0])
-    m = S.MLP(ctx, batch=32768, ff_scale=4.0, seed=seed, center=(lo + hi) / 2, half=(hi - lo) / 2)
+    # low Fourier frequencies on the transmitter inputs, higher on the cell inputs;
+    # the network learns the residual over the free-space gain of each link
+    m = S.MLP(ctx, batch=32768, ff_scale=1.0, ff_scale_cell=4.0, seed=seed, center=(lo + hi) / 2, half=(hi - lo) / 2,
+              prior=(w.scene.freq_hz, grid.z))
     rep = S.train(m, maps[tr].contiguous(), mask[tr].contiguous(), tx[tr].contiguous(), grid, steps=steps, lr=2e-3,
                   seed=seed)
     pv = m.predict_maps(tx[va], grid)

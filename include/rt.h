@@ -239,9 +239,14 @@ rt_status rt_paths_power_grad(rt_ctx* ctx, rt_scene* scene, const rt_trace_param
  * models, Sec. I, and closes Sec. III-A with learning as a calibration
  * tool; it specifies no network).  Function: inputs v = (tx x, y, z, cell
  * x, y), normalised as (v - in_center) / in_half; Fourier features
- * [sin 2 pi B v, cos 2 pi B v] with B (64 x 5) drawn N(0, ff_scale^2);
- * 4 hidden layers of 256 with the tanh-form GELU; linear head giving the
- * path gain in dB.  Parameters (fp32, rt_mlp_param_count() of them):
+ * [sin 2 pi B v, cos 2 pi B v] with B (64 x 5) drawn N(0, s^2), s =
+ * ff_scale on the transmitter columns and ff_scale_cell on the cell columns;
+ * 4 hidden layers of 256 with the tanh-form GELU; linear head.  The output
+ * (path gain in dB) is the head plus, when prior_freq_hz > 0, the free-space
+ * gain of the link, 20 log10(c0 / (4 pi f d)) with d the distance from the
+ * transmitter to (cell x, cell y, prior_rx_z) (the Friis gain of an
+ * isotropic pair, Sec. II-A); the network then learns the residual.
+ * Parameters (fp32, rt_mlp_param_count() of them):
  * W1[256][128] b1[256] W2[256][256] b2 W3 b3 W4 b4 w5[256] b5[1].
  * Matrix products run on bf16 MFMA with fp32 accumulation; training uses
  * Adam (beta 0.9/0.999, eps 1e-8) on fp32 master weights and the masked
@@ -249,10 +254,13 @@ rt_status rt_paths_power_grad(rt_ctx* ctx, rt_scene* scene, const rt_trace_param
 typedef struct rt_mlp rt_mlp;
 typedef struct {
     int32_t batch;        /* rows per call: multiple of 1024 (scratch is sized for it) */
-    float ff_scale;       /* standard deviation of the Fourier matrix entries */
+    float ff_scale;       /* std of the Fourier entries on the transmitter inputs (x, y, z) */
     uint64_t seed;        /* initialisation seed */
     float in_center[5];
     float in_half[5];
+    float ff_scale_cell;  /* std of the Fourier entries on the cell inputs (x, y); 0 = ff_scale */
+    float prior_rx_z;     /* receiver height of the free-space prior [m] */
+    double prior_freq_hz; /* carrier of the free-space prior [Hz]; 0 = no prior */
 } rt_mlp_config;
 
 rt_status rt_mlp_param_count(int64_t* n);
@@ -274,13 +282,20 @@ rt_status rt_mlp_grad(rt_mlp* mlp, const float* v, const float* t, const float* 
 /* One Adam step with learning rate lr on the batch; loss (dev, nullable). */
 rt_status rt_mlp_train_step(rt_mlp* mlp, const float* v, const float* t, const float* m, int64_t n, float lr,
                             float* loss);
+/* Positions i < n (ascending) with mask[i] != 0 of a byte mask (dev, n <
+ * 2^32) into index (dev, uint32, capacity entries); *count (host) receives
+ * the number of such positions.  RT_ERR_CAPACITY (and nothing written) when
+ * it exceeds capacity.  Synchronises the context's stream. */
+rt_status rt_mlp_valid_index(rt_mlp* mlp, const uint8_t* mask, int64_t n, uint32_t* index, int64_t capacity,
+                             int64_t* count);
 /* Draw n training rows from a stack of T coverage maps (dev): maps [T][ny][nx]
- * in dB, mask [T][ny][nx] (1 = usable cell), tx [T][3]; rows are taken by a
- * counter-based hash of (seed, step, row) among masked-in cells (up to 8
- * draws, else the row gets m = 0).  Writes v [n][5], t [n], m [n] (dev). */
-rt_status rt_mlp_sample_batch(rt_mlp* mlp, const float* maps, const uint8_t* mask, const float* tx, int32_t T,
-                              const rt_grid* grid, uint64_t seed, uint64_t step, float* v, float* t, float* m,
-                              int64_t n);
+ * in dB, tx [T][3], and the usable cells as flat positions into maps (index
+ * [count], from rt_mlp_valid_index over the cell mask); row i takes index
+ * entry (h mod count), h a counter-based hash of (seed, step, i).  Writes v
+ * [n][5], t [n] and m [n] = 1 (dev). */
+rt_status rt_mlp_sample_batch(rt_mlp* mlp, const float* maps, const uint32_t* index, int64_t count, const float* tx,
+                              int32_t T, const rt_grid* grid, uint64_t seed, uint64_t step, float* v, float* t,
+                              float* m, int64_t n);
 /* Predicted maps [T][ny][nx] (dev, dB) for transmitters tx [T][3] (dev) on the
  * grid's cell centres. */
 rt_status rt_mlp_predict_maps(rt_mlp* mlp, const float* tx, int32_t T, const rt_grid* grid, float* maps);

@@ -12,7 +12,9 @@ function in bf16/fp32):
 * Fourier features gamma(v) = [sin(2 pi B v), cos(2 pi B v)], B in R^{64x5};
 * 4 hidden layers of width 256, h_l = gelu(W_l h_{l-1} + b_l), with the tanh
   form gelu(x) = x / 2 (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3)));
-* linear head y = w_5 . h_4 + b_5 (path gain in dB);
+* linear head y = w_5 . h_4 + b_5, plus optionally the free-space gain of the
+  link, 20 log10(c0 / (4 pi f d)) (Friis with isotropic antennas, Sec. II-A),
+  so that the network learns the residual (path gain in dB);
 * loss = sum_i m_i (y_i - t_i)^2 / sum_i m_i (mask m_i in {0, 1}).
 
 Parameter vector layout (float32 on the GPU, float64 here):
@@ -21,6 +23,8 @@ W1[256][128], b1[256], W2[256][256], b2, W3, b3, W4, b4, w5[256], b5[1].
 from __future__ import annotations
 
 import numpy as np
+
+from .consts import C0
 
 N_IN = 5
 N_FREQ = 64
@@ -70,8 +74,17 @@ def features(v, Bf):
     return np.concatenate([np.sin(proj), np.cos(proj)], axis=1)
 
 
-def forward(theta, v, Bf, feats=None):
-    """Prediction and the cache for ``backward``."""
+def free_space_db(points, freq_hz, rx_z):
+    """Free-space gain [dB] from the transmitter (points[:, 0:3]) to the cell
+    centre (points[:, 3], points[:, 4], rx_z): 20 log10(lambda / (4 pi d))."""
+    p = np.asarray(points, dtype=np.float64)
+    d = np.sqrt((p[:, 3] - p[:, 0]) ** 2 + (p[:, 4] - p[:, 1]) ** 2 + (rx_z - p[:, 2]) ** 2)
+    return 20.0 * np.log10(C0 / freq_hz / (4.0 * np.pi * d))
+
+
+def forward(theta, v, Bf, feats=None, prior_db=None):
+    """Prediction and the cache for ``backward``; prior_db (per row, e.g. from
+    ``free_space_db``) is added to the head's output."""
     layers = unpack(theta)
     h = features(v, Bf) if feats is None else np.asarray(feats, dtype=np.float64)
     cache = [h]
@@ -81,6 +94,8 @@ def forward(theta, v, Bf, feats=None):
         cache.append((z, h))
     w5, b5 = layers[-1]
     y = h @ w5[0] + b5[0]
+    if prior_db is not None:
+        y = y + np.asarray(prior_db, dtype=np.float64)
     return y, cache
 
 

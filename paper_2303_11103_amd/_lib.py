@@ -45,7 +45,8 @@ class rt_grid(ctypes.Structure):
 
 class rt_mlp_config(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int32), ("ff_scale", ctypes.c_float), ("seed", ctypes.c_uint64),
-                ("in_center", ctypes.c_float * 5), ("in_half", ctypes.c_float * 5)]
+                ("in_center", ctypes.c_float * 5), ("in_half", ctypes.c_float * 5), ("ff_scale_cell", ctypes.c_float),
+                ("prior_rx_z", ctypes.c_float), ("prior_freq_hz", ctypes.c_double)]
 
 
 class rt_scene_info_t(ctypes.Structure):
@@ -91,7 +92,9 @@ SIGNATURES = {
     "rt_mlp_forward": [P, P, I64, P],
     "rt_mlp_grad": [P, P, P, P, I64, P, P],
     "rt_mlp_train_step": [P, P, P, P, I64, ctypes.c_float, P],
-    "rt_mlp_sample_batch": [P, P, P, P, I32, ctypes.POINTER(rt_grid), ctypes.c_uint64, ctypes.c_uint64, P, P, P, I64],
+    "rt_mlp_valid_index": [P, P, I64, P, I64, ctypes.POINTER(I64)],
+    "rt_mlp_sample_batch": [P, P, P, I64, P, I32, ctypes.POINTER(rt_grid), ctypes.c_uint64, ctypes.c_uint64, P, P, P,
+                            I64],
     "rt_mlp_predict_maps": [P, P, I32, ctypes.POINTER(rt_grid), P],
 }
 _RESTYPE = {"rt_last_error": ctypes.c_char_p}

@@ -139,57 +139,4 @@ struct GradArgs {
 };
 hipError_t launch_power_grad(const GradArgs& a, const MatTable& mats, hipStream_t s);
 
-
-// ---------------------------------------------------------------- MLP surrogate
-constexpr int kFreq = 64;
-enum : int { kEpiStoreF32 = 0, kEpiBiasGelu = 1, kEpiGeluGrad = 2 };
-
-struct GemmArgs {  // C[m][n] = sum_k A[m * lda + k] B[n * ldb + k], bf16 in, fp32 accumulate
-    const __bf16* A;
-    const __bf16* B;
-    int lda, ldb;
-    int M, N, K, ksplit;
-    int epi;
-    const float* bias;     // kEpiBiasGelu
-    __bf16* outZ;          // kEpiBiasGelu: z; kEpiGeluGrad: dz (may be null for z)
-    __bf16* outH;          // kEpiBiasGelu: gelu(z)
-    const __bf16* Zprev;   // kEpiGeluGrad
-    float* outF;           // kEpiStoreF32: [split][M][N]
-};
-
-struct MlpNorm {
-    float center[5];
-    float inv_half[5];
-};
-
-struct MlpLayout {
-    int64_t w_off[5], w_size[5], b_off[5];
-    int32_t fan_in[5];
-    int64_t bf_off[4];
-    int64_t total;
-};
-
-hipError_t launch_gemm_nt(const GemmArgs& g, int splits, hipStream_t s);
-hipError_t launch_features(const float* v, int64_t n, const float* ff, const MlpNorm& norm, __bf16* out, hipStream_t s);
-hipError_t launch_head(const __bf16* H4, const __bf16* Z4, const float* w5, const float* b5, const float* t,
-                       const float* m, int64_t n, const float* msum, float* pred, float* loss, __bf16* dZ4, float* gw5,
-                       float* gb5, hipStream_t s);
-hipError_t launch_mask_sum(const float* m, int64_t n, float* out, hipStream_t s);
-hipError_t launch_transpose(const __bf16* in, int64_t R, int64_t C, __bf16* out, hipStream_t s);
-hipError_t launch_colsum(const __bf16* dZ, int64_t rows, float* db, hipStream_t s);
-hipError_t launch_reduce_splits(const float* part, int S, int64_t n, float* grad, hipStream_t s);
-hipError_t launch_mlp_init(float* params, float* ff, uint64_t seed, float ff_scale, const MlpLayout& lay,
-                           hipStream_t s);
-hipError_t launch_refresh_bf16(const float* params, const MlpLayout& lay, __bf16* wbf, __bf16* wtbf, hipStream_t s);
-hipError_t launch_adam(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2,
-                       float eps, float c1, float c2, hipStream_t s);
-hipError_t launch_sample(const float* maps, const uint8_t* mask, const float* tx, int32_t T, double gx0, double gy0,
-                         double gcell, int32_t gnx, int32_t gny, uint64_t seed, uint64_t step, float* v, float* t,
-                         float* m, int64_t n, hipStream_t s);
-hipError_t launch_infer_fused(const float* tx, int32_t T, double gx0, double gy0, double gcell, int32_t gnx,
-                              int32_t gny, const float* ff, const MlpNorm& norm, const __bf16* wbf,
-                              const MlpLayout& lay, const float* params, float* out, hipStream_t s);
-hipError_t launch_map_inputs(const float* tx, int32_t T, double gx0, double gy0, double gcell, int32_t gnx,
-                             int32_t gny, int64_t row0, int64_t rows, float* v, hipStream_t s);
-
 }  // namespace rt

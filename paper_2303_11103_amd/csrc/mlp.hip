@@ -15,7 +15,7 @@
 // The transposed operands come from a tiled transpose kernel.
 #include <hip/hip_runtime.h>
 
-#include "kernels.h"
+#include "mlp_kernels.h"
 
 namespace rt {
 
@@ -39,6 +39,15 @@ __device__ __forceinline__ float gelu_grad(float x) {
     const float s = sigm2(u);
     const float du = kGeluC * (1.0f + 3.0f * 0.044715f * x * x);
     return s + 2.0f * x * s * (1.0f - s) * du;
+}
+
+// Free-space gain [dB] of the link from the transmitter (v[0..2]) to the cell
+// (v[3], v[4], prior_rx_z); 0 when the prior is off.
+__device__ __forceinline__ float prior_db(const MlpNorm& nm, float tx, float ty, float tz, float cx, float cy) {
+    if (!nm.prior_on) return 0.0f;
+    const float dx = cx - tx, dy = cy - ty, dz = nm.prior_rx_z - tz;
+    const float d2 = fmaxf(dx * dx + dy * dy + dz * dz, 1e-6f);
+    return nm.prior_db - 3.0102999566398120f * __log2f(d2);  // 10 log10(d2) = (10 log10 2) log2(d2)
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -123,6 +132,7 @@ __global__ void features_kernel(const float* __restrict__ v, int64_t n, const fl
 // pred = w5 . h4 + b5; loss and dZ4 = g w5 gelu'(Z4); dw5 and db5 partial sums.
 __global__ __launch_bounds__(256) void head_kernel(const bf16* __restrict__ H4, const bf16* __restrict__ Z4,
                                                    const float* __restrict__ w5, const float* __restrict__ b5,
+                                                   const float* __restrict__ v, MlpNorm norm,
                                                    const float* __restrict__ t, const float* __restrict__ m,
                                                    int64_t n, const float* __restrict__ msum, float* __restrict__ pred,
                                                    float* __restrict__ loss, bf16* __restrict__ dZ4,
@@ -142,6 +152,8 @@ __global__ __launch_bounds__(256) void head_kernel(const bf16* __restrict__ H4, 
         if (row < n) {
             float y = b5[0];
             for (int k = 0; k < 256; ++k) y += sw[k] * (float)H4[row * 256 + k];
+            const float* vr = v + 5 * row;
+            y += prior_db(norm, vr[0], vr[1], vr[2], vr[3], vr[4]);
             if (pred) pred[row] = y;
             if (t) {
                 const float inv = 1.0f / fmaxf(msum[0], 1.0f);
@@ -221,9 +233,11 @@ __device__ __forceinline__ uint64_t splitmix(uint64_t x) {
 }
 __device__ __forceinline__ float u01(uint64_t h) { return ((float)(h >> 40) + 0.5f) * 0x1p-24f; }
 
-// Weights uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)), biases 0; Fourier matrix N(0, scale^2).
-__global__ void init_kernel(float* __restrict__ params, float* __restrict__ ff, uint64_t seed, float ff_scale,
-                            MlpLayout lay) {
+// Weights uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)), biases 0; Fourier matrix
+// N(0, s^2) with s = ff_scale_tx on the transmitter columns (0..2) and
+// ff_scale_cell on the cell columns (3, 4).
+__global__ void init_kernel(float* __restrict__ params, float* __restrict__ ff, uint64_t seed, float ff_scale_tx,
+                            float ff_scale_cell, MlpLayout lay) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < lay.total) {
         float v = 0.0f;
@@ -239,7 +253,7 @@ __global__ void init_kernel(float* __restrict__ params, float* __restrict__ ff, 
         const uint64_t h1 = splitmix(seed * 7919u + 0x1234567ull + 2 * (uint64_t)i);
         const uint64_t h2 = splitmix(seed * 7919u + 0x1234567ull + 2 * (uint64_t)i + 1);
         const float r = sqrtf(-2.0f * logf(u01(h1)));
-        ff[i] = ff_scale * r * cospif(2.0f * u01(h2));
+        ff[i] = ((i % 5) < 3 ? ff_scale_tx : ff_scale_cell) * r * cospif(2.0f * u01(h2));
     }
 }
 
@@ -274,19 +288,20 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, 
 
 // Random (tx, cell) samples from a stack of maps: counter-based hash of
 // (seed, step, row); up to 8 draws until a masked-in cell is found.
-__global__ void sample_kernel(const float* __restrict__ maps, const uint8_t* __restrict__ mask,
+__global__ void sample_kernel(const float* __restrict__ maps, const uint32_t* __restrict__ index, int64_t count,
                               const float* __restrict__ tx, int32_t T, double gx0, double gy0, double gcell,
                               int32_t gnx, int32_t gny, uint64_t seed, uint64_t step, float* __restrict__ v,
                               float* __restrict__ t, float* __restrict__ m, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t cells = (int64_t)gnx * gny;
-    const uint64_t total = (uint64_t)T * (uint64_t)cells;
-    uint64_t h = splitmix(seed ^ splitmix(step * 0x100000001B3ull + (uint64_t)i));
-    uint64_t s = h % total;
-    for (int tries = 0; tries < 8 && !mask[s]; ++tries) {
-        h = splitmix(h);
-        s = h % total;
+    const uint64_t h = splitmix(seed ^ splitmix(step * 0x100000001B3ull + (uint64_t)i));
+    const uint64_t s = index[h % (uint64_t)count];
+    if (s >= (uint64_t)T * (uint64_t)cells) {  // an index that does not belong to this map stack
+        for (int k = 0; k < 5; ++k) v[5 * i + k] = 0.0f;
+        t[i] = 0.0f;
+        m[i] = 0.0f;
+        return;
     }
     const int64_t tt = (int64_t)(s / (uint64_t)cells), c = (int64_t)(s % (uint64_t)cells);
     const int64_t iy = c / gnx, ix = c - iy * gnx;
@@ -295,8 +310,76 @@ __global__ void sample_kernel(const float* __restrict__ maps, const uint8_t* __r
     v[5 * i + 2] = tx[3 * tt + 2];
     v[5 * i + 3] = (float)(gx0 + (ix + 0.5) * gcell);
     v[5 * i + 4] = (float)(gy0 + (iy + 0.5) * gcell);
-    t[i] = mask[s] ? maps[s] : 0.0f;
-    m[i] = mask[s] ? 1.0f : 0.0f;
+    t[i] = maps[s];
+    m[i] = 1.0f;
+}
+
+// ------------------------------------------------------------------ valid-cell index
+// 256 threads per tile of kIndexTile bytes; thread j owns bytes [16 j, 16 j + 16).
+__device__ __forceinline__ uint32_t count16(const uint8_t* __restrict__ mask, int64_t b, int64_t n) {
+    uint32_t c = 0;
+    for (int k = 0; k < 16; ++k)
+        if (b + k < n) c += mask[b + k] != 0;
+    return c;
+}
+
+__global__ __launch_bounds__(256) void index_count_kernel(const uint8_t* __restrict__ mask, int64_t n,
+                                                          uint32_t* __restrict__ tile_counts) {
+    __shared__ uint32_t part[4];
+    const int64_t b = (int64_t)blockIdx.x * kIndexTile + threadIdx.x * 16;
+    uint32_t c = count16(mask, b, n);
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) tile_counts[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
+// one block of 1024 threads: exclusive prefix of the tile counts, total last
+__global__ __launch_bounds__(1024) void index_scan_kernel(const uint32_t* __restrict__ cnt, int64_t tiles,
+                                                          uint64_t* __restrict__ off) {
+    __shared__ uint64_t wsum[16];
+    __shared__ uint64_t carry;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < tiles; base += 1024) {
+        const int64_t i = base + tid;
+        const uint64_t x = i < tiles ? cnt[i] : 0;
+        uint64_t incl = x;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint64_t y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        uint64_t before = carry;
+        for (int k = 0; k < w; ++k) before += wsum[k];
+        if (i < tiles) off[i] = before + incl - x;
+        __syncthreads();
+        if (tid == 1023) carry = before + incl;
+        __syncthreads();
+    }
+    if (tid == 0) off[tiles] = carry;
+}
+
+__global__ __launch_bounds__(256) void index_write_kernel(const uint8_t* __restrict__ mask, int64_t n,
+                                                          const uint64_t* __restrict__ off,
+                                                          uint32_t* __restrict__ index) {
+    __shared__ uint32_t wsum[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t b = (int64_t)blockIdx.x * kIndexTile + tid * 16;
+    const uint32_t c = count16(mask, b, n);
+    uint32_t incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint64_t at = off[blockIdx.x] + incl - c;
+    for (int k = 0; k < w; ++k) at += wsum[k];
+    for (int k = 0; k < 16; ++k)
+        if (b + k < n && mask[b + k]) index[at++] = (uint32_t)(b + k);
 }
 
 // Inputs of every (tx, cell) pair of a map stack, rows ordered [tx][cell].
@@ -415,7 +498,13 @@ __global__ __launch_bounds__(512) void infer_fused_kernel(InferArgs a) {
     y += __shfl_xor(y, 1);
     y += __shfl_xor(y, 2);
     const int64_t gr = row0 + r;
-    if (part == 0 && gr < a.total) a.out[gr] = y + a.params[a.lay.b_off[4]];
+    if (part == 0 && gr < a.total) {
+        const int64_t t = gr / cells, c = gr - t * cells;
+        const int64_t iy = c / a.gnx, ix = c - iy * a.gnx;
+        const float pr = prior_db(a.norm, a.tx[3 * t], a.tx[3 * t + 1], a.tx[3 * t + 2],
+                                  (float)(a.gx0 + (ix + 0.5) * a.gcell), (float)(a.gy0 + (iy + 0.5) * a.gcell));
+        a.out[gr] = y + a.params[a.lay.b_off[4]] + pr;
+    }
 }
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -434,11 +523,11 @@ hipError_t launch_features(const float* v, int64_t n, const float* ff, const Mlp
     return hipGetLastError();
 }
 
-hipError_t launch_head(const bf16* H4, const bf16* Z4, const float* w5, const float* b5, const float* t,
-                       const float* m, int64_t n, const float* msum, float* pred, float* loss, bf16* dZ4, float* gw5,
-                       float* gb5, hipStream_t s) {
-    hipLaunchKernelGGL(head_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, H4, Z4, w5, b5, t, m, n, msum, pred,
-                       loss, dZ4, gw5, gb5);
+hipError_t launch_head(const bf16* H4, const bf16* Z4, const float* w5, const float* b5, const float* v,
+                       const MlpNorm& norm, const float* t, const float* m, int64_t n, const float* msum, float* pred,
+                       float* loss, bf16* dZ4, float* gw5, float* gb5, hipStream_t s) {
+    hipLaunchKernelGGL(head_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, H4, Z4, w5, b5, v, norm, t, m, n, msum,
+                       pred, loss, dZ4, gw5, gb5);
     return hipGetLastError();
 }
 
@@ -464,10 +553,10 @@ hipError_t launch_reduce_splits(const float* part, int S, int64_t n, float* grad
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_init(float* params, float* ff, uint64_t seed, float ff_scale, const MlpLayout& lay,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(init_kernel, dim3(blocks_for(lay.total, 256)), dim3(256), 0, s, params, ff, seed, ff_scale,
-                       lay);
+hipError_t launch_mlp_init(float* params, float* ff, uint64_t seed, float ff_scale_tx, float ff_scale_cell,
+                           const MlpLayout& lay, hipStream_t s) {
+    hipLaunchKernelGGL(init_kernel, dim3(blocks_for(lay.total, 256)), dim3(256), 0, s, params, ff, seed, ff_scale_tx,
+                       ff_scale_cell, lay);
     return hipGetLastError();
 }
 
@@ -483,11 +572,28 @@ hipError_t launch_adam(float* p, const float* g, float* m1, float* m2, int64_t n
     return hipGetLastError();
 }
 
-hipError_t launch_sample(const float* maps, const uint8_t* mask, const float* tx, int32_t T, double gx0, double gy0,
-                         double gcell, int32_t gnx, int32_t gny, uint64_t seed, uint64_t step, float* v, float* t,
-                         float* m, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(sample_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, maps, mask, tx, T, gx0, gy0, gcell,
-                       gnx, gny, seed, step, v, t, m, n);
+hipError_t launch_sample(const float* maps, const uint32_t* index, int64_t count, const float* tx, int32_t T,
+                         double gx0, double gy0, double gcell, int32_t gnx, int32_t gny, uint64_t seed, uint64_t step,
+                         float* v, float* t, float* m, int64_t n, hipStream_t s) {
+    if (count < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sample_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, maps, index, count, tx, T, gx0, gy0,
+                       gcell, gnx, gny, seed, step, v, t, m, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_index_count(const uint8_t* mask, int64_t n, uint32_t* tile_counts, hipStream_t s) {
+    hipLaunchKernelGGL(index_count_kernel, dim3(blocks_for(n, kIndexTile)), dim3(256), 0, s, mask, n, tile_counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_index_scan(const uint32_t* tile_counts, int64_t tiles, uint64_t* offsets, hipStream_t s) {
+    hipLaunchKernelGGL(index_scan_kernel, dim3(1), dim3(1024), 0, s, tile_counts, tiles, offsets);
+    return hipGetLastError();
+}
+
+hipError_t launch_index_write(const uint8_t* mask, int64_t n, const uint64_t* offsets, uint32_t* index,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(index_write_kernel, dim3(blocks_for(n, kIndexTile)), dim3(256), 0, s, mask, n, offsets, index);
     return hipGetLastError();
 }
 

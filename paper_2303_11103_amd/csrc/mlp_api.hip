@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "kernels.h"
+#include "mlp_kernels.h"
 #include "rt.h"
 
 rt_status rt_internal_fail(rt_status code, const char* msg);
@@ -115,8 +115,8 @@ rt_status gradient(rt_mlp* h, const float* v, const float* t, const float* m, in
     MLP_HIP(hipMemsetAsync(h->grad, 0, (size_t)L.total * sizeof(float), s));
     MLP_HIP(hipMemsetAsync(h->scal, 0, 2 * sizeof(float), s));
     MLP_HIP(rt::launch_mask_sum(m, n, h->scal, s));
-    MLP_HIP(rt::launch_head(h->H[3], h->Z[3], h->params + L.w_off[4], h->params + L.b_off[4], t, m, n, h->scal,
-                            h->pred, h->scal + 1, h->dZa, h->grad + L.w_off[4], h->grad + L.b_off[4], s));
+    MLP_HIP(rt::launch_head(h->H[3], h->Z[3], h->params + L.w_off[4], h->params + L.b_off[4], v, h->norm, t, m, n,
+                            h->scal, h->pred, h->scal + 1, h->dZa, h->grad + L.w_off[4], h->grad + L.b_off[4], s));
     __bf16* dz = h->dZa;
     __bf16* dz_next = h->dZb;
     for (int l = 3; l >= 0; --l) {
@@ -179,6 +179,10 @@ rt_status rt_mlp_create(rt_ctx* c, const rt_mlp_config* cfg, rt_mlp** out) {
         if (!(cfg->in_half[i] > 0) || !std::isfinite(cfg->in_center[i]))
             return rt_internal_fail(RT_ERR_ARG, "input normalisation needs finite centres and positive half-ranges");
     if (!(cfg->ff_scale > 0)) return rt_internal_fail(RT_ERR_ARG, "ff_scale must be positive");
+    if (!(cfg->ff_scale_cell >= 0) || !std::isfinite(cfg->ff_scale_cell))
+        return rt_internal_fail(RT_ERR_ARG, "ff_scale_cell must be >= 0 (0 = ff_scale)");
+    if (!(cfg->prior_freq_hz >= 0) || !std::isfinite(cfg->prior_freq_hz) || !std::isfinite(cfg->prior_rx_z))
+        return rt_internal_fail(RT_ERR_ARG, "prior_freq_hz must be >= 0 and prior_rx_z finite");
     MLP_HIP(hipSetDevice(rt_internal_device(c)));
     rt_mlp* h = new rt_mlp();
     h->ctx = c;
@@ -188,6 +192,10 @@ rt_status rt_mlp_create(rt_ctx* c, const rt_mlp_config* cfg, rt_mlp** out) {
         h->norm.center[i] = cfg->in_center[i];
         h->norm.inv_half[i] = 1.0f / cfg->in_half[i];
     }
+    h->norm.prior_on = cfg->prior_freq_hz > 0 ? 1 : 0;
+    h->norm.prior_rx_z = cfg->prior_rx_z;
+    h->norm.prior_db = h->norm.prior_on ? (float)(20.0 * std::log10(299792458.0 / (4.0 * M_PI * cfg->prior_freq_hz)))
+                                        : 0.0f;
     const int64_t P = h->lay.total, B = cfg->batch;
     h->nbf = h->lay.bf_off[3] + h->lay.w_size[3];
     hipError_t e = hipSuccess;
@@ -217,7 +225,8 @@ rt_status rt_mlp_create(rt_ctx* c, const rt_mlp_config* cfg, rt_mlp** out) {
     hipStream_t s = rt_internal_stream(c);
     if (e == hipSuccess) e = hipMemsetAsync(h->m1, 0, P * sizeof(float), s);
     if (e == hipSuccess) e = hipMemsetAsync(h->m2, 0, P * sizeof(float), s);
-    if (e == hipSuccess) e = rt::launch_mlp_init(h->params, h->ff, cfg->seed, cfg->ff_scale, h->lay, s);
+    const float s_cell = cfg->ff_scale_cell > 0 ? cfg->ff_scale_cell : cfg->ff_scale;
+    if (e == hipSuccess) e = rt::launch_mlp_init(h->params, h->ff, cfg->seed, cfg->ff_scale, s_cell, h->lay, s);
     if (e == hipSuccess) e = rt::launch_refresh_bf16(h->params, h->lay, h->wbf, h->wtbf, s);
     if (e != hipSuccess) {
         rt_mlp_destroy(h);
@@ -264,8 +273,8 @@ rt_status rt_mlp_forward(rt_mlp* h, const float* v, int64_t n, float* y) {
     MLP_HIP(hipSetDevice(rt_internal_device(h->ctx)));
     if ((st = forward(h, v, n, s)) != RT_OK) return st;
     const rt::MlpLayout& L = h->lay;
-    MLP_HIP(rt::launch_head(h->H[3], h->Z[3], h->params + L.w_off[4], h->params + L.b_off[4], nullptr, nullptr, n,
-                            nullptr, y, nullptr, nullptr, nullptr, nullptr, s));
+    MLP_HIP(rt::launch_head(h->H[3], h->Z[3], h->params + L.w_off[4], h->params + L.b_off[4], v, h->norm, nullptr,
+                            nullptr, n, nullptr, y, nullptr, nullptr, nullptr, nullptr, s));
     return RT_OK;
 }
 
@@ -301,13 +310,42 @@ rt_status rt_mlp_train_step(rt_mlp* h, const float* v, const float* t, const flo
     return RT_OK;
 }
 
-rt_status rt_mlp_sample_batch(rt_mlp* h, const float* maps, const uint8_t* mask, const float* tx, int32_t T,
-                              const rt_grid* g, uint64_t seed, uint64_t step, float* v, float* t, float* m,
-                              int64_t n) {
-    if (!h || !maps || !mask || !tx || !g || !v || !t || !m) return rt_internal_fail(RT_ERR_ARG, "NULL argument");
-    if (T < 1 || n < 1 || g->nx < 1 || g->ny < 1) return rt_internal_fail(RT_ERR_ARG, "empty map stack or batch");
+rt_status rt_mlp_valid_index(rt_mlp* h, const uint8_t* mask, int64_t n, uint32_t* index, int64_t capacity,
+                             int64_t* count) {
+    if (!h || !mask || !count || (capacity > 0 && !index)) return rt_internal_fail(RT_ERR_ARG, "NULL argument");
+    if (n < 1 || n >= (int64_t(1) << 32)) return rt_internal_fail(RT_ERR_ARG, "mask length must be in [1, 2^32)");
+    if (capacity < 0) return rt_internal_fail(RT_ERR_ARG, "negative capacity");
     hipStream_t s = rt_internal_stream(h->ctx);
-    MLP_HIP(rt::launch_sample(maps, mask, tx, T, g->x0, g->y0, g->cell, g->nx, g->ny, seed, step, v, t, m, n, s));
+    MLP_HIP(hipSetDevice(rt_internal_device(h->ctx)));
+    const int64_t tiles = (n + rt::kIndexTile - 1) / rt::kIndexTile;
+    uint32_t* cnt = nullptr;
+    uint64_t* off = nullptr;
+    MLP_HIP(hipMalloc((void**)&cnt, (size_t)tiles * sizeof(uint32_t)));
+    hipError_t e = hipMalloc((void**)&off, (size_t)(tiles + 1) * sizeof(uint64_t));
+    uint64_t total = 0;
+    if (e == hipSuccess) e = rt::launch_index_count(mask, n, cnt, s);
+    if (e == hipSuccess) e = rt::launch_index_scan(cnt, tiles, off, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&total, off + tiles, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && (int64_t)total <= capacity) e = rt::launch_index_write(mask, n, off, index, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(cnt);
+    if (off) (void)hipFree(off);
+    MLP_HIP(e);
+    *count = (int64_t)total;
+    if ((int64_t)total > capacity) return rt_internal_fail(RT_ERR_CAPACITY, "index capacity below the valid-cell count");
+    return RT_OK;
+}
+
+rt_status rt_mlp_sample_batch(rt_mlp* h, const float* maps, const uint32_t* index, int64_t count, const float* tx,
+                              int32_t T, const rt_grid* g, uint64_t seed, uint64_t step, float* v, float* t, float* m,
+                              int64_t n) {
+    if (!h || !maps || !index || !tx || !g || !v || !t || !m) return rt_internal_fail(RT_ERR_ARG, "NULL argument");
+    if (T < 1 || n < 1 || g->nx < 1 || g->ny < 1) return rt_internal_fail(RT_ERR_ARG, "empty map stack or batch");
+    if (count < 1) return rt_internal_fail(RT_ERR_ARG, "no usable cells (count < 1)");
+    hipStream_t s = rt_internal_stream(h->ctx);
+    MLP_HIP(rt::launch_sample(maps, index, count, tx, T, g->x0, g->y0, g->cell, g->nx, g->ny, seed, step, v, t, m, n,
+                              s));
     return RT_OK;
 }
 

@@ -126,7 +126,14 @@ __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_node
     };
     auto pop = [&]() {
         --sp;
-        return sp < kStack ? stack[sp][tid] : ovf[sp - kStack];
+        int v;
+        if (sp < kStack) {
+            v = stack[sp][tid];
+            asm volatile("" ::: "memory");  // an LDS read, not a flat one shared with ovf
+        } else {
+            v = ovf[sp - kStack];
+        }
+        return v;
     };
     while (true) {
         if (node >= 0) {
@@ -137,6 +144,9 @@ __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_node
                 const float4* np = reinterpret_cast<const float4*>(lds_nodes + node);
                 X0 = np[0]; X1 = np[1]; Y0 = np[2]; Y1 = np[3]; Z0 = np[4]; Z1 = np[5];
                 ch = reinterpret_cast<const int4*>(np)[6];
+                // keeps the two branches distinct, so that the LDS reads are not
+                // merged with the global ones into generic (flat) loads
+                asm volatile("" ::: "memory");
             } else {
                 const float4* np = reinterpret_cast<const float4*>(sc.nodes + node);
                 X0 = np[0]; X1 = np[1]; Y0 = np[2]; Y1 = np[3]; Z0 = np[4]; Z1 = np[5];

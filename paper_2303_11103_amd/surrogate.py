@@ -31,11 +31,18 @@ class MLP:
     """Handle on the library's Fourier-feature MLP (weights live on the GPU)."""
 
     def __init__(self, ctx: Context, batch=32768, ff_scale=4.0, seed=0, center=(0, 0, 0, 0, 0),
-                 half=(1, 1, 1, 1, 1)):
+                 half=(1, 1, 1, 1, 1), ff_scale_cell=0.0, prior=None):
+        """ff_scale: Fourier std on the transmitter inputs; ff_scale_cell on the
+        cell inputs (0 = ff_scale); prior = (freq_hz, rx_z) adds the free-space
+        gain of the link to the output (the network learns the residual)."""
         self.ctx = ctx
         cfg = L.rt_mlp_config()
         cfg.batch = int(batch)
         cfg.ff_scale = float(ff_scale)
+        cfg.ff_scale_cell = float(ff_scale_cell)
+        if prior is not None:
+            cfg.prior_freq_hz = float(prior[0])
+            cfg.prior_rx_z = float(prior[1])
         cfg.seed = int(seed)
         for i in range(5):
             cfg.in_center[i] = float(center[i])
@@ -82,7 +89,22 @@ class MLP:
         check(lib.rt_mlp_train_step(self.h, _p(v), _p(t), _p(m), v.shape[0], float(lr), _p(self._loss)))
         return self._loss
 
-    def sample_batch(self, maps, mask, tx, grid, seed, step, n, out=None):
+    def valid_index(self, mask):
+        """Flat positions of the nonzero entries of a uint8 mask (ascending), as an
+        int32 tensor holding the uint32 values."""
+        mask = mask.contiguous()
+        n = mask.numel()
+        count = ctypes.c_int64()
+        self.ctx._bind_stream()
+        # count first (capacity 0 reports RT_ERR_CAPACITY with the count), then write
+        st = lib.rt_mlp_valid_index(self.h, _p(mask), n, None, 0, ctypes.byref(count))
+        if st not in (0, L.RT_ERR_CAPACITY):
+            check(st)
+        idx = torch.empty(max(1, count.value), dtype=torch.int32, device=mask.device)
+        check(lib.rt_mlp_valid_index(self.h, _p(mask), n, _p(idx), count.value, ctypes.byref(count)))
+        return idx[:count.value]
+
+    def sample_batch(self, maps, index, tx, grid, seed, step, n, out=None):
         dev = maps.device
         if out is None:
             out = (torch.empty((n, 5), dtype=torch.float32, device=dev), torch.empty(n, dtype=torch.float32, device=dev),
@@ -90,8 +112,8 @@ class MLP:
         v, t, m = out
         g = grid_struct(grid)
         self.ctx._bind_stream()
-        check(lib.rt_mlp_sample_batch(self.h, _p(maps), _p(mask), _p(tx), tx.shape[0], ctypes.byref(g), int(seed),
-                                      int(step), _p(v), _p(t), _p(m), n))
+        check(lib.rt_mlp_sample_batch(self.h, _p(maps), _p(index), index.numel(), _p(tx), tx.shape[0],
+                                      ctypes.byref(g), int(seed), int(step), _p(v), _p(t), _p(m), n))
         return v, t, m
 
     def predict_maps(self, tx, grid, out=None):
@@ -141,17 +163,19 @@ class TrainReport:
 
 
 def train(mlp: MLP, maps, mask, tx, grid, steps=2000, lr=1e-3, seed=1, log_every=0):
-    """Adam with a cosine learning-rate schedule on batches drawn from the maps."""
+    """Adam with a cosine learning-rate schedule on batches drawn uniformly from
+    the usable cells (mask != 0) of the maps."""
     import time
     n = mlp.batch
     dev = maps.device
+    index = mlp.valid_index(mask)
     bufs = (torch.empty((n, 5), dtype=torch.float32, device=dev), torch.empty(n, dtype=torch.float32, device=dev),
             torch.empty(n, dtype=torch.float32, device=dev))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     loss = None
     for s in range(steps):
-        v, t, m = mlp.sample_batch(maps, mask, tx, grid, seed, s, n, out=bufs)
+        v, t, m = mlp.sample_batch(maps, index, tx, grid, seed, s, n, out=bufs)
         cur = lr * 0.5 * (1.0 + math.cos(math.pi * s / steps))
         loss = mlp.train_step(v, t, m, max(cur, lr * 1e-3))
         if log_every and (s % log_every == 0 or s == steps - 1):

@@ -12,21 +12,25 @@ from oracle import geom, native
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2303_11103_amd", "csrc")
-WORK = os.path.join(ROOT, "_work")
 
 
 @pytest.fixture(scope="module")
-def checker():
-    os.makedirs(WORK, exist_ok=True)
-    exe = os.path.join(WORK, "bvh_check")
+def workdir(tmp_path_factory):
+    return str(tmp_path_factory.mktemp("bvh_host"))
+
+
+@pytest.fixture(scope="module")
+def checker(workdir):
+    exe = os.path.join(workdir, "bvh_check")
     subprocess.run(["g++", "-O2", "-std=c++17", "-I", CSRC, os.path.join(CSRC, "scene.cpp"),
                     os.path.join(ROOT, "tests", "host", "bvh_check.cpp"), "-o", exe], check=True)
     return exe
 
 
 def _run(exe, s, O, D):
-    inp = os.path.join(WORK, "bvh_in.bin")
-    out = os.path.join(WORK, "bvh_out.bin")
+    work = os.path.dirname(exe)
+    inp = os.path.join(work, "bvh_in.bin")
+    out = os.path.join(work, "bvh_out.bin")
     with open(inp, "wb") as f:
         np.asarray([len(s.V), s.nt, len(s.materials), len(O)], dtype=np.int64).tofile(f)
         np.ascontiguousarray(s.V, dtype=np.float32).tofile(f)

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     assert sorted(_lib.SIGNATURES) == names
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
     from paper_2303_11103_amd import _lib
     # sizes implied by the header (natural alignment, x86-64)
     assert ctypes.sizeof(_lib.rt_material) == 8
@@ -38,19 +38,20 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.rt_trace_params) == 48
     assert ctypes.sizeof(_lib.rt_grid) == 40
     assert ctypes.sizeof(_lib.rt_scene_info_t) == 40
+    assert ctypes.sizeof(_lib.rt_mlp_config) == 72
     src = (
         "#include <stddef.h>\n#include <stdio.h>\n#include \"rt.h\"\n"
-        "int main(){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(rt_material), sizeof(rt_device),"
+        "int main(){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(rt_material), sizeof(rt_device),"
         " sizeof(rt_trace_params), sizeof(rt_grid), sizeof(rt_scene_info_t),"
-        " offsetof(rt_trace_params, num_rays), offsetof(rt_grid, nx)); return 0;}\n")
-    tmp = os.path.join(ROOT, "_work")
-    os.makedirs(tmp, exist_ok=True)
-    c = os.path.join(tmp, "layout_check.c")
-    exe = os.path.join(tmp, "layout_check")
-    open(c, "w").write(src)
-    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
-    vals = list(map(int, subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()))
-    assert vals == [8, 32, 48, 40, 40, _lib.rt_trace_params.num_rays.offset, _lib.rt_grid.nx.offset]
+        " offsetof(rt_trace_params, num_rays), offsetof(rt_grid, nx), sizeof(rt_mlp_config),"
+        " offsetof(rt_mlp_config, ff_scale_cell), offsetof(rt_mlp_config, prior_freq_hz)); return 0;}\n")
+    c = tmp_path / "layout_check.c"
+    exe = tmp_path / "layout_check"
+    c.write_text(src)
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    vals = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()))
+    assert vals == [8, 32, 48, 40, 40, _lib.rt_trace_params.num_rays.offset, _lib.rt_grid.nx.offset, 72,
+                    _lib.rt_mlp_config.ff_scale_cell.offset, _lib.rt_mlp_config.prior_freq_hz.offset]
 
 
 def test_null_and_invalid_arguments_fail_on_host():

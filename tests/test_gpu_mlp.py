@@ -95,7 +95,7 @@ def test_training_reduces_loss_on_a_smooth_field():
     assert np.mean(losses[-10:]) < 0.6 * np.mean(losses[:10]), (losses[0], losses[-1])
 
 
-def test_sample_batch_and_predict_maps():
+def test_valid_index_sample_batch_and_predict_maps():
     import scenegen as sg
     m = _mlp(batch=1024, seed=9)
     grid = sg.Grid(-10.0, -20.0, 2.0, 16, 12, 1.5)
@@ -103,19 +103,24 @@ def test_sample_batch_and_predict_maps():
     dev = "cuda"
     rng = np.random.default_rng(3)
     maps = torch.tensor(rng.normal(size=(T, grid.ny, grid.nx)).astype(np.float32), device=dev)
-    mask = torch.tensor((rng.random((T, grid.ny, grid.nx)) < 0.5).astype(np.uint8), device=dev)
+    mask = torch.tensor((rng.random((T, grid.ny, grid.nx)) < 0.3).astype(np.uint8), device=dev)
     tx = torch.tensor(rng.uniform(-5, 5, size=(T, 3)).astype(np.float32), device=dev)
-    v, t, mm = m.sample_batch(maps, mask, tx, grid, seed=11, step=4, n=1024)
+    # the index is the ordered list of usable flat positions (integer work: exact)
+    idx = m.valid_index(mask).cpu().numpy().view(np.uint32)
+    assert np.array_equal(idx, np.flatnonzero(mask.cpu().numpy().reshape(-1)))
+    v, t, mm = m.sample_batch(maps, m.valid_index(mask), tx, grid, seed=11, step=4, n=1024)
     v, t, mm = v.cpu().numpy(), t.cpu().numpy(), mm.cpu().numpy()
     txn, mapsn, maskn = tx.cpu().numpy(), maps.cpu().numpy(), mask.cpu().numpy()
+    assert np.all(mm == 1.0)
+    seen = set()
     for i in range(1024):
         k = int(np.argmin(np.abs(txn - v[i, :3]).sum(1)))
         assert np.array_equal(txn[k], v[i, :3])
         ix = int(round((v[i, 3] - grid.x0) / grid.cell - 0.5))
         iy = int(round((v[i, 4] - grid.y0) / grid.cell - 0.5))
-        if mm[i] > 0:
-            assert maskn[k, iy, ix] == 1 and t[i] == mapsn[k, iy, ix]
-    assert mm.mean() > 0.9
+        assert maskn[k, iy, ix] == 1 and t[i] == mapsn[k, iy, ix]
+        seen.add((k, iy, ix))
+    assert len(seen) > 0.8 * len(idx)  # 1024 uniform draws over ~170 cells reach nearly all
     pred = m.predict_maps(tx, grid).cpu().numpy()
     # the same inputs through the row-wise forward
     ys, xs = np.meshgrid(grid.y0 + (np.arange(grid.ny) + 0.5) * grid.cell,
@@ -129,3 +134,45 @@ def test_sample_batch_and_predict_maps():
     vp = np.concatenate([vv, np.zeros((pad, 5), np.float32)])
     y = m.forward(torch.tensor(vp, device=dev)).cpu().numpy()[:len(vv)]
     assert np.allclose(pred.reshape(-1), y, rtol=1e-5, atol=1e-4)
+
+
+def test_free_space_prior_and_per_input_fourier_scales():
+    """With the prior on, forward = oracle MLP + the oracle's free-space gain on
+    raw coordinates; map prediction equals the row-wise forward; the Fourier
+    matrix has the requested per-column spread."""
+    from paper_2303_11103_amd.surrogate import MLP
+    import scenegen as sg
+    lo = np.array([-200.0, -200.0, 10.0, -200.0, -200.0])
+    hi = np.array([200.0, 200.0, 65.0, 200.0, 200.0])
+    m = MLP(ctx(), batch=1024, ff_scale=1.0, ff_scale_cell=6.0, seed=21, center=(lo + hi) / 2, half=(hi - lo) / 2,
+            prior=(3.5e9, 1.5))
+    p, ff = m.get_params()
+    B = ff.cpu().double().numpy()
+    assert 0.6 < B[:, :3].std() < 1.5 and 4.0 < B[:, 3:].std() < 8.5
+    rng = np.random.default_rng(5)
+    raw = np.concatenate([rng.uniform(-200, 200, size=(512, 2)), rng.uniform(10, 65, size=(512, 1)),
+                          rng.uniform(-200, 200, size=(512, 2))], 1).astype(np.float32)
+    y = m.forward(torch.tensor(raw, device="cuda")).cpu().double().numpy()
+    vn = (raw.astype(np.float64) - (lo + hi) / 2) / ((hi - lo) / 2)
+    theta = p.cpu().double().numpy()
+    q = []
+    for li, (W, b) in enumerate(omlp.unpack(theta)):
+        q.append(bf16(W).reshape(-1) if li < 4 else W.reshape(-1))
+        q.append(b)
+    feats = bf16(omlp.features(vn, B))
+    prior = omlp.free_space_db(raw.astype(np.float64), 3.5e9, 1.5)
+    yo, _ = omlp.forward(np.concatenate(q), vn, B, feats=feats, prior_db=prior)
+    head = yo - prior
+    assert np.max(np.abs(prior)) > 40
+    # the prior itself to fp32 rounding; the network part to the bf16 tolerance of the plain forward test
+    assert np.max(np.abs(y - yo)) <= 2e-2 * np.max(np.abs(head)) + 1e-3
+    grid = sg.Grid(-40.0, -30.0, 4.0, 20, 16, 1.5)
+    tx = torch.tensor(raw[:2, :3], device="cuda")
+    pred = m.predict_maps(tx, grid).cpu().numpy()
+    ys, xs = np.meshgrid(grid.y0 + (np.arange(grid.ny) + 0.5) * grid.cell,
+                         grid.x0 + (np.arange(grid.nx) + 0.5) * grid.cell, indexing="ij")
+    vv = np.concatenate([np.stack([np.full(xs.size, raw[k, 0]), np.full(xs.size, raw[k, 1]),
+                                   np.full(xs.size, raw[k, 2]), xs.reshape(-1), ys.reshape(-1)], 1)
+                         for k in range(2)]).astype(np.float32)
+    yr = m.forward(torch.tensor(vv, device="cuda")).cpu().numpy()
+    assert np.allclose(pred.reshape(-1), yr, rtol=1e-5, atol=1e-3)

@@ -1,0 +1,63 @@
+"""What the trained surrogate gains over the ray tracer alone: on held-out
+rooftop transmitters of the urban scene it predicts the ray-traced maps far
+better than the free-space gain it starts from, and it produces them many
+times faster than tracing them."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import scenegen as sg
+from oracle import mlp as omlp
+
+from gpu_common import ctx, lib, requires_gpu, scene
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+def test_trained_surrogate_beats_free_space_and_outruns_the_tracer():
+    m_lib = lib()
+    from paper_2303_11103_amd import surrogate as S
+    w = sg.urban_workload()
+    sc = scene(w.scene)
+    grid = sg.Grid(-200.0, -200.0, 4.0, 100, 100, 1.5)
+    n_tx, n_val = 512, 64
+    tx_np = sg.rooftop_tx_positions(w.scene, n_tx, seed=5)
+    p = m_lib.TraceParams(w.scene.freq_hz, 3, 2_000_000)
+    S.ray_traced_maps(ctx(), sc, p, tx_np[:4], grid)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    maps, mask = S.ray_traced_maps(ctx(), sc, p, tx_np, grid)
+    torch.cuda.synchronize()
+    trace_s_per_map = (time.perf_counter() - t0) / n_tx
+    maps = torch.where(mask.bool(), maps, torch.zeros_like(maps))
+    tx = torch.tensor(tx_np, device="cuda")
+    tr, va = slice(0, n_tx - n_val), slice(n_tx - n_val, n_tx)
+    lo = np.array([-200.0, -200.0, 10.0, -200.0, -200.0])
+    hi = np.array([200.0, 200.0, 65.0, 200.0, 200.0])
+    m = S.MLP(ctx(), batch=8192, ff_scale=1.0, ff_scale_cell=4.0, seed=3, center=(lo + hi) / 2, half=(hi - lo) / 2,
+              prior=(w.scene.freq_hz, grid.z))
+    S.train(m, maps[tr].contiguous(), mask[tr].contiguous(), tx[tr].contiguous(), grid, steps=3000, lr=2e-3, seed=3)
+    txv = tx[va].contiguous()
+    m.predict_maps(txv, grid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = m.predict_maps(txv, grid)
+    torch.cuda.synchronize()
+    sur_s_per_map = (time.perf_counter() - t0) / n_val
+    rmse = S.rmse_db(pred, maps[va], mask[va])
+    # the free-space gain alone, from the oracle's definition, on the same cells
+    ys, xs = np.meshgrid(grid.y0 + (np.arange(grid.ny) + 0.5) * grid.cell,
+                         grid.x0 + (np.arange(grid.nx) + 0.5) * grid.cell, indexing="ij")
+    fs = np.stack([omlp.free_space_db(np.stack([np.full(xs.size, t[0]), np.full(xs.size, t[1]), np.full(xs.size, t[2]),
+                                                xs.reshape(-1), ys.reshape(-1)], 1), w.scene.freq_hz, grid.z)
+                   for t in tx_np[va]]).reshape(n_val, grid.ny, grid.nx)
+    sel = mask[va].cpu().numpy().astype(bool)
+    rmse_fs = float(np.sqrt(np.mean((fs - maps[va].cpu().numpy())[sel] ** 2)))
+    print("surrogate rmse %.2f dB vs free space %.2f dB; %.3g s/map traced, %.3g s/map predicted"
+          % (rmse, rmse_fs, trace_s_per_map, sur_s_per_map))
+    assert sel.sum() > 1000
+    assert rmse < 0.75 * rmse_fs, (rmse, rmse_fs)
+    assert sur_s_per_map * 5 < trace_s_per_map, (sur_s_per_map, trace_s_per_map)
+    m.close()

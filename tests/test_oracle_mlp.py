@@ -51,3 +51,24 @@ def test_features_are_unit_circle_pairs():
     f = mlp.features(v, Bf)
     assert f.shape == (v.shape[0], 128)
     assert np.allclose(f[:, :64] ** 2 + f[:, 64:] ** 2, 1.0)
+
+
+def test_free_space_prior_equals_image_method_line_of_sight():
+    """The prior's definition against the oracle's image-method LoS path
+    (isotropic antennas, no obstacle): 10 log10 |a|^2."""
+    import scenegen as sg
+    from oracle import geom, image
+    s = sg.make_toy()
+    s.V[:, 2] -= 1000.0  # move the scene far below the links
+    g = geom.Geometry(s)
+    rng = np.random.default_rng(4)
+    pts = np.concatenate([rng.uniform(-50, 50, size=(6, 2)), rng.uniform(10, 60, size=(6, 1)),
+                          rng.uniform(-80, 80, size=(6, 2))], 1)
+    rx_z = 1.5
+    prior = mlp.free_space_db(pts, 3.5e9, rx_z)
+    from types import SimpleNamespace
+    for k in range(len(pts)):
+        dev = lambda p: SimpleNamespace(pos=tuple(p), yaw=0.0, pitch=0.0, roll=0.0, pattern=0)
+        P = image.paths(g, dev(pts[k, :3]), [dev((pts[k, 3], pts[k, 4], rx_z))], [])[0]
+        assert len(P) == 1 and P[0].faces == ()
+        assert abs(10 * np.log10(abs(P[0].a) ** 2) - prior[k]) < 1e-9
