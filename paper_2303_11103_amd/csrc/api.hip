@@ -350,6 +350,7 @@ rt_status rt_scene_create(rt_ctx* c, const float* V, int64_t nv, const int32_t* 
     s->dev.num_faces = h.num_faces;
     s->dev.nt = (int32_t)nt;
     s->dev.num_nodes = (int32_t)h.nodes.size();
+    s->dev.stack_need = h.stack_need;
     *out = s;
     return RT_OK;
 }

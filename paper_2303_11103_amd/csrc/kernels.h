@@ -32,7 +32,7 @@ struct DevScene {
     int32_t num_faces;
     int32_t nt;
     int32_t num_nodes;
-    int32_t pad;
+    int32_t stack_need;  // worst-case traversal stack entries of the tree
 };
 
 struct SbrArgs {

@@ -119,7 +119,7 @@ __device__ __forceinline__ void store_ray(RayState* __restrict__ p, const Ray& r
     reinterpret_cast<int4*>(p)[5] = int4{r.ray, 0, 0, 0};
 }
 
-template <int MODE, bool FIRST>
+template <int MODE, bool FIRST, bool OVF>
 #ifndef RT_TRACE_WAVES_PER_EU
 #define RT_TRACE_WAVES_PER_EU 4
 #endif
@@ -184,7 +184,7 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
             const d3 d = st.d;
             double tbest = __builtin_inf();
             TravStats ts;
-            const int best = traverse<false, (MODE & kModeStats) != 0, kTraceBlock>(
+            const int best = traverse<false, (MODE & kModeStats) != 0, kTraceBlock, OVF>(
                 a.sc, lds_nodes, n_lds, o, d, st.excl, st.excl, a.tmin, tbest, stack, &ts);
             if (MODE & kModeStats) {
                 const int nd = a.max_depth + 1;
@@ -279,12 +279,18 @@ __global__ void finalize_db_kernel(const float* __restrict__ g, float* __restric
     db[i] = v > 0.0f ? 10.0f * log10f(v) : -__builtin_inff();
 }
 
+template <int MODE, bool OVF>
+void launch_depth(const SbrArgs& a, const MatTable& mats, int grid, hipStream_t s) {
+    if (a.depth == 0)
+        hipLaunchKernelGGL((sbr_bounce<MODE, true, OVF>), dim3(grid), dim3(kTraceBlock), 0, s, a, mats);
+    else
+        hipLaunchKernelGGL((sbr_bounce<MODE, false, OVF>), dim3(grid), dim3(kTraceBlock), 0, s, a, mats);
+}
+
 template <int MODE>
 hipError_t launch_mode(const SbrArgs& a, const MatTable& mats, int grid, hipStream_t s) {
-    if (a.depth == 0)
-        hipLaunchKernelGGL((sbr_bounce<MODE, true>), dim3(grid), dim3(kTraceBlock), 0, s, a, mats);
-    else
-        hipLaunchKernelGGL((sbr_bounce<MODE, false>), dim3(grid), dim3(kTraceBlock), 0, s, a, mats);
+    if (a.sc.stack_need > kStack) launch_depth<MODE, true>(a, mats, grid, s);
+    else launch_depth<MODE, false>(a, mats, grid, s);
     return hipGetLastError();
 }
 
