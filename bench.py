@@ -310,6 +310,34 @@ def extras(rt, ctx, scene, w, torch):
     torch.cuda.synchronize()
     res["grad_ms"] = round((time.perf_counter() - t0) * 1e3 / 10, 4)
     res["grad_paths"] = int((od["depth"][0] >= 0).sum())
+    # large procedural city: coverage map at full size
+    c = sg.city_workload()
+    t0 = time.perf_counter()
+    sc = rt.Scene.from_scenegen(ctx, c.scene)
+    scene_s = time.perf_counter() - t0
+    pc = rt.TraceParams(c.scene.freq_hz, c.max_depth, c.num_rays)
+    dev = ctx.torch_device
+    outc = {"gain": torch.empty((c.grid.ny, c.grid.nx), dtype=torch.float32, device=dev),
+            "hits": torch.empty((c.grid.ny, c.grid.nx), dtype=torch.int32, device=dev),
+            "gain_db": torch.empty((c.grid.ny, c.grid.nx), dtype=torch.float32, device=dev),
+            "ray_bounces": torch.empty(c.max_depth + 1, dtype=torch.int64, device=dev)}
+    rt.coverage_map(ctx, sc, pc, c.tx[0], c.grid, out=outc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        rt.coverage_map(ctx, sc, pc, c.tx[0], c.grid, out=outc)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / 2
+    rbc = int(outc["ray_bounces"].sum())
+    info = sc.info()
+    res["city"] = {"workload": "large city coverage map: 50x50 blocks (%d tris), 1e8 rays, depth 5, 2000x2000 "
+                               "cells of 1 m, 28 GHz, TR 38.901 tx" % info["num_triangles"],
+                   "coverage_map_ms": round(ms, 3), "ray_bounces": rbc,
+                   "M_ray_bounces_per_s": round(rbc / (ms / 1e3) / 1e6, 1),
+                   "bvh_nodes": info["bvh_nodes"], "bvh_build_ms": round(info["build_ms"], 1),
+                   "scene_create_s": round(scene_s, 2)}
+    log("bench: city %s" % res["city"])
+    sc.close()
     return res
 
 

@@ -31,7 +31,7 @@ def test_scene_faces_match_oracle_grouping():
         assert info["bvh_depth"] <= 30
 
 
-@pytest.mark.parametrize("case", ["toy", "urban_stride", "urban_full_small", "city_stride"])
+@pytest.mark.parametrize("case", ["toy", "urban_stride", "urban_full_small", "city_stride", "city_full_stride"])
 def test_hits_match_oracle(case):
     m = lib()
     if case == "toy":
@@ -43,9 +43,12 @@ def test_hits_match_oracle(case):
     elif case == "urban_full_small":
         w = sg.urban_workload(num_rays=150_001)          # whole lattice: coherent band order on
         p = params(w)
-    else:
+    elif case == "city_stride":
         w = sg.city_workload(num_rays=100_000_000, blocks=12)
         p = params(w, ray_begin=11, ray_stride=2003)     # 49 925 rays of the 1e8 lattice, 5 bounces
+    else:
+        w = sg.city_workload()                           # the full large city: 50x50 blocks, ~220k triangles
+        p = params(w, ray_begin=13, ray_stride=40009)    # 2 500 rays of the 1e8 lattice, 5 bounces
     tri, t = m.trace_record(ctx(), scene(w.scene), p, w.tx[0])
     orc = sbr.trace(w.scene, w.tx[0], oracle_params(p), record=True)
     compared, excluded = compare_hits(tri.cpu().numpy(), t.cpu().numpy(), orc)
@@ -137,6 +140,35 @@ def test_coverage_full_lattice_equals_sum_of_sublattices():
     rel = ((g_full - g_sum).abs() / g_sum.clamp_min(1e-30))[nz]
     assert float(rel.max()) < 1e-4
     assert int(h_full.sum()) > 1_000_000
+
+
+def test_city_coverage_full_equals_sum_of_sublattices():
+    """Large city at its full size (about 220k triangles, 1e8 rays, 5 bounces,
+    2000x2000 cells): the map equals the sum of the maps of 4 disjoint
+    sub-lattices (hit counts exactly, gains to fp32 atomic ordering)."""
+    m = lib()
+    w = sg.city_workload()
+    p = params(w)
+    sc = scene(w.scene)
+    assert sc.info()["num_triangles"] > 200_000
+    full = m.coverage_map(ctx(), sc, p, w.tx[0], w.grid)
+    g_full = full["gain"].double()
+    h_full = full["hits"].clone()
+    rb_full = int(full["ray_bounces"].sum())
+    g_sum = torch.zeros_like(g_full)
+    h_sum = torch.zeros_like(h_full)
+    rb = 0
+    for b in range(4):
+        o = m.coverage_map(ctx(), sc, params(w, ray_begin=b, ray_stride=4), w.tx[0], w.grid)
+        g_sum += o["gain"].double()
+        h_sum += o["hits"]
+        rb += int(o["ray_bounces"].sum())
+    assert torch.equal(h_full, h_sum)
+    assert rb == rb_full and rb > 100_000_000
+    nz = h_full > 0
+    rel = ((g_full - g_sum).abs() / g_sum.clamp_min(1e-30))[nz]
+    assert float(rel.max()) < 1e-4
+    assert int(nz.sum()) > 100_000
 
 
 def test_argument_errors_are_reported():
