@@ -84,7 +84,20 @@ typedef struct {
     double t_min;             /* minimum accepted hit distance [m], >= 0 (1e-4 typical) */
     int64_t ray_begin;        /* trace rays ray_begin, ray_begin + ray_stride, ... < N */
     int64_t ray_stride;       /* >= 1 (1 = all rays from ray_begin) */
+    int32_t cand_mode;        /* rt_compute_paths candidates: RT_CAND_ALL or RT_CAND_SPHERE */
+    float sphere_kappa;       /* RT_CAND_SPHERE: reception-sphere factor kappa > 0 (2 typical) */
 } rt_trace_params;
+
+/* Candidate modes of rt_compute_paths.  RT_CAND_ALL (0): every distinct face
+ * sequence found by the rays is tried for every receiver (Sec. II-B).
+ * RT_CAND_SPHERE (1): a sequence is tried for a receiver only when a ray
+ * segment with that sequence of reflections before it passes the receiver
+ * within kappa (s + t) sqrt(4 pi / N), s being the path length before the
+ * segment and t the distance along it to the closest approach (clamped to
+ * [0, hit]): the ray tube of the lattice widened by kappa.  Needs max_depth
+ * <= 5 and fewer than 2^24 faces. */
+#define RT_CAND_ALL     0
+#define RT_CAND_SPHERE  1
 
 /* Horizontal coverage grid: cell (ix, iy) covers [x0 + ix*cell, x0 + (ix+1)*cell)
  * x [y0 + iy*cell, y0 + (iy+1)*cell) at height z; maps are stored [ny][nx]. */

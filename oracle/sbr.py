@@ -78,7 +78,7 @@ def _cross_plane(o, d, t_hit, grid):
 
 
 def trace(scene, tx, params: TraceParams, grid=None, rx_ant=None, record=False, delta=1e-6,
-          candidates=False, threads=None, geo=None, idx=None) -> TraceResult:
+          candidates=False, threads=None, geo=None, idx=None, sphere=None) -> TraceResult:
     """Trace the (sub)set of lattice rays of one transmitter.
 
     With ``grid`` the coverage map (gain, hits) is accumulated; ``record``
@@ -86,6 +86,16 @@ def trace(scene, tx, params: TraceParams, grid=None, rx_ant=None, record=False, 
     face sequence of every hit prefix of length 1..max_depth.  ``idx``
     (optional) lists the lattice indices to trace instead of the params'
     sub-lattice.
+
+    ``sphere = (rx_positions [nrx][3], kappa)`` collects reception-sphere
+    candidates: the sequence of the reflections before a segment becomes a
+    candidate of receiver R when the segment's closest approach to R, at
+    t* = clamp((R - o) . d, 0, t_hit), lies within kappa (s + t*) sqrt(4 pi / n)
+    of R (s the path length before the segment, n the number of traced rays):
+    ``res.sphere_pairs[r]`` is the set of sequences of receiver r,
+    ``res.sphere_sure[r]`` those accepted by a ray that never passed within
+    delta of an edge, away from the radius, and ``res.sphere_borderline`` the
+    (r, sequence) pairs decided within 1e-6 relative of the radius by some ray.
     """
     geo = geo or Geometry(scene)
     lam = em.wavelength(geo.freq)
@@ -105,8 +115,15 @@ def trace(scene, tx, params: TraceParams, grid=None, rx_ant=None, record=False, 
         cell_ray = []
         scale = (lam / (4.0 * np.pi)) ** 2 * (4.0 * np.pi / N) / (grid.cell * grid.cell)
         rx_ant = rx_ant or _iso()
-    seqs = [() for _ in range(n)] if candidates else None
+    seqs = [() for _ in range(n)] if (candidates or sphere is not None) else None
     cand = set() if candidates else None
+    if sphere is not None:
+        rx_pos = np.asarray(sphere[0], dtype=np.float64).reshape(-1, 3)
+        sk = float(sphere[1]) * np.sqrt(4.0 * np.pi / n)
+        path_len = np.zeros(n)
+        res.sphere_pairs = [set() for _ in range(rx_pos.shape[0])]
+        res.sphere_sure = [set() for _ in range(rx_pos.shape[0])]
+        res.sphere_borderline = set()
     eta_m = em.eta(geo.materials[:, 0], geo.materials[:, 1], geo.freq)
     pec_m = ~np.isfinite(geo.materials[:, 1])
 
@@ -163,6 +180,8 @@ def trace(scene, tx, params: TraceParams, grid=None, rx_ant=None, record=False, 
             span = valid & (tcu > -delta) & (tcu < t + delta)
             borderline = span & (border | (np.abs(tcu) < delta) | (np.abs(tcu - t) < delta))
             res.ambiguous[alive[borderline]] = True
+        if sphere is not None and k >= 1:
+            _sphere_pairs(res, rx_pos, sk, o, d, t, path_len[alive], [seqs[r] for r in alive], res.ambiguous[alive])
         if k == params.max_depth:
             break
         hit = tri >= 0
@@ -177,17 +196,44 @@ def trace(scene, tx, params: TraceParams, grid=None, rx_ant=None, record=False, 
         E = em.transfer(E, d, d_r, n_f, r_perp, r_par)
         o, d = p, d_r
         excl = geo.face[tri].astype(np.int32)
-        if candidates:
+        if sphere is not None:
+            path_len[alive] += t
+        if seqs is not None:
             for j, r in enumerate(alive):
                 s = seqs[r] + (int(excl[j]),)
                 seqs[r] = s
-                cand.add(s)
+                if candidates:
+                    cand.add(s)
     if grid is not None:
         res.gain = gain.reshape(grid.ny, grid.nx)
         res.hits = hits.reshape(grid.ny, grid.nx)
         res.cell_rays = cell_ray
     res.candidates = cand
     return res
+
+
+def _sphere_pairs(res, R, sk, o, d, t, s_len, seq, amb_ray, chunk=4096):
+    """Receiver spheres passed by the segments o + t' d, 0 <= t' <= t.  A pair
+    is also "sure" when a ray that never came within delta of an edge accepted
+    it away from the radius."""
+    for c0 in range(0, o.shape[0], chunk):
+        oo, dd, tt, ss = o[c0:c0 + chunk], d[c0:c0 + chunk], t[c0:c0 + chunk], s_len[c0:c0 + chunk]
+        w = R[None, :, :] - oo[:, None, :]
+        ts = np.einsum("mrk,mk->mr", w, dd)
+        ts = np.minimum(np.maximum(ts, 0.0), tt[:, None])
+        q = oo[:, None, :] + ts[..., None] * dd[:, None, :] - R[None, :, :]
+        dist = np.sqrt(np.einsum("mrk,mrk->mr", q, q))
+        rad = sk * (ss[:, None] + ts)
+        acc = dist <= rad
+        border = np.abs(dist - rad) <= 1e-6 * rad
+        for mi, ri in zip(*np.nonzero(acc | border)):
+            sq = seq[c0 + mi]
+            if acc[mi, ri]:
+                res.sphere_pairs[ri].add(sq)
+                if not border[mi, ri] and not amb_ray[c0 + mi]:
+                    res.sphere_sure[ri].add(sq)
+            if border[mi, ri]:
+                res.sphere_borderline.add((int(ri), sq))
 
 
 def _iso():

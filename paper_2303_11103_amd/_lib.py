@@ -35,7 +35,7 @@ class rt_device(ctypes.Structure):
 class rt_trace_params(ctypes.Structure):
     _fields_ = [("freq_hz", ctypes.c_double), ("max_depth", ctypes.c_int32), ("max_paths_per_rx", ctypes.c_int32),
                 ("num_rays", ctypes.c_int64), ("t_min", ctypes.c_double), ("ray_begin", ctypes.c_int64),
-                ("ray_stride", ctypes.c_int64)]
+                ("ray_stride", ctypes.c_int64), ("cand_mode", ctypes.c_int32), ("sphere_kappa", ctypes.c_float)]
 
 
 class rt_grid(ctypes.Structure):

@@ -62,6 +62,9 @@ struct rt_ctx {
     DevBuf queue[2];
     DevBuf counters;   // uint32 [depth + 1][kQueueRegions] queue region counts
     DevBuf table;      // candidate prefix table
+    DevBuf pairs;      // reception-sphere (receiver, prefix slot) set
+    DevBuf pair_rx;    // receiver of each extracted pair
+    DevBuf rgrid;      // receiver grid: cell starts then receiver lists
     DevBuf cands;
     DevBuf rx;         // double [nrx][3]
     DevBuf rx_ant;     // Antenna [nrx]
@@ -114,6 +117,10 @@ rt_status check_params(const rt_trace_params* p) {
     if (p->ray_stride < 1) return fail(RT_ERR_ARG, "ray_stride must be >= 1");
     int64_t count = (p->num_rays - p->ray_begin + p->ray_stride - 1) / p->ray_stride;
     if (count >= (int64_t(1) << 31)) return fail(RT_ERR_ARG, "more than 2^31 - 1 traced rays per call");
+    if (p->cand_mode != RT_CAND_ALL && p->cand_mode != RT_CAND_SPHERE)
+        return fail(RT_ERR_ARG, "cand_mode must be RT_CAND_ALL or RT_CAND_SPHERE");
+    if (p->cand_mode == RT_CAND_SPHERE && (!(p->sphere_kappa > 0) || !std::isfinite(p->sphere_kappa)))
+        return fail(RT_ERR_ARG, "sphere_kappa must be positive");
     return RT_OK;
 }
 
@@ -187,7 +194,7 @@ int grid_for(const rt_ctx* c) { return c->num_cu * 4; }
 rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx, const rt_device* rx_ant,
                   const rt_grid* g, int mode, float* gain, uint32_t* hits, uint64_t* stats, int32_t* rec_tri,
                   double* rec_t, uint64_t* table, uint64_t table_mask, uint32_t* overflow,
-                  uint64_t* work = nullptr) {
+                  uint64_t* work = nullptr, const rt::SbrArgs* sphere = nullptr) {
     const int64_t count = traced_count(p);
     const int64_t chunk = std::min(count, kChunk);
     const int64_t region_cap = rt::sbr_region_capacity(chunk, grid_for(c));
@@ -230,6 +237,22 @@ rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_dev
     a.table = table;
     a.table_mask = table_mask;
     a.overflow = overflow;
+    if (sphere) {
+        a.rx = sphere->rx;
+        a.cell_start = sphere->cell_start;
+        a.cell_rx = sphere->cell_rx;
+        a.rgx0 = sphere->rgx0;
+        a.rgy0 = sphere->rgy0;
+        a.rgcell = sphere->rgcell;
+        a.rgnx = sphere->rgnx;
+        a.rgny = sphere->rgny;
+        a.rz_lo = sphere->rz_lo;
+        a.rz_hi = sphere->rz_hi;
+        a.sphere_k = sphere->sphere_k;
+        a.pairs = sphere->pairs;
+        a.pairs_mask = sphere->pairs_mask;
+        a.pairs_overflow = sphere->pairs_overflow;
+    }
     uint32_t* cnt = (uint32_t*)c->counters.p;
     for (int64_t pos0 = 0; pos0 < count; pos0 += chunk) {
         a.pos0 = pos0;
@@ -292,7 +315,8 @@ rt_status rt_destroy(rt_ctx* c) {
     if (!c) return RT_OK;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (DevBuf* b : {&c->queue[0], &c->queue[1], &c->counters, &c->table, &c->cands, &c->rx, &c->rx_ant, &c->paths})
+    for (DevBuf* b : {&c->queue[0], &c->queue[1], &c->counters, &c->table, &c->cands, &c->rx, &c->rx_ant, &c->paths,
+                      &c->pairs, &c->pair_rx, &c->rgrid})
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
@@ -496,21 +520,33 @@ rt_status rt_compute_paths(rt_ctx* c, rt_scene* s, const rt_trace_params* p, con
     for (int i = 0; i < nrx; ++i)
         if ((st = check_device(rx + i, "rx", s->host.max_abs)) != RT_OK) return st;
     RT_HIP(hipSetDevice(c->device));
+    const bool sphere = p->cand_mode == RT_CAND_SPHERE && p->max_depth > 0;
+    if (sphere) {
+        if (p->max_depth > rt::kSphereMaxDepth) return fail(RT_ERR_ARG, "reception-sphere mode needs max_depth <= 5");
+        if (s->host.num_faces >= rt::kSphereMaxFaces)
+            return fail(RT_ERR_ARG, "reception-sphere mode needs fewer than 2^24 faces");
+    }
     const int P = p->max_paths_per_rx;
     const int fd = std::max(p->max_depth, 1);
     const int64_t count = traced_count(p);
-    // candidate prefix table: power of two >= 2 * (rays * depth), capped at 2^26
+    // candidate prefix table: power of two >= 2 * (rays * depth), capped at 2^26;
+    // in sphere mode it holds only the sequences that reach a receiver
     uint64_t want = std::max<uint64_t>(1024, 2ull * (uint64_t)count * (uint64_t)std::max(p->max_depth, 1));
+    if (sphere) want = std::min<uint64_t>(want, 1ull << 22);
     uint64_t cap = 1024;
     while (cap < want && cap < (1ull << 26)) cap <<= 1;
     RT_HIP(ensure(c->table, cap * sizeof(uint64_t)));
-    const uint32_t max_cand = (uint32_t)std::min<uint64_t>(cap, 1ull << 24);
+    // sphere mode: (receiver, sequence) pair set of 16 entries per path slot of every receiver
+    uint64_t pcap = 1024;
+    if (sphere)
+        while (pcap < 16ull * (uint64_t)nrx * (uint64_t)P && pcap < (1ull << 26)) pcap <<= 1;
+    const uint32_t max_cand = (uint32_t)std::min<uint64_t>(sphere ? pcap : cap, 1ull << 24);
     RT_HIP(ensure(c->cands, (size_t)max_cand * sizeof(rt::Cand)));
     RT_HIP(ensure(c->rx, (size_t)nrx * 3 * sizeof(double)));
     RT_HIP(ensure(c->rx_ant, (size_t)nrx * sizeof(rt::Antenna)));
     const size_t per = (size_t)nrx * P;
     const size_t rec_bytes = per * (2 + 8 + 1 + 2 + 2) * sizeof(float) + per * (1 + fd) * sizeof(int32_t) +
-                             (size_t)nrx * sizeof(uint32_t) + 2 * sizeof(uint32_t);
+                             (size_t)nrx * sizeof(uint32_t) + 3 * sizeof(uint32_t);
     RT_HIP(ensure(c->paths, rec_bytes));
     std::vector<double> rxp(3 * (size_t)nrx);
     std::vector<rt::Antenna> rxa(nrx);
@@ -520,6 +556,84 @@ rt_status rt_compute_paths(rt_ctx* c, rt_scene* s, const rt_trace_params* p, con
     }
     RT_HIP(hipMemcpy(c->rx.p, rxp.data(), rxp.size() * sizeof(double), hipMemcpyHostToDevice));
     RT_HIP(hipMemcpy(c->rx_ant.p, rxa.data(), rxa.size() * sizeof(rt::Antenna), hipMemcpyHostToDevice));
+    rt::SbrArgs sph{};
+    if (sphere) {
+        // every accepted pair has a path length below (max_depth + 1) times the
+        // diagonal of the box holding the scene, the transmitters and the
+        // receivers, so no sphere is wider than r_ins
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        auto grow = [&](double x, double y, double z) {
+            const double v[3] = {x, y, z};
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = std::min(lo[k], v[k]);
+                hi[k] = std::max(hi[k], v[k]);
+            }
+        };
+        for (const rt::Tri& tr : s->host.tris) {
+            grow(tr.v0[0], tr.v0[1], tr.v0[2]);
+            grow(tr.v0[0] + tr.e1[0], tr.v0[1] + tr.e1[1], tr.v0[2] + tr.e1[2]);
+            grow(tr.v0[0] + tr.e2[0], tr.v0[1] + tr.e2[1], tr.v0[2] + tr.e2[2]);
+        }
+        for (int i = 0; i < ntx; ++i) grow(tx[i].pos[0], tx[i].pos[1], tx[i].pos[2]);
+        double rlo[3] = {1e300, 1e300, 1e300}, rhi[3] = {-1e300, -1e300, -1e300};
+        for (int i = 0; i < nrx; ++i) {
+            grow(rxp[3 * i], rxp[3 * i + 1], rxp[3 * i + 2]);
+            for (int k = 0; k < 3; ++k) {
+                rlo[k] = std::min(rlo[k], rxp[3 * i + k]);
+                rhi[k] = std::max(rhi[k], rxp[3 * i + k]);
+            }
+        }
+        const double diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                      (hi[2] - lo[2]) * (hi[2] - lo[2]));
+        sph.sphere_k = (double)p->sphere_kappa * std::sqrt(4.0 * M_PI / (double)count);
+        const double r_ins = sph.sphere_k * (p->max_depth + 1) * diag * (1.0 + 1e-9) + 1e-9;
+        const double ext = std::max(rhi[0] - rlo[0], rhi[1] - rlo[1]) + 2.0 * r_ins;
+        const double cell = std::max(2.0 * r_ins, ext / 1024.0);
+        sph.rgx0 = rlo[0] - r_ins;
+        sph.rgy0 = rlo[1] - r_ins;
+        sph.rgcell = cell;
+        sph.rgnx = std::max(1, (int)std::ceil((rhi[0] - rlo[0] + 2.0 * r_ins) / cell));
+        sph.rgny = std::max(1, (int)std::ceil((rhi[1] - rlo[1] + 2.0 * r_ins) / cell));
+        sph.rz_lo = rlo[2] - r_ins;
+        sph.rz_hi = rhi[2] + r_ins;
+        // CSR lists: receiver r in every cell that meets the square of half-side r_ins around it
+        const int ncell = sph.rgnx * sph.rgny;
+        std::vector<int32_t> start(ncell + 1, 0), items;
+        auto cell_range = [&](double v, double v0, int n, int& a0, int& a1) {
+            a0 = std::min(std::max((int)std::floor((v - r_ins - v0) / cell), 0), n - 1);
+            a1 = std::min(std::max((int)std::floor((v + r_ins - v0) / cell), 0), n - 1);
+        };
+        for (int pass = 0; pass < 2; ++pass) {
+            std::vector<int32_t> fill(start.begin(), start.end() - 1);
+            for (int i = 0; i < nrx; ++i) {
+                int x0, x1, y0, y1;
+                cell_range(rxp[3 * i], sph.rgx0, sph.rgnx, x0, x1);
+                cell_range(rxp[3 * i + 1], sph.rgy0, sph.rgny, y0, y1);
+                for (int iy = y0; iy <= y1; ++iy)
+                    for (int ix = x0; ix <= x1; ++ix) {
+                        const int cc = iy * sph.rgnx + ix;
+                        if (pass == 0) ++start[cc + 1];
+                        else items[fill[cc]++] = i;
+                    }
+            }
+            if (pass == 0) {
+                for (int k = 0; k < ncell; ++k) start[k + 1] += start[k];
+                items.assign(start[ncell], 0);
+            }
+        }
+        RT_HIP(ensure(c->rgrid, (start.size() + items.size()) * sizeof(int32_t)));
+        RT_HIP(hipMemcpy(c->rgrid.p, start.data(), start.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        if (!items.empty())
+            RT_HIP(hipMemcpy((int32_t*)c->rgrid.p + start.size(), items.data(), items.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice));
+        sph.rx = (const double*)c->rx.p;
+        sph.cell_start = (const int32_t*)c->rgrid.p;
+        sph.cell_rx = (const int32_t*)c->rgrid.p + start.size();
+        RT_HIP(ensure(c->pairs, pcap * sizeof(uint64_t)));
+        RT_HIP(ensure(c->pair_rx, (size_t)max_cand * sizeof(int32_t)));
+        sph.pairs = (uint64_t*)c->pairs.p;
+        sph.pairs_mask = pcap - 1;
+    }
     char* base = (char*)c->paths.p;
     rt::PathArgs pa{};
     pa.sc = s->dev;
@@ -529,6 +643,7 @@ rt_status rt_compute_paths(rt_ctx* c, rt_scene* s, const rt_trace_params* p, con
     pa.rx_ant = (const rt::Antenna*)c->rx_ant.p;
     pa.nrx = nrx;
     pa.cands = (const rt::Cand*)c->cands.p;
+    pa.pair_rx = sphere ? (const int32_t*)c->pair_rx.p : nullptr;
     pa.max_depth = p->max_depth;
     pa.P = P;
     pa.fd = fd;
@@ -540,31 +655,41 @@ rt_status rt_compute_paths(rt_ctx* c, rt_scene* s, const rt_trace_params* p, con
     pa.depth = (int32_t*)base; base += per * sizeof(int32_t);
     pa.faces = (int32_t*)base; base += per * fd * sizeof(int32_t);
     pa.counts = (uint32_t*)base; base += (size_t)nrx * sizeof(uint32_t);
-    uint32_t* ncand = (uint32_t*)base;       // [0] candidates, [1] table overflow
+    uint32_t* ncand = (uint32_t*)base;       // [0] candidates, [1] table overflow, [2] pair-set overflow
     pa.ncand = ncand;
+    sph.pairs_overflow = ncand + 2;
     rt::MatTable mats = make_mats(s, p->freq_hz);
     int worst = 0;
     std::vector<int32_t> counts_h(nrx);
     for (int t = 0; t < ntx; ++t) {
         RT_HIP(hipMemsetAsync(c->table.p, 0xff, cap * sizeof(uint64_t), c->stream));
-        RT_HIP(hipMemsetAsync(ncand, 0, 2 * sizeof(uint32_t), c->stream));
+        if (sphere) RT_HIP(hipMemsetAsync(c->pairs.p, 0xff, pcap * sizeof(uint64_t), c->stream));
+        RT_HIP(hipMemsetAsync(ncand, 0, 3 * sizeof(uint32_t), c->stream));
         RT_HIP(hipMemsetAsync(pa.counts, 0, (size_t)nrx * sizeof(uint32_t), c->stream));
-        if (p->max_depth > 0) {
+        if (sphere) {
+            st = run_sbr(c, s, p, tx + t, nullptr, nullptr, rt::kModeSphere, nullptr, nullptr, nullptr, nullptr,
+                         nullptr, (uint64_t*)c->table.p, cap - 1, ncand + 1, nullptr, &sph);
+            if (st != RT_OK) return st;
+            RT_HIP(rt::launch_extract_pairs((const uint64_t*)c->pairs.p, pcap, (const uint64_t*)c->table.p,
+                                            (rt::Cand*)c->cands.p, (int32_t*)c->pair_rx.p, ncand, max_cand,
+                                            c->stream));
+        } else if (p->max_depth > 0) {
             st = run_sbr(c, s, p, tx + t, nullptr, nullptr, rt::kModeCandidates, nullptr, nullptr, nullptr, nullptr,
                          nullptr, (uint64_t*)c->table.p, cap - 1, ncand + 1);
             if (st != RT_OK) return st;
             RT_HIP(rt::launch_extract_candidates((const uint64_t*)c->table.p, cap, p->max_depth,
                                                  (rt::Cand*)c->cands.p, ncand, max_cand, c->stream));
         }
-        uint32_t hc[2] = {0, 0};
+        uint32_t hc[3] = {0, 0, 0};
         RT_HIP(hipMemcpyAsync(hc, ncand, sizeof(hc), hipMemcpyDeviceToHost, c->stream));
         RT_HIP(hipStreamSynchronize(c->stream));
         if (hc[1]) return fail(RT_ERR_CAPACITY, "candidate table overflow: too many distinct face sequences");
-        if (hc[0] > max_cand) return fail(RT_ERR_CAPACITY, "more than 2^24 candidate face sequences");
+        if (hc[2]) return fail(RT_ERR_CAPACITY, "reception-sphere pair set overflow");
+        if (hc[0] > max_cand) return fail(RT_ERR_CAPACITY, "more than 2^24 candidates");
         c->last_candidates = hc[0];
         for (int k = 0; k < 3; ++k) pa.tx[k] = tx[t].pos[k];
         pa.tx_ant = make_antenna(tx + t);
-        const int64_t items = (int64_t)nrx * ((int64_t)hc[0] + 1);
+        const int64_t items = sphere ? (int64_t)nrx + (int64_t)hc[0] : (int64_t)nrx * ((int64_t)hc[0] + 1);
         RT_HIP(rt::launch_image_paths(pa, mats, items, c->stream));
         const size_t off = (size_t)t * per;
         RT_HIP(rt::launch_sort_paths(pa, nrx, a + 2 * off, T + 8 * off, tau + off, aod + 2 * off, aoa + 2 * off,

@@ -14,9 +14,10 @@ struct alignas(16) RayState {
     double d[3];    // unit direction (fp64)
     float E[6];     // field, complex Cartesian (re, im) per axis
     int32_t excl;   // face of the last reflection (-1 at the transmitter)
-    int32_t prefix; // candidate-table slot of the face sequence so far (-1 none)
-    int32_t ray;    // lattice position j: ray index = begin + j * stride
-    int32_t pad;
+    int32_t prefix; // candidate-table slot of the face sequence so far (-1 none);
+                    // reception-sphere mode: path length so far (float bits)
+    int32_t ray;    // lattice position j: ray index = begin + j * stride;
+    int32_t pad[3]; // reception-sphere mode: ray, pad = the face sequence, 24 bits per face
 };
 static_assert(sizeof(RayState) == 96, "ray state size");
 
@@ -72,9 +73,26 @@ struct SbrArgs {
     uint64_t* table;
     uint64_t table_mask;
     uint32_t* overflow;
+    // reception-sphere mode: receivers binned on an xy grid (each receiver in
+    // every cell within r_ins of it, CSR lists), the heights they span widened
+    // by r_ins, and the set of (receiver, prefix slot) pairs
+    const double* rx;            // [nrx][3]
+    const int32_t* cell_start;   // [rnx * rny + 1]
+    const int32_t* cell_rx;
+    double rgx0, rgy0, rgcell;
+    int32_t rgnx, rgny;
+    double rz_lo, rz_hi;
+    double sphere_k;             // kappa sqrt(4 pi / N): sphere radius per metre of path
+    uint64_t* pairs;
+    uint64_t pairs_mask;
+    uint32_t* pairs_overflow;
 };
 
-enum : int { kModeCoverage = 1, kModeRecord = 2, kModeCandidates = 4, kModeStats = 8 };
+// kModeSphere: rays carry their face sequence and path length; segments after
+// the first reflection record (receiver, sequence) pairs within the spheres.
+enum : int { kModeCoverage = 1, kModeRecord = 2, kModeCandidates = 4, kModeStats = 8, kModeSphere = 16 };
+constexpr int kSphereMaxDepth = 5;       // faces packed 24 bits each into 128 bits
+constexpr int32_t kSphereMaxFaces = 1 << 24;
 
 // Rays one queue region must hold for a bounce launch of `grid` blocks over
 // at most `chunk` rays: the waves of a region (every kQueueRegions-th) times
@@ -100,6 +118,7 @@ struct PathArgs {
     int32_t nrx;
     const Cand* cands;
     const uint32_t* ncand;   // device count
+    const int32_t* pair_rx;  // reception-sphere mode: receiver of candidate j (null: every receiver)
     int32_t max_depth;
     int32_t P;               // slots per rx
     uint32_t* counts;        // [nrx] paths found
@@ -115,6 +134,8 @@ struct PathArgs {
 };
 
 hipError_t launch_paths_power(const float* a, const int32_t* depth, int64_t n, int P, double* power, hipStream_t s);
+hipError_t launch_extract_pairs(const uint64_t* pairs, uint64_t pairs_cap, const uint64_t* table, Cand* out,
+                                int32_t* out_rx, uint32_t* count, uint32_t max_out, hipStream_t s);
 hipError_t launch_extract_candidates(const uint64_t* table, uint64_t cap, int32_t max_depth, Cand* out,
                                      uint32_t* count, uint32_t max_out, hipStream_t s);
 hipError_t launch_image_paths(const PathArgs& a, const MatTable& mats, int64_t max_items, hipStream_t s);

@@ -41,6 +41,37 @@ __global__ void extract_candidates_kernel(const uint64_t* __restrict__ table, ui
     if (at < max_out) out[at] = c;
 }
 
+// Reception-sphere pairs: every (receiver, prefix slot) of the pair set
+// becomes a candidate (face sequence rebuilt from the prefix table) tied to
+// its receiver.
+__global__ void extract_pairs_kernel(const uint64_t* __restrict__ pairs, uint64_t pairs_cap,
+                                     const uint64_t* __restrict__ table, Cand* __restrict__ out,
+                                     int32_t* __restrict__ out_rx, uint32_t* count, uint32_t max_out) {
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= pairs_cap) return;
+    const uint64_t pk = pairs[s];
+    if (pk == kEmptyKey) return;
+    const int32_t r = (int32_t)(pk >> 32);
+    const int32_t slot = (int32_t)(uint32_t)(pk & 0xffffffffull);
+    int faces_rev[kMaxK];
+    int k = 0;
+    uint64_t key = table[slot];
+    while (true) {
+        faces_rev[k++] = (int32_t)(uint32_t)(key & 0xffffffffull);
+        const int64_t parent = (int64_t)(key >> 32) - 1;
+        if (parent < 0 || k >= kMaxK) break;
+        key = table[parent];
+    }
+    Cand c;
+    c.depth = k;
+    for (int i = 0; i < kMaxK; ++i) c.faces[i] = i < k ? faces_rev[k - 1 - i] : -1;
+    const uint32_t at = atomicAdd(count, 1u);
+    if (at < max_out) {
+        out[at] = c;
+        out_rx[at] = r;
+    }
+}
+
 __device__ __forceinline__ d3 ld3(const double* p) { return d3{p[0], p[1], p[2]}; }
 
 __device__ __forceinline__ void sph_basis(d3 d, d3& th, d3& ph) {
@@ -93,11 +124,20 @@ __global__ __launch_bounds__(kBlock) void image_paths_kernel(PathArgs a, MatTabl
     const int n_lds = stage_nodes(a.sc, lds_nodes);
     const int64_t ncand = (int64_t)(*a.ncand);
     const int64_t per_rx = ncand + 1;
-    const int64_t total = per_rx * a.nrx;
+    // every candidate for every receiver, or (pair mode) the line of sight of
+    // every receiver followed by the receiver-tied candidates
+    const int64_t total = a.pair_rx ? a.nrx + ncand : per_rx * a.nrx;
     for (int64_t item = (int64_t)blockIdx.x * kBlock + threadIdx.x; item < total;
          item += (int64_t)gridDim.x * kBlock) {
-        const int r = (int)(item / per_rx);
-        const int64_t c = item - (int64_t)r * per_rx - 1;
+        int r;
+        int64_t c;
+        if (a.pair_rx) {
+            r = item < a.nrx ? (int)item : a.pair_rx[item - a.nrx];
+            c = item < a.nrx ? -1 : item - a.nrx;
+        } else {
+            r = (int)(item / per_rx);
+            c = item - (int64_t)r * per_rx - 1;
+        }
         int K = 0;
         int fc[kMaxK];
         if (c >= 0) {
@@ -291,6 +331,14 @@ hipError_t launch_extract_candidates(const uint64_t* table, uint64_t cap, int32_
     const uint64_t blocks = (cap + 255) / 256;
     hipLaunchKernelGGL(extract_candidates_kernel, dim3((unsigned)blocks), dim3(256), 0, s, table, cap, max_depth,
                        out, count, max_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_extract_pairs(const uint64_t* pairs, uint64_t pairs_cap, const uint64_t* table, Cand* out,
+                                int32_t* out_rx, uint32_t* count, uint32_t max_out, hipStream_t s) {
+    const uint64_t blocks = (pairs_cap + 255) / 256;
+    hipLaunchKernelGGL(extract_pairs_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pairs, pairs_cap, table, out,
+                       out_rx, count, max_out);
     return hipGetLastError();
 }
 

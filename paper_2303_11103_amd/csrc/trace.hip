@@ -83,13 +83,17 @@ __device__ int32_t cand_insert(uint64_t* table, uint64_t mask, int32_t parent, i
 }
 
 // Ray state in registers; loaded from / stored to the 96-byte queue record
-// with 16-byte vector accesses.
+// with 16-byte vector accesses.  In reception-sphere mode (SPH) the prefix
+// word holds the path length so far and the last 16 bytes the face sequence.
 struct Ray {
     d3 o, d;
     float E[6];
     int32_t excl, prefix, ray;
+    float s;          // SPH: path length before the current segment [m]
+    uint32_t seq[4];  // SPH: faces of the reflections so far, 24 bits each
 };
 
+template <bool SPH>
 __device__ __forceinline__ void load_ray(const RayState* __restrict__ p, Ray& r) {
     const double2* q = reinterpret_cast<const double2*>(p);
     const double2 a0 = q[0], a1 = q[1], a2 = q[2];
@@ -105,18 +109,133 @@ __device__ __forceinline__ void load_ray(const RayState* __restrict__ p, Ray& r)
     r.E[4] = __int_as_float(f1.x);
     r.E[5] = __int_as_float(f1.y);
     r.excl = f1.z;
-    r.prefix = f1.w;
-    r.ray = f2.x;
+    if (SPH) {
+        r.prefix = -1;
+        r.s = __int_as_float(f1.w);
+        r.ray = -1;
+        r.seq[0] = (uint32_t)f2.x;
+        r.seq[1] = (uint32_t)f2.y;
+        r.seq[2] = (uint32_t)f2.z;
+        r.seq[3] = (uint32_t)f2.w;
+    } else {
+        r.prefix = f1.w;
+        r.ray = f2.x;
+    }
 }
 
+template <bool SPH>
 __device__ __forceinline__ void store_ray(RayState* __restrict__ p, const Ray& r) {
     double2* q = reinterpret_cast<double2*>(p);
     q[0] = double2{r.o.x, r.o.y};
     q[1] = double2{r.o.z, r.d.x};
     q[2] = double2{r.d.y, r.d.z};
     reinterpret_cast<float4*>(p)[3] = float4{r.E[0], r.E[1], r.E[2], r.E[3]};
-    reinterpret_cast<int4*>(p)[4] = int4{__float_as_int(r.E[4]), __float_as_int(r.E[5]), r.excl, r.prefix};
-    reinterpret_cast<int4*>(p)[5] = int4{r.ray, 0, 0, 0};
+    if (SPH) {
+        reinterpret_cast<int4*>(p)[4] = int4{__float_as_int(r.E[4]), __float_as_int(r.E[5]), r.excl, __float_as_int(r.s)};
+        reinterpret_cast<int4*>(p)[5] = int4{(int)r.seq[0], (int)r.seq[1], (int)r.seq[2], (int)r.seq[3]};
+    } else {
+        reinterpret_cast<int4*>(p)[4] = int4{__float_as_int(r.E[4]), __float_as_int(r.E[5]), r.excl, r.prefix};
+        reinterpret_cast<int4*>(p)[5] = int4{r.ray, 0, 0, 0};
+    }
+}
+
+// Face i (0..4) of a packed sequence: bits [24 i, 24 i + 24) of the 128-bit
+// little-endian word seq (constant word indices, so the array stays in registers).
+__device__ __forceinline__ uint32_t get_face(const uint32_t seq[4], int i) {
+    switch (i) {
+        case 0: return seq[0] & 0xFFFFFFu;
+        case 1: return ((seq[0] >> 24) | (seq[1] << 8)) & 0xFFFFFFu;
+        case 2: return ((seq[1] >> 16) | (seq[2] << 16)) & 0xFFFFFFu;
+        case 3: return (seq[2] >> 8) & 0xFFFFFFu;
+        default: return seq[3] & 0xFFFFFFu;
+    }
+}
+
+__device__ __forceinline__ void put_face(uint32_t seq[4], int i, uint32_t f) {
+    switch (i) {
+        case 0: seq[0] |= f; break;
+        case 1: seq[0] |= f << 24; seq[1] |= f >> 8; break;
+        case 2: seq[1] |= f << 16; seq[2] |= f >> 16; break;
+        case 3: seq[2] |= f << 8; break;
+        default: seq[3] |= f; break;
+    }
+}
+
+// Insert (receiver, prefix slot) into the pair set.
+__device__ void pair_insert(const SbrArgs& a, int32_t r, int32_t slot) {
+    const uint64_t key = ((uint64_t)(uint32_t)r << 32) | (uint32_t)slot;
+    uint64_t h = mix32(key ^ 0x5bd1e995ull) & a.pairs_mask;
+    for (int probe = 0; probe < 256; ++probe) {
+        const uint64_t cur = __hip_atomic_load(a.pairs + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == key) return;
+        if (cur == kEmptyKey) {
+            const uint64_t prev = atomicCAS((unsigned long long*)(a.pairs + h), (unsigned long long)kEmptyKey,
+                                            (unsigned long long)key);
+            if (prev == kEmptyKey || prev == key) return;
+        }
+        h = (h + 1) & a.pairs_mask;
+    }
+    atomicOr(a.pairs_overflow, 1u);
+}
+
+// Receivers whose reception sphere the segment o + t d, 0 <= t <= tbest
+// (tbest = inf: no hit) passes: the closest approach t* = clamp((R - o) . d,
+// 0, tbest) lies within sphere_k (s + t*) of R.  The segment is clipped to
+// the receivers' height band and grid rectangle and walked cell by cell (2-D
+// DDA); the face sequence's prefix slot is inserted on the first pair.
+__device__ void sphere_pairs(const SbrArgs& a, const Ray& st, d3 o, d3 d, double tbest) {
+    double t0 = 0.0, t1 = tbest;
+    auto clip = [&](double oc, double dc, double lo, double hi) {
+        if (dc != 0.0) {
+            const double ta = (lo - oc) / dc, tb = (hi - oc) / dc;
+            t0 = fmax(t0, fmin(ta, tb));
+            t1 = fmin(t1, fmax(ta, tb));
+        } else if (oc < lo || oc > hi) {
+            t1 = -1.0;
+        }
+    };
+    clip(o.z, d.z, a.rz_lo, a.rz_hi);
+    clip(o.x, d.x, a.rgx0, a.rgx0 + a.rgnx * a.rgcell);
+    clip(o.y, d.y, a.rgy0, a.rgy0 + a.rgny * a.rgcell);
+    if (!(t0 <= t1)) return;
+    const double px = o.x + t0 * d.x - a.rgx0, py = o.y + t0 * d.y - a.rgy0;
+    int ix = min(max((int)floor(px / a.rgcell), 0), a.rgnx - 1);
+    int iy = min(max((int)floor(py / a.rgcell), 0), a.rgny - 1);
+    const int sx = d.x > 0.0 ? 1 : -1, sy = d.y > 0.0 ? 1 : -1;
+    double tnx = d.x != 0.0 ? (a.rgx0 + (ix + (d.x > 0.0 ? 1 : 0)) * a.rgcell - o.x) / d.x : __builtin_inf();
+    double tny = d.y != 0.0 ? (a.rgy0 + (iy + (d.y > 0.0 ? 1 : 0)) * a.rgcell - o.y) / d.y : __builtin_inf();
+    const double dtx = d.x != 0.0 ? a.rgcell / fabs(d.x) : __builtin_inf();
+    const double dty = d.y != 0.0 ? a.rgcell / fabs(d.y) : __builtin_inf();
+    int32_t slot = -3;  // not looked up yet
+    for (int it = 0; it < a.rgnx + a.rgny + 2; ++it) {
+        const int c = iy * a.rgnx + ix;
+        for (int j = a.cell_start[c]; j < a.cell_start[c + 1]; ++j) {
+            const int32_t r = a.cell_rx[j];
+            const d3 R{a.rx[3 * r], a.rx[3 * r + 1], a.rx[3 * r + 2]};
+            double ts = dot(sub(R, o), d);
+            ts = ts < 0.0 ? 0.0 : (ts > tbest ? tbest : ts);
+            const d3 w = sub(add(o, scale(d, ts)), R);
+            const double rad = a.sphere_k * ((double)st.s + ts);
+            if (dot(w, w) <= rad * rad) {
+                if (slot == -3) {
+                    slot = -1;
+                    for (int i = 0; i < a.depth && slot != -2; ++i)
+                        slot = cand_insert(a.table, a.table_mask, slot, (int32_t)get_face(st.seq, i), a.overflow);
+                }
+                if (slot >= 0) pair_insert(a, r, slot);
+            }
+        }
+        if (fmin(tnx, tny) > t1) break;
+        if (tnx < tny) {
+            ix += sx;
+            tnx += dtx;
+            if (ix < 0 || ix >= a.rgnx) break;
+        } else {
+            iy += sy;
+            tny += dty;
+            if (iy < 0 || iy >= a.rgny) break;
+        }
+    }
 }
 
 template <int MODE, bool FIRST, bool OVF>
@@ -177,8 +296,10 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
                 st.excl = -1;
                 st.prefix = -1;
                 st.ray = (int32_t)pos;
+                st.s = 0.0f;
+                st.seq[0] = st.seq[1] = st.seq[2] = st.seq[3] = 0u;
             } else {
-                load_ray(a.in + region_in * a.region_cap + region_off, st);
+                load_ray<(MODE & kModeSphere) != 0>(a.in + region_in * a.region_cap + region_off, st);
             }
             const d3 o = st.o;
             const d3 d = st.d;
@@ -192,6 +313,7 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
                 atomicAdd((unsigned long long*)&a.work[nd + a.depth], (unsigned long long)ts.nodes);
                 atomicAdd((unsigned long long*)&a.work[2 * nd + a.depth], (unsigned long long)ts.tris);
             }
+            if ((MODE & kModeSphere) && a.depth >= 1) sphere_pairs(a, st, o, d, tbest);
             if (MODE & kModeRecord) {
                 const int64_t at = (int64_t)a.depth * a.count + st.ray;
                 a.rec_tri[at] = best >= 0 ? a.sc.tris[best].orig : -1;
@@ -249,6 +371,10 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
                 if (MODE & kModeCandidates) {
                     if (st.prefix != -2) st.prefix = cand_insert(a.table, a.table_mask, st.prefix, sh.face, a.overflow);
                 }
+                if (MODE & kModeSphere) {
+                    st.s += (float)tbest;
+                    put_face(st.seq, a.depth, (uint32_t)sh.face);
+                }
             }
         }
         // wave-ballot compaction of the survivors into the next queue
@@ -258,7 +384,9 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
             const int region = (int)(wave % kQueueRegions);
             if (lane == 0) b = atomicAdd(a.out_count + region, (uint32_t)__popcll(m));
             b = __shfl(b, 0);
-            if (alive) store_ray(a.out + region * a.region_cap + b + __popcll(m & ((1ull << lane) - 1ull)), st);
+            if (alive)
+                store_ray<(MODE & kModeSphere) != 0>(
+                    a.out + region * a.region_cap + b + __popcll(m & ((1ull << lane) - 1ull)), st);
         }
     }
 }
@@ -307,6 +435,7 @@ hipError_t launch_sbr_bounce(const SbrArgs& a, const MatTable& mats, int mode, i
         case kModeCoverage: return launch_mode<kModeCoverage>(a, mats, grid, s);
         case kModeRecord: return launch_mode<kModeRecord>(a, mats, grid, s);
         case kModeCandidates: return launch_mode<kModeCandidates>(a, mats, grid, s);
+        case kModeSphere: return launch_mode<kModeSphere>(a, mats, grid, s);
         case kModeCoverage | kModeStats: return launch_mode<kModeCoverage | kModeStats>(a, mats, grid, s);
         default: return hipErrorInvalidValue;
     }

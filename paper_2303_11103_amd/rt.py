@@ -29,10 +29,13 @@ class TraceParams:
     ray_begin: int = 0
     ray_stride: int = 1
     max_paths_per_rx: int = 64
+    cand_mode: int = 0         # 0 = every candidate for every receiver, 1 = reception spheres
+    sphere_kappa: float = 2.0
 
     def c(self):
         return L.rt_trace_params(float(self.freq_hz), int(self.max_depth), int(self.max_paths_per_rx),
-                                 int(self.num_rays), float(self.t_min), int(self.ray_begin), int(self.ray_stride))
+                                 int(self.num_rays), float(self.t_min), int(self.ray_begin), int(self.ray_stride),
+                                 int(self.cand_mode), float(self.sphere_kappa))
 
     def traced(self) -> int:
         return (self.num_rays - self.ray_begin + self.ray_stride - 1) // self.ray_stride

@@ -35,7 +35,7 @@ def test_struct_layouts_match_header(tmp_path):
     # sizes implied by the header (natural alignment, x86-64)
     assert ctypes.sizeof(_lib.rt_material) == 8
     assert ctypes.sizeof(_lib.rt_device) == 32
-    assert ctypes.sizeof(_lib.rt_trace_params) == 48
+    assert ctypes.sizeof(_lib.rt_trace_params) == 56
     assert ctypes.sizeof(_lib.rt_grid) == 40
     assert ctypes.sizeof(_lib.rt_scene_info_t) == 40
     assert ctypes.sizeof(_lib.rt_mlp_config) == 72
@@ -50,7 +50,7 @@ def test_struct_layouts_match_header(tmp_path):
     c.write_text(src)
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
     vals = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()))
-    assert vals == [8, 32, 48, 40, 40, _lib.rt_trace_params.num_rays.offset, _lib.rt_grid.nx.offset, 72,
+    assert vals == [8, 32, 56, 40, 40, _lib.rt_trace_params.num_rays.offset, _lib.rt_grid.nx.offset, 72,
                     _lib.rt_mlp_config.ff_scale_cell.offset, _lib.rt_mlp_config.prior_freq_hz.offset]
 
 

@@ -84,6 +84,42 @@ def test_paths_match_oracle(case):
     assert np.all(tau[depth < 0] == -1.0) and np.all(o["a"][0].cpu().numpy()[depth < 0] == 0)
 
 
+def test_reception_sphere_paths_match_oracle():
+    """Reception-sphere candidates (kappa = 2) on the urban differentiation
+    case: every path the oracle finds from pairs it accepted for sure is found,
+    every GPU path is a valid path of the same rays' full candidate set with
+    the oracle's coefficients; the recall against the full set is reported."""
+    m = lib()
+    w = sg.diff_workload(num_rays=200_000)
+    w.rx = w.rx[:64]
+    p_all = params(w, max_paths_per_rx=64)
+    p_sph = params(w, max_paths_per_rx=64, cand_mode=1, sphere_kappa=2.0)
+    sc = scene(w.scene)
+    o_sph = m.compute_paths(ctx(), sc, p_sph, w.tx, w.rx)
+    pairs = m.last_candidate_count(ctx())
+    o_all = m.compute_paths(ctx(), sc, p_all, w.tx, w.rx)
+    g = geom.Geometry(w.scene)
+    rxp = np.array([r.pos for r in w.rx], dtype=np.float32).astype(np.float64)
+    r = sbr.trace(w.scene, w.tx[0], oracle_params(p_sph), candidates=True, sphere=(rxp, 2.0), geo=g)
+    full = image.paths(g, w.tx[0], w.rx, r.candidates)
+    gs, ga = _gpu_paths(o_sph), _gpu_paths(o_all)
+    found = total = sure_n = 0
+    for i in range(len(w.rx)):
+        allowed = {p.faces: p for p in full[i]}
+        sure = {p.faces for p in image.paths(g, w.tx[0], [w.rx[i]], r.sphere_sure[i])[0]}
+        assert set(gs[i]) <= set(allowed), (i, set(gs[i]) - set(allowed))
+        assert sure <= set(gs[i]), (i, sure - set(gs[i]))
+        for k, q in gs[i].items():
+            ref = allowed[k]
+            assert abs(q["a"] - ref.a) <= 1e-4 * abs(ref.a) and abs(q["tau"] - ref.tau) <= 1e-6 * ref.tau
+        found += len(set(gs[i]) & set(ga[i]))
+        total += len(ga[i])
+        sure_n += len(sure)
+    print("sphere pairs %d, paths %d of %d found by all candidates (recall %.3f), %d sure"
+          % (pairs, found, total, found / total, sure_n))
+    assert sure_n >= 40 and found >= 0.5 * total
+
+
 def test_paths_toy_recall_against_exhaustive_search():
     m = lib()
     w = sg.toy_workload()

@@ -435,3 +435,22 @@ def test_coverage_matches_image_method_away_from_edges():
         c = (grid.x0 + ix + 0.5, grid.y0 + iy + 0.5, 1.5)
         P = image.paths(g, tx, [_dev(c)], [(0,)])[0]
         assert abs(gain[iy, ix] / image.received_power(P) - 1) < 0.05
+
+
+def test_reception_sphere_scale_on_a_ground_plane():
+    """Reception spheres are ray tubes widened by kappa: over a single ground
+    plane, kappa = 2 gives every receiver the ground reflection (the lattice's
+    rays are no farther apart than the tube width), kappa = 0.05 gives almost
+    none; sphere candidates are always a subset of the ray prefixes."""
+    s = _ground_scene(300.0)
+    g = geom.Geometry(s)
+    tx = _dev((0, 0, 30))
+    rng = np.random.default_rng(7)
+    rx = np.concatenate([rng.uniform(-150, 150, size=(40, 2)), np.full((40, 1), 1.5)], 1)
+    p = sbr.TraceParams(50_000, 1)
+    wide = sbr.trace(s, tx, p, candidates=True, sphere=(rx, 2.0), geo=g)
+    ground = {(int(g.face[0]),)}
+    assert all(pairs == ground for pairs in wide.sphere_pairs)
+    narrow = sbr.trace(s, tx, p, sphere=(rx, 0.05), geo=g)
+    assert sum(len(x) for x in narrow.sphere_pairs) <= 5
+    assert all(x <= wide.candidates for x in narrow.sphere_pairs)
