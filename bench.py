@@ -336,6 +336,16 @@ def extras(rt, ctx, scene, w, torch):
                    "M_ray_bounces_per_s": round(rbc / (ms / 1e3) / 1e6, 1),
                    "bvh_nodes": info["bvh_nodes"], "bvh_build_ms": round(info["build_ms"], 1),
                    "scene_create_s": round(scene_s, 2)}
+    # paths to the 4096 street receivers with reception-sphere candidates
+    pp = rt.TraceParams(c.scene.freq_hz, c.max_depth, c.num_rays, max_paths_per_rx=256, cand_mode=1,
+                        sphere_kappa=2.0)
+    t0 = time.perf_counter()
+    op = rt.compute_paths(ctx, sc, pp, c.tx, c.rx)
+    torch.cuda.synchronize()
+    res["city"]["paths_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    res["city"]["paths_found"] = int(op["num_paths"].sum())
+    res["city"]["rx_with_paths"] = int((op["num_paths"] > 0).sum())
+    res["city"]["sphere_pairs"] = rt.last_candidate_count(ctx)
     log("bench: city %s" % res["city"])
     sc.close()
     return res
