@@ -15,6 +15,8 @@
 // The transposed operands come from a tiled transpose kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "mlp_kernels.h"
 
 namespace rt {
@@ -398,16 +400,28 @@ __global__ void map_inputs_kernel(const float* __restrict__ tx, int32_t T, doubl
     v[5 * i + 4] = (float)(gy0 + (iy + 0.5) * gcell);
 }
 
-// Fused inference over map rows (tx, cell): a block of 8 waves owns 128 rows;
-// the activations stay in LDS across the four layers (one 128 x 256 bf16
-// buffer, overwritten in place after a barrier), the weights stream from L2
-// as MFMA B-fragments, wave w computes rows (w / 4) * 64 .. +64 and columns
-// (w % 4) * 64 .. +64 of every layer, and the head reduces each row in four
-// lanes.
-constexpr int kInferRows = 128;
-constexpr int kActLd = 256 + 8;
+// ------------------------------------------------------------------ map inference (register-resident)
+// Map inference with f16 MFMA (v_mfma_f32_16x16x32_f16), written as
+// C = W X^T so that rows are the MFMA's n dimension: a wave keeps 32 rows (two
+// n-tiles) of activations in registers for the whole network.  The output
+// tile layout (lane l: features 4 (l / 16) + r of row l % 16) is the next
+// layer's B operand once the k positions of a 32-feature step are mapped to
+// features p -> p < 4 ? 4 g + p : 16 + 4 g + p - 4 (g = l / 16); the weights
+// are pre-arranged with the same map, as 1 KB fragments (one per m-tile and
+// k-step, 16 bytes per lane) that a block stages layer by layer in LDS.
+// GELU (the tanh form) is evaluated in packed f16 as x clamp(1/2 + u Q(u^2),
+// 0, 1), u = clamp(x / 4, -1, 1), Q a degree-6 least-squares fit (largest
+// deviation 2e-4 in exact arithmetic); the Fourier features use the hardware
+// sine and cosine of the phase in turns.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __fp16 fp16x2 __attribute__((ext_vector_type(2)));
+constexpr int kV2Waves = 8;                 // 512 threads, 32 rows per wave
+constexpr int kV2Rows = 32 * kV2Waves;      // rows per block pass
+constexpr int kFragHalves = 512;            // 16 x 32 f16 per fragment
+constexpr int kL1Frags = 16 * 4, kLFrags = 16 * 8;
 
-struct InferArgs {
+struct InferV2Args {
     const float* tx;
     int32_t T;
     double gx0, gy0, gcell;
@@ -415,95 +429,203 @@ struct InferArgs {
     int64_t total;
     const float* ff;
     MlpNorm norm;
-    const bf16* wbf;
-    MlpLayout lay;
+    const _Float16* wfrag;  // layer 1: kL1Frags fragments, layers 2..4: kLFrags each
     const float* params;
+    MlpLayout lay;
     float* out;
 };
 
-__global__ __launch_bounds__(512) void infer_fused_kernel(InferArgs a) {
-    __shared__ __attribute__((aligned(16))) bf16 act[kInferRows][kActLd];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int rh = wave >> 2, cq = wave & 3;
-    const int64_t row0 = (int64_t)blockIdx.x * kInferRows;
-    const int64_t cells = (int64_t)a.gnx * a.gny;
-    // Fourier features of the block's rows
-    for (int e = tid; e < kInferRows * kFreq; e += 512) {
-        const int r = e / kFreq, j = e - r * kFreq;
-        int64_t gr = row0 + r;
-        if (gr >= a.total) gr = a.total - 1;
-        const int64_t t = gr / cells, c = gr - t * cells;
-        const int64_t iy = c / a.gnx, ix = c - iy * a.gnx;
-        const float v[5] = {a.tx[3 * t], a.tx[3 * t + 1], a.tx[3 * t + 2], (float)(a.gx0 + (ix + 0.5) * a.gcell),
-                            (float)(a.gy0 + (iy + 0.5) * a.gcell)};
-        float rev = 0.0f;
-#pragma unroll
-        for (int i = 0; i < 5; ++i) rev += a.ff[j * 5 + i] * ((v[i] - a.norm.center[i]) * a.norm.inv_half[i]);
-        float sn, cs;
-        sincospif(2.0f * rev, &sn, &cs);
-        act[r][j] = (bf16)sn;
-        act[r][kFreq + j] = (bf16)cs;
+__device__ __forceinline__ f16x2 gelu2(f16x2 x) {
+    const f16x2 q = {(_Float16)0.25f, (_Float16)0.25f};
+    f16x2 u = x * q;
+    u = __builtin_elementwise_min(__builtin_elementwise_max(u, (f16x2){(_Float16)-1.0f, (_Float16)-1.0f}),
+                                  (f16x2){(_Float16)1.0f, (_Float16)1.0f});
+    const f16x2 t = u * u;
+    auto c = [](float v) { return (f16x2){(_Float16)v, (_Float16)v}; };
+    f16x2 p = c(1.60618985f);
+    p = __builtin_elementwise_fma(p, t, c(-6.98037448f));
+    p = __builtin_elementwise_fma(p, t, c(12.9487521f));
+    p = __builtin_elementwise_fma(p, t, c(-13.5802262f));
+    p = __builtin_elementwise_fma(p, t, c(9.05178404f));
+    p = __builtin_elementwise_fma(p, t, c(-4.1370718f));
+    p = __builtin_elementwise_fma(p, t, c(1.59098072f));
+    f16x2 ph = __builtin_elementwise_fma(u, p, c(0.5f));
+    ph = __builtin_elementwise_min(__builtin_elementwise_max(ph, c(0.0f)), c(1.0f));
+    return x * ph;
+}
+
+__device__ __forceinline__ f16x2 to_f16x2(float a, float b) {
+    return __builtin_bit_cast(f16x2, __builtin_amdgcn_cvt_pkrtz(a, b));
+}
+
+// Input feature (weight column) of k position p = 32 s + 8 g + j of a layer.
+__device__ __forceinline__ int v2_column(int layer, int s, int g, int j) {
+    if (layer == 0) {
+        const int f = 16 * s + 4 * g + (j & 3);
+        return j < 4 ? f : kFreq + f;
     }
-    __syncthreads();
-    for (int l = 0; l < 4; ++l) {
-        const int K = a.lay.fan_in[l];
-        const bf16* W = a.wbf + a.lay.bf_off[l];
-        floatx4 acc[4][4];
+    return j < 4 ? 32 * s + 4 * g + j : 32 * s + 16 + 4 * g + (j - 4);
+}
+
+// Fragment-major f16 copies of W1..W4 in the kernel's k order.
+__global__ void v2_weights_kernel(const float* __restrict__ params, MlpLayout lay, _Float16* __restrict__ wfrag) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one fragment lane (8 halves)
+    const int64_t n1 = (int64_t)kL1Frags * 64, nl = (int64_t)kLFrags * 64;
+    if (e >= n1 + 3 * nl) return;
+    int layer;
+    int64_t r;
+    if (e < n1) {
+        layer = 0;
+        r = e;
+    } else {
+        layer = 1 + (int)((e - n1) / nl);
+        r = (e - n1) % nl;
+    }
+    const int S = layer == 0 ? 4 : 8;
+    const int lane = (int)(r % 64);
+    const int frag = (int)(r / 64);
+    const int mt = frag / S, s = frag % S;
+    const int mrow = mt * 16 + (lane & 15), g = lane >> 4;
+    const int K = lay.fan_in[layer];
+    const float* W = params + lay.w_off[layer];
+    for (int j = 0; j < 8; ++j) wfrag[e * 8 + j] = (_Float16)W[(int64_t)mrow * K + v2_column(layer, s, g, j)];
+}
+
+__global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
+    __shared__ __attribute__((aligned(16))) _Float16 wl[kLFrags * kFragHalves];  // 128 KB: one layer
+    __shared__ float bias_s[4][256];
+    __shared__ float ff_s[kFreq * 5];
+    __shared__ float w5_s[256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, nn = lane & 15;
+    for (int i = tid; i < 4 * 256; i += 512) bias_s[i / 256][i % 256] = a.params[a.lay.b_off[i / 256] + i % 256];
+    for (int i = tid; i < kFreq * 5; i += 512) ff_s[i] = a.ff[i];
+    for (int i = tid; i < 256; i += 512) w5_s[i] = a.params[a.lay.w_off[4] + i];
+    const float b5 = a.params[a.lay.b_off[4]];
+    const int64_t cells = (int64_t)a.gnx * a.gny;
+    for (int64_t base = (int64_t)blockIdx.x * kV2Rows; base < a.total; base += (int64_t)gridDim.x * kV2Rows) {
+        int64_t row[2];
+        float v[2][5];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        bf16x8 bn[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            bn[j] = *reinterpret_cast<const bf16x8*>(W + (size_t)(cq * 64 + j * 16 + (lane & 15)) * K + (lane >> 4) * 8);
-        for (int k0 = 0; k0 < K; k0 += 32) {
-            bf16x8 bc[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bc[j] = bn[j];
-            if (k0 + 32 < K) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    bn[j] = *reinterpret_cast<const bf16x8*>(W + (size_t)(cq * 64 + j * 16 + (lane & 15)) * K + k0 + 32 +
-                                                             (lane >> 4) * 8);
-            }
-            bf16x8 af[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                af[i] = *reinterpret_cast<const bf16x8*>(&act[rh * 64 + i * 16 + (lane & 15)][k0 + (lane >> 4) * 8]);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bc[j], acc[i][j], 0, 0, 0);
+        for (int t = 0; t < 2; ++t) {
+            int64_t r = base + wave * 32 + t * 16 + nn;
+            row[t] = r;
+            if (r >= a.total) r = a.total - 1;
+            const int64_t ti = r / cells, c = r - ti * cells;
+            const int64_t iy = c / a.gnx, ix = c - iy * a.gnx;
+            v[t][0] = a.tx[3 * ti];
+            v[t][1] = a.tx[3 * ti + 1];
+            v[t][2] = a.tx[3 * ti + 2];
+            v[t][3] = (float)(a.gx0 + (ix + 0.5) * a.gcell);
+            v[t][4] = (float)(a.gy0 + (iy + 0.5) * a.gcell);
         }
-        __syncthreads();  // every wave has read this layer's input
-        const float* bias = a.params + a.lay.b_off[l];
+        __syncthreads();  // previous pass done with the LDS weights (and the small tables are written)
+        // layer 1 weights
+        {
+            const uint4* src = reinterpret_cast<const uint4*>(a.wfrag);
+            uint4* dst = reinterpret_cast<uint4*>(wl);
+            for (int i = tid; i < kL1Frags * 64; i += 512) dst[i] = src[i];
+        }
+        // Fourier features as the first B operand: lane (g, nn), k-step s holds sin and
+        // cos of frequencies 16 s + 4 g + 0..3 of its row
+        f16x8 B[2][8];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int col = cq * 64 + j * 16 + (lane & 15);
-            const float b = bias[col];
+        for (int t = 0; t < 2; ++t) {
+            float vn[5];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 5; ++i) vn[i] = (v[t][i] - a.norm.center[i]) * a.norm.inv_half[i];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) act[rh * 64 + i * 16 + (lane >> 4) * 4 + r][col] = (bf16)gelu(acc[i][j][r] + b);
+            for (int s = 0; s < 4; ++s) {
+                float sn[4], cs[4];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int f = 16 * s + 4 * g + jj;
+                    float rev = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) rev = fmaf(ff_s[f * 5 + i], vn[i], rev);
+                    sn[jj] = __builtin_amdgcn_sinf(rev);
+                    cs[jj] = __builtin_amdgcn_cosf(rev);
+                }
+                const f16x2 h0 = to_f16x2(sn[0], sn[1]), h1 = to_f16x2(sn[2], sn[3]);
+                const f16x2 h2 = to_f16x2(cs[0], cs[1]), h3 = to_f16x2(cs[2], cs[3]);
+                B[t][s] = (f16x8){h0[0], h0[1], h1[0], h1[1], h2[0], h2[1], h3[0], h3[1]};
+            }
         }
         __syncthreads();
-    }
-    // head: four lanes per row
-    const int r = tid >> 2, part = tid & 3;
-    const float* w5 = a.params + a.lay.w_off[4];
-    float y = 0.0f;
-    for (int k = part * 64; k < part * 64 + 64; ++k) y += w5[k] * (float)act[r][k];
-    y += __shfl_xor(y, 1);
-    y += __shfl_xor(y, 2);
-    const int64_t gr = row0 + r;
-    if (part == 0 && gr < a.total) {
-        const int64_t t = gr / cells, c = gr - t * cells;
-        const int64_t iy = c / a.gnx, ix = c - iy * a.gnx;
-        const float pr = prior_db(a.norm, a.tx[3 * t], a.tx[3 * t + 1], a.tx[3 * t + 2],
-                                  (float)(a.gx0 + (ix + 0.5) * a.gcell), (float)(a.gy0 + (iy + 0.5) * a.gcell));
-        a.out[gr] = y + a.params[a.lay.b_off[4]] + pr;
+#pragma unroll
+        for (int layer = 0; layer < 4; ++layer) {
+            const int S = layer == 0 ? 4 : 8;
+            if (layer > 0) {
+                __syncthreads();  // every wave is done with the previous layer's weights
+                const uint4* src = reinterpret_cast<const uint4*>(a.wfrag + (int64_t)(kL1Frags + (layer - 1) * kLFrags) *
+                                                                            kFragHalves);
+                uint4* dst = reinterpret_cast<uint4*>(wl);
+                for (int i = tid; i < kLFrags * 64; i += 512) dst[i] = src[i];
+                __syncthreads();
+            }
+            // software pipeline over the 8 output groups (32 features each): the
+            // MFMAs of group q are issued before the GELU of group q - 1
+            f16x8 Bn[2][8];
+            floatx4 accp[2][2];
+#pragma unroll
+            for (int q = 0; q <= 8; ++q) {
+                floatx4 acc[2][2];
+                if (q < 8) {
+#pragma unroll
+                    for (int mi = 0; mi < 2; ++mi) {
+                        const int m0 = (2 * q + mi) * 16 + 4 * g;
+                        const floatx4 b = {bias_s[layer][m0], bias_s[layer][m0 + 1], bias_s[layer][m0 + 2],
+                                           bias_s[layer][m0 + 3]};
+                        acc[mi][0] = b;
+                        acc[mi][1] = b;
+                    }
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        const f16x8 A0 =
+                            *reinterpret_cast<const f16x8*>(wl + ((2 * q) * S + s) * kFragHalves + lane * 8);
+                        const f16x8 A1 =
+                            *reinterpret_cast<const f16x8*>(wl + ((2 * q + 1) * S + s) * kFragHalves + lane * 8);
+#pragma unroll
+                        for (int t = 0; t < 2; ++t) {
+                            acc[0][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, B[t][s], acc[0][t], 0, 0, 0);
+                            acc[1][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, B[t][s], acc[1][t], 0, 0, 0);
+                        }
+                    }
+                }
+                if (q > 0) {
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        const f16x2 h0 = gelu2(to_f16x2(accp[0][t][0], accp[0][t][1]));
+                        const f16x2 h1 = gelu2(to_f16x2(accp[0][t][2], accp[0][t][3]));
+                        const f16x2 h2 = gelu2(to_f16x2(accp[1][t][0], accp[1][t][1]));
+                        const f16x2 h3 = gelu2(to_f16x2(accp[1][t][2], accp[1][t][3]));
+                        Bn[t][q - 1] = (f16x8){h0[0], h0[1], h1[0], h1[1], h2[0], h2[1], h3[0], h3[1]};
+                    }
+                }
+                if (q < 8) {
+#pragma unroll
+                    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                        for (int t = 0; t < 2; ++t) accp[mi][t] = acc[mi][t];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) B[t][q] = Bn[t][q];
+        }
+        // head: lane's features of B[t][q] are 32 q + 4 g + j (j < 4) and 32 q + 16 + 4 g + j - 4
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            float y = 0.0f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) y = fmaf(w5_s[v2_column(1, q, g, j)], (float)B[t][q][j], y);
+            y += __shfl_xor(y, 16);
+            y += __shfl_xor(y, 32);
+            if (g == 0 && row[t] < a.total)
+                a.out[row[t]] = y + b5 + prior_db(a.norm, v[t][0], v[t][1], v[t][2], v[t][3], v[t][4]);
+        }
     }
 }
 
@@ -597,10 +719,14 @@ hipError_t launch_index_write(const uint8_t* mask, int64_t n, const uint64_t* of
     return hipGetLastError();
 }
 
-hipError_t launch_infer_fused(const float* tx, int32_t T, double gx0, double gy0, double gcell, int32_t gnx,
-                              int32_t gny, const float* ff, const MlpNorm& norm, const __bf16* wbf,
-                              const MlpLayout& lay, const float* params, float* out, hipStream_t s) {
-    InferArgs a;
+int64_t v2_weights_halves() { return (int64_t)(kL1Frags + 3 * kLFrags) * kFragHalves; }
+
+hipError_t launch_infer_v2(const float* tx, int32_t T, double gx0, double gy0, double gcell, int32_t gnx, int32_t gny,
+                           const float* ff, const MlpNorm& norm, _Float16* wfrag, const MlpLayout& lay,
+                           const float* params, float* out, int grid, hipStream_t s) {
+    const int64_t lanes = (int64_t)(kL1Frags + 3 * kLFrags) * 64;
+    hipLaunchKernelGGL(v2_weights_kernel, dim3(blocks_for(lanes, 256)), dim3(256), 0, s, params, lay, wfrag);
+    InferV2Args a;
     a.tx = tx;
     a.T = T;
     a.gx0 = gx0;
@@ -611,11 +737,13 @@ hipError_t launch_infer_fused(const float* tx, int32_t T, double gx0, double gy0
     a.total = (int64_t)T * gnx * gny;
     a.ff = ff;
     a.norm = norm;
-    a.wbf = wbf;
-    a.lay = lay;
+    a.wfrag = wfrag;
     a.params = params;
+    a.lay = lay;
     a.out = out;
-    hipLaunchKernelGGL(infer_fused_kernel, dim3(blocks_for(a.total, kInferRows)), dim3(512), 0, s, a);
+    const int64_t passes = (a.total + kV2Rows - 1) / kV2Rows;
+    const unsigned blocks = (unsigned)std::min<int64_t>(passes, grid);
+    hipLaunchKernelGGL(infer_v2_kernel, dim3(blocks), dim3(512), 0, s, a);
     return hipGetLastError();
 }
 

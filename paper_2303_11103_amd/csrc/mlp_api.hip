@@ -63,6 +63,8 @@ struct rt_mlp {
     // batch scratch (rows = cfg.batch)
     __bf16 *feats = nullptr, *Z[4] = {}, *H[4] = {}, *dZa = nullptr, *dZb = nullptr, *T1 = nullptr, *T2 = nullptr;
     float *part = nullptr, *scal = nullptr, *pred = nullptr, *vin = nullptr;  // scal: [0] mask sum, [1] loss
+    _Float16* wfrag = nullptr;  // map inference: fragment-major f16 weights
+    int num_cu = 256;
     int64_t step = 0;
     std::vector<void*> allocs;
 };
@@ -222,6 +224,13 @@ rt_status rt_mlp_create(rt_ctx* c, const rt_mlp_config* cfg, rt_mlp** out) {
     A(&h->scal, 4);
     A(&h->pred, B);
     A(&h->vin, B * 5);
+    A(&h->wfrag, (size_t)rt::v2_weights_halves());
+    {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, rt_internal_device(c)) == hipSuccess &&
+            cu > 0)
+            h->num_cu = cu;
+    }
     hipStream_t s = rt_internal_stream(c);
     if (e == hipSuccess) e = hipMemsetAsync(h->m1, 0, P * sizeof(float), s);
     if (e == hipSuccess) e = hipMemsetAsync(h->m2, 0, P * sizeof(float), s);
@@ -354,8 +363,8 @@ rt_status rt_mlp_predict_maps(rt_mlp* h, const float* tx, int32_t T, const rt_gr
     if (T < 1 || g->nx < 1 || g->ny < 1) return rt_internal_fail(RT_ERR_ARG, "empty map stack");
     hipStream_t s = rt_internal_stream(h->ctx);
     MLP_HIP(hipSetDevice(rt_internal_device(h->ctx)));
-    MLP_HIP(rt::launch_infer_fused(tx, T, g->x0, g->y0, g->cell, g->nx, g->ny, h->ff, h->norm, h->wbf, h->lay,
-                                   h->params, maps, s));
+    MLP_HIP(rt::launch_infer_v2(tx, T, g->x0, g->y0, g->cell, g->nx, g->ny, h->ff, h->norm, h->wfrag, h->lay,
+                                h->params, maps, h->num_cu, s));
     return RT_OK;
 }
 

@@ -65,9 +65,12 @@ hipError_t launch_index_count(const uint8_t* mask, int64_t n, uint32_t* tile_cou
 hipError_t launch_index_scan(const uint32_t* tile_counts, int64_t tiles, uint64_t* offsets, hipStream_t s);
 hipError_t launch_index_write(const uint8_t* mask, int64_t n, const uint64_t* offsets, uint32_t* index,
                               hipStream_t s);
-hipError_t launch_infer_fused(const float* tx, int32_t T, double gx0, double gy0, double gcell, int32_t gnx,
-                              int32_t gny, const float* ff, const MlpNorm& norm, const __bf16* wbf,
-                              const MlpLayout& lay, const float* params, float* out, hipStream_t s);
+// Register-resident f16 map inference: fragment weights are rebuilt from
+// the fp32 parameters into wfrag (v2_weights_halves() f16) on every call.
+int64_t v2_weights_halves();
+hipError_t launch_infer_v2(const float* tx, int32_t T, double gx0, double gy0, double gcell, int32_t gnx, int32_t gny,
+                           const float* ff, const MlpNorm& norm, _Float16* wfrag, const MlpLayout& lay,
+                           const float* params, float* out, int grid, hipStream_t s);
 hipError_t launch_map_inputs(const float* tx, int32_t T, double gx0, double gy0, double gcell, int32_t gnx,
                              int32_t gny, int64_t row0, int64_t rows, float* v, hipStream_t s);
 

@@ -95,6 +95,33 @@ def test_training_reduces_loss_on_a_smooth_field():
     assert np.mean(losses[-10:]) < 0.6 * np.mean(losses[:10]), (losses[0], losses[-1])
 
 
+def test_map_inference_of_a_trained_network_matches_the_forward():
+    """After training on a smooth field (large activations), map inference
+    (f16, polynomial GELU) agrees with the bf16 row-wise forward to 1% of the
+    output range; the polynomial GELU itself is pinned on the CPU."""
+    import scenegen as sg
+    m = _mlp(batch=4096, seed=7, ff_scale=1.0)
+    rng = np.random.default_rng(8)
+    dev = "cuda"
+    for s in range(300):
+        v = rng.uniform(-1, 1, size=(4096, 5)).astype(np.float32)
+        t = (40 * np.sin(2 * v[:, 3]) + 20 * np.cos(3 * v[:, 4]) - 30 * v[:, 2]).astype(np.float32)
+        m.train_step(torch.tensor(v, device=dev), torch.tensor(t, device=dev), torch.ones(4096, device=dev), 2e-3)
+    grid = sg.Grid(-1.0, -1.0, 0.0625, 32, 32, 0.0)
+    tx = torch.tensor(rng.uniform(-1, 1, size=(4, 3)).astype(np.float32), device=dev)
+    pred = m.predict_maps(tx, grid).cpu().numpy().reshape(-1)
+    ys, xs = np.meshgrid(grid.y0 + (np.arange(grid.ny) + 0.5) * grid.cell,
+                         grid.x0 + (np.arange(grid.nx) + 0.5) * grid.cell, indexing="ij")
+    txn = tx.cpu().numpy()
+    vv = np.concatenate([np.stack([np.full(xs.size, txn[k, 0]), np.full(xs.size, txn[k, 1]),
+                                   np.full(xs.size, txn[k, 2]), xs.reshape(-1), ys.reshape(-1)], 1)
+                         for k in range(4)]).astype(np.float32)
+    y = m.forward(torch.tensor(vv, device=dev)).cpu().numpy()
+    span = np.max(y) - np.min(y)
+    assert span > 10
+    assert np.max(np.abs(pred - y)) <= 1e-2 * span, (np.max(np.abs(pred - y)), span)
+
+
 def test_valid_index_sample_batch_and_predict_maps():
     import scenegen as sg
     m = _mlp(batch=1024, seed=9)
@@ -133,7 +160,9 @@ def test_valid_index_sample_batch_and_predict_maps():
     pad = (-len(vv)) % 128
     vp = np.concatenate([vv, np.zeros((pad, 5), np.float32)])
     y = m.forward(torch.tensor(vp, device=dev)).cpu().numpy()[:len(vv)]
-    assert np.allclose(pred.reshape(-1), y, rtol=1e-5, atol=1e-4)
+    # map inference runs f16 MFMA with a polynomial GELU (deviation <= 2e-4 of the tanh form), the
+    # row-wise forward bf16 MFMA with the exact tanh GELU
+    assert np.max(np.abs(pred.reshape(-1) - y)) <= 2e-2 * np.max(np.abs(y)) + 1e-4
 
 
 def test_free_space_prior_and_per_input_fourier_scales():
@@ -175,4 +204,5 @@ def test_free_space_prior_and_per_input_fourier_scales():
                                    np.full(xs.size, raw[k, 2]), xs.reshape(-1), ys.reshape(-1)], 1)
                          for k in range(2)]).astype(np.float32)
     yr = m.forward(torch.tensor(vv, device="cuda")).cpu().numpy()
-    assert np.allclose(pred.reshape(-1), yr, rtol=1e-5, atol=1e-3)
+    prior_r = omlp.free_space_db(vv.astype(np.float64), 3.5e9, 1.5)
+    assert np.max(np.abs(pred.reshape(-1) - yr)) <= 2e-2 * np.max(np.abs(yr - prior_r)) + 1e-3

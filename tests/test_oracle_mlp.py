@@ -72,3 +72,15 @@ def test_free_space_prior_equals_image_method_line_of_sight():
         P = image.paths(g, dev(pts[k, :3]), [dev((pts[k, 3], pts[k, 4], rx_z))], [])[0]
         assert len(P) == 1 and P[0].faces == ()
         assert abs(10 * np.log10(abs(P[0].a) ** 2) - prior[k]) < 1e-9
+
+
+def test_polynomial_gelu_of_map_inference_is_close_to_the_tanh_form():
+    """The map-inference kernel evaluates GELU as x clamp(1/2 + u Q(u^2), 0, 1),
+    u = clamp(x / 4, -1, 1); in exact arithmetic it stays within 2.5e-4 of the
+    tanh form everywhere (coefficients as in the kernel)."""
+    q = [1.59098072, -4.1370718, 9.05178404, -13.5802262, 12.9487521, -6.98037448, 1.60618985]
+    x = np.linspace(-12, 12, 48001)
+    u = np.clip(x / 4, -1, 1)
+    phi = np.clip(0.5 + u * np.polyval(q[::-1], u * u), 0, 1)
+    assert np.max(np.abs(x * phi - mlp.gelu(x))) < 2.5e-4 * np.maximum(1.0, np.abs(x)).max()
+    assert np.max(np.abs(x * phi - mlp.gelu(x))[np.abs(x) <= 4]) < 2.5e-4
