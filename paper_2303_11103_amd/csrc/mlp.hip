@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256) void head_kernel(const bf16* __restrict__ H4, 
                 const float inv = 1.0f / fmaxf(msum[0], 1.0f);
                 const float e = y - t[row];
                 gval = 2.0f * m[row] * e * inv;
-                atomicAdd(loss, m[row] * e * e * inv);
+                acc[tid] = m[row] * e * e * inv;  // this row's share of the loss
             }
         }
         sg[tid] = gval;
@@ -169,9 +169,13 @@ __global__ __launch_bounds__(256) void head_kernel(const bf16* __restrict__ H4, 
     __syncthreads();
     if (!t) return;
     if (tid == 0) {
-        float s = 0.0f;
-        for (int i = 0; i < 256; ++i) s += sg[i];
+        float s = 0.0f, l = 0.0f;
+        for (int i = 0; i < 256; ++i) {
+            s += sg[i];
+            l += acc[i];
+        }
         atomicAdd(gb5, s);
+        atomicAdd(loss, l);  // one atomic per block
     }
     // thread = feature column k: dw5[k] += sum_rows g h4[row][k]; dZ4 = g w5[k] gelu'(z)
     const int k = tid;
@@ -210,12 +214,18 @@ __global__ void transpose_kernel(const bf16* __restrict__ in, int64_t R, int64_t
 }
 
 // db[n] += sum_rows dZ[row][n] (dZ: rows x N, N = 256)
-__global__ void colsum_kernel(const bf16* __restrict__ dZ, int64_t rows, float* __restrict__ db) {
-    const int n = threadIdx.x;
+// db[c] += sum_i dZt[c][i]: one block per row c of the transposed gradient
+// (contiguous), a tree reduction, no atomics.
+__global__ __launch_bounds__(256) void rowsum_kernel(const bf16* __restrict__ dZt, int64_t cols,
+                                                     float* __restrict__ db) {
+    __shared__ float part[4];
+    const bf16* p = dZt + (int64_t)blockIdx.x * cols;
     float a = 0.0f;
-    const int64_t r0 = (int64_t)blockIdx.x * 256;
-    for (int64_t i = r0; i < r0 + 256 && i < rows; ++i) a += (float)dZ[i * 256 + n];
-    atomicAdd(db + n, a);
+    for (int64_t i = threadIdx.x; i < cols; i += 256) a += (float)p[i];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) db[blockIdx.x] += part[0] + part[1] + part[2] + part[3];
 }
 
 // grad[i] += sum_s part[s][i]
@@ -665,8 +675,8 @@ hipError_t launch_transpose(const bf16* in, int64_t R, int64_t C, bf16* out, hip
     return hipGetLastError();
 }
 
-hipError_t launch_colsum(const bf16* dZ, int64_t rows, float* db, hipStream_t s) {
-    hipLaunchKernelGGL(colsum_kernel, dim3(blocks_for(rows, 256)), dim3(256), 0, s, dZ, rows, db);
+hipError_t launch_rowsum(const bf16* dZt, int64_t rows, int64_t cols, float* db, hipStream_t s) {
+    hipLaunchKernelGGL(rowsum_kernel, dim3((unsigned)rows), dim3(256), 0, s, dZt, cols, db);
     return hipGetLastError();
 }
 

@@ -123,9 +123,9 @@ rt_status gradient(rt_mlp* h, const float* v, const float* t, const float* m, in
     __bf16* dz_next = h->dZb;
     for (int l = 3; l >= 0; --l) {
         const int K = L.fan_in[l];
-        MLP_HIP(rt::launch_colsum(dz, n, h->grad + L.b_off[l], s));
         // dW_l = dZ_l^T H_{l-1}: both operands transposed so that rows are the reduction axis
         MLP_HIP(rt::launch_transpose(dz, n, kHidden, h->T1, s));
+        MLP_HIP(rt::launch_rowsum(h->T1, kHidden, n, h->grad + L.b_off[l], s));  // db_l = column sums of dZ_l
         const __bf16* hp = l ? h->H[l - 1] : h->feats;
         MLP_HIP(rt::launch_transpose(hp, n, K, h->T2, s));
         int S = kSplits;

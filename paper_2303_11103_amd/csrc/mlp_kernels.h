@@ -47,7 +47,7 @@ hipError_t launch_head(const __bf16* H4, const __bf16* Z4, const float* w5, cons
                        float* loss, __bf16* dZ4, float* gw5, float* gb5, hipStream_t s);
 hipError_t launch_mask_sum(const float* m, int64_t n, float* out, hipStream_t s);
 hipError_t launch_transpose(const __bf16* in, int64_t R, int64_t C, __bf16* out, hipStream_t s);
-hipError_t launch_colsum(const __bf16* dZ, int64_t rows, float* db, hipStream_t s);
+hipError_t launch_rowsum(const __bf16* dZt, int64_t rows, int64_t cols, float* db, hipStream_t s);
 hipError_t launch_reduce_splits(const float* part, int S, int64_t n, float* grad, hipStream_t s);
 hipError_t launch_mlp_init(float* params, float* ff, uint64_t seed, float ff_scale_tx, float ff_scale_cell,
                            const MlpLayout& lay, hipStream_t s);
