@@ -378,10 +378,11 @@ def surrogate_bench(rt, ctx, scene, w, torch, steps=20000, n_tx=4096, seed=3):
     maps = torch.where(mask.bool(), maps, torch.zeros_like(maps))
     lo = np.array([-200.0, -200.0, 10.0, -200.0, -200.0])
     hi = np.array([200.0, 200.0, 65.0, 200.0, 200.0])
-    # low Fourier frequencies on the transmitter inputs, higher on the cell inputs;
-    # the network learns the residual over the free-space gain of each link
+    # Fourier rows: 8 on the transmitter (low frequencies), 16 on the cell, 40 on the
+    # cell relative to the transmitter; the network learns the residual over the
+    # free-space gain of each link
     m = S.MLP(ctx, batch=32768, ff_scale=1.0, ff_scale_cell=4.0, seed=seed, center=(lo + hi) / 2, half=(hi - lo) / 2,
-              prior=(w.scene.freq_hz, grid.z))
+              prior=(w.scene.freq_hz, grid.z), ff_rows_tx=8, ff_rows_rel=40, ff_scale_rel=32.0)
     rep = S.train(m, maps[tr].contiguous(), mask[tr].contiguous(), tx[tr].contiguous(), grid, steps=steps, lr=2e-3,
                   seed=seed)
     pv = m.predict_maps(tx[va], grid)

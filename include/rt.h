@@ -253,7 +253,8 @@ rt_status rt_paths_power_grad(rt_ctx* ctx, rt_scene* scene, const rt_trace_param
  * tool; it specifies no network).  Function: inputs v = (tx x, y, z, cell
  * x, y), normalised as (v - in_center) / in_half; Fourier features
  * [sin 2 pi B v, cos 2 pi B v] with B (64 x 5) drawn N(0, s^2), s =
- * ff_scale on the transmitter columns and ff_scale_cell on the cell columns;
+ * ff_scale on the transmitter columns and ff_scale_cell on the cell columns
+ * (or structured, see ff_rows_tx);
  * 4 hidden layers of 256 with the tanh-form GELU; linear head.  The output
  * (path gain in dB) is the head plus, when prior_freq_hz > 0, the free-space
  * gain of the link, 20 log10(c0 / (4 pi f d)) with d the distance from the
@@ -274,6 +275,15 @@ typedef struct {
     float ff_scale_cell;  /* std of the Fourier entries on the cell inputs (x, y); 0 = ff_scale */
     float prior_rx_z;     /* receiver height of the free-space prior [m] */
     double prior_freq_hz; /* carrier of the free-space prior [Hz]; 0 = no prior */
+    /* Structured B (used when ff_rows_tx + ff_rows_rel > 0): the first ff_rows_tx
+     * rows see the transmitter only (std ff_scale), the last ff_rows_rel rows the
+     * cell relative to the transmitter in x, y (std ff_scale_rel, entries b and -b
+     * on the cell and transmitter columns) and the transmitter height (std
+     * ff_scale), the rows between the cell only (std ff_scale_cell). */
+    int32_t ff_rows_tx;
+    int32_t ff_rows_rel;
+    float ff_scale_rel;
+    int32_t reserved;     /* 0 */
 } rt_mlp_config;
 
 rt_status rt_mlp_param_count(int64_t* n);

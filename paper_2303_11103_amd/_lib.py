@@ -46,7 +46,8 @@ class rt_grid(ctypes.Structure):
 class rt_mlp_config(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int32), ("ff_scale", ctypes.c_float), ("seed", ctypes.c_uint64),
                 ("in_center", ctypes.c_float * 5), ("in_half", ctypes.c_float * 5), ("ff_scale_cell", ctypes.c_float),
-                ("prior_rx_z", ctypes.c_float), ("prior_freq_hz", ctypes.c_double)]
+                ("prior_rx_z", ctypes.c_float), ("prior_freq_hz", ctypes.c_double), ("ff_rows_tx", ctypes.c_int32),
+                ("ff_rows_rel", ctypes.c_int32), ("ff_scale_rel", ctypes.c_float), ("reserved", ctypes.c_int32)]
 
 
 class rt_scene_info_t(ctypes.Structure):

@@ -245,11 +245,21 @@ __device__ __forceinline__ uint64_t splitmix(uint64_t x) {
 }
 __device__ __forceinline__ float u01(uint64_t h) { return ((float)(h >> 40) + 0.5f) * 0x1p-24f; }
 
-// Weights uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)), biases 0; Fourier matrix
-// N(0, s^2) with s = ff_scale_tx on the transmitter columns (0..2) and
-// ff_scale_cell on the cell columns (3, 4).
-__global__ void init_kernel(float* __restrict__ params, float* __restrict__ ff, uint64_t seed, float ff_scale_tx,
-                            float ff_scale_cell, MlpLayout lay) {
+// Weights uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)), biases 0.  Fourier matrix
+// (64 x 5, columns tx x, y, z, cell x, y) from unit normals z(f, c):
+// independent (rows_tx = rows_rel = 0): s_tx z on the transmitter columns,
+// s_cell z on the cell columns; structured: rows f < rows_tx transmitter only
+// (s_tx z), rows f >= 64 - rows_rel the cell relative to the transmitter
+// (s_rel z(f, 3..4) on the cell columns, the negatives on tx x, y, s_tx z on
+// tx z), the rows between cell only (s_cell z).
+__device__ __forceinline__ float unit_normal(uint64_t seed, int64_t i) {
+    const uint64_t h1 = splitmix(seed * 7919u + 0x1234567ull + 2 * (uint64_t)i);
+    const uint64_t h2 = splitmix(seed * 7919u + 0x1234567ull + 2 * (uint64_t)i + 1);
+    return sqrtf(-2.0f * logf(u01(h1))) * cospif(2.0f * u01(h2));
+}
+
+__global__ void init_kernel(float* __restrict__ params, float* __restrict__ ff, uint64_t seed, MlpFourier fs,
+                            MlpLayout lay) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < lay.total) {
         float v = 0.0f;
@@ -262,10 +272,21 @@ __global__ void init_kernel(float* __restrict__ params, float* __restrict__ ff, 
         params[i] = v;
     }
     if (i < kFreq * 5) {
-        const uint64_t h1 = splitmix(seed * 7919u + 0x1234567ull + 2 * (uint64_t)i);
-        const uint64_t h2 = splitmix(seed * 7919u + 0x1234567ull + 2 * (uint64_t)i + 1);
-        const float r = sqrtf(-2.0f * logf(u01(h1)));
-        ff[i] = ((i % 5) < 3 ? ff_scale_tx : ff_scale_cell) * r * cospif(2.0f * u01(h2));
+        const int f = (int)(i / 5), c = (int)(i % 5);
+        const float z = unit_normal(seed, i);
+        float b;
+        if (fs.rows_tx + fs.rows_rel == 0) {
+            b = (c < 3 ? fs.s_tx : fs.s_cell) * z;
+        } else if (f < fs.rows_tx) {
+            b = c < 3 ? fs.s_tx * z : 0.0f;
+        } else if (f >= kFreq - fs.rows_rel) {
+            if (c >= 3) b = fs.s_rel * z;
+            else if (c == 2) b = fs.s_tx * z;
+            else b = -fs.s_rel * unit_normal(seed, (int64_t)f * 5 + 3 + c);  // minus the cell entry
+        } else {
+            b = c >= 3 ? fs.s_cell * z : 0.0f;
+        }
+        ff[i] = b;
     }
 }
 
@@ -685,10 +706,9 @@ hipError_t launch_reduce_splits(const float* part, int S, int64_t n, float* grad
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_init(float* params, float* ff, uint64_t seed, float ff_scale_tx, float ff_scale_cell,
-                           const MlpLayout& lay, hipStream_t s) {
-    hipLaunchKernelGGL(init_kernel, dim3(blocks_for(lay.total, 256)), dim3(256), 0, s, params, ff, seed, ff_scale_tx,
-                       ff_scale_cell, lay);
+hipError_t launch_mlp_init(float* params, float* ff, uint64_t seed, const MlpFourier& fs, const MlpLayout& lay,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(init_kernel, dim3(blocks_for(lay.total, 256)), dim3(256), 0, s, params, ff, seed, fs, lay);
     return hipGetLastError();
 }
 

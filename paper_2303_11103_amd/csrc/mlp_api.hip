@@ -185,6 +185,10 @@ rt_status rt_mlp_create(rt_ctx* c, const rt_mlp_config* cfg, rt_mlp** out) {
         return rt_internal_fail(RT_ERR_ARG, "ff_scale_cell must be >= 0 (0 = ff_scale)");
     if (!(cfg->prior_freq_hz >= 0) || !std::isfinite(cfg->prior_freq_hz) || !std::isfinite(cfg->prior_rx_z))
         return rt_internal_fail(RT_ERR_ARG, "prior_freq_hz must be >= 0 and prior_rx_z finite");
+    if (cfg->ff_rows_tx < 0 || cfg->ff_rows_rel < 0 || cfg->ff_rows_tx + cfg->ff_rows_rel > rt::kFreq)
+        return rt_internal_fail(RT_ERR_ARG, "ff_rows_tx, ff_rows_rel must be >= 0 with a sum <= 64");
+    if (cfg->ff_rows_rel > 0 && (!(cfg->ff_scale_rel > 0) || !std::isfinite(cfg->ff_scale_rel)))
+        return rt_internal_fail(RT_ERR_ARG, "ff_scale_rel must be positive");
     MLP_HIP(hipSetDevice(rt_internal_device(c)));
     rt_mlp* h = new rt_mlp();
     h->ctx = c;
@@ -234,8 +238,9 @@ rt_status rt_mlp_create(rt_ctx* c, const rt_mlp_config* cfg, rt_mlp** out) {
     hipStream_t s = rt_internal_stream(c);
     if (e == hipSuccess) e = hipMemsetAsync(h->m1, 0, P * sizeof(float), s);
     if (e == hipSuccess) e = hipMemsetAsync(h->m2, 0, P * sizeof(float), s);
-    const float s_cell = cfg->ff_scale_cell > 0 ? cfg->ff_scale_cell : cfg->ff_scale;
-    if (e == hipSuccess) e = rt::launch_mlp_init(h->params, h->ff, cfg->seed, cfg->ff_scale, s_cell, h->lay, s);
+    rt::MlpFourier fs{cfg->ff_scale, cfg->ff_scale_cell > 0 ? cfg->ff_scale_cell : cfg->ff_scale, cfg->ff_scale_rel,
+                      cfg->ff_rows_tx, cfg->ff_rows_rel};
+    if (e == hipSuccess) e = rt::launch_mlp_init(h->params, h->ff, cfg->seed, fs, h->lay, s);
     if (e == hipSuccess) e = rt::launch_refresh_bf16(h->params, h->lay, h->wbf, h->wtbf, s);
     if (e != hipSuccess) {
         rt_mlp_destroy(h);

@@ -49,8 +49,13 @@ hipError_t launch_mask_sum(const float* m, int64_t n, float* out, hipStream_t s)
 hipError_t launch_transpose(const __bf16* in, int64_t R, int64_t C, __bf16* out, hipStream_t s);
 hipError_t launch_rowsum(const __bf16* dZt, int64_t rows, int64_t cols, float* db, hipStream_t s);
 hipError_t launch_reduce_splits(const float* part, int S, int64_t n, float* grad, hipStream_t s);
-hipError_t launch_mlp_init(float* params, float* ff, uint64_t seed, float ff_scale_tx, float ff_scale_cell,
-                           const MlpLayout& lay, hipStream_t s);
+// Fourier-matrix initialisation (see init_kernel).
+struct MlpFourier {
+    float s_tx, s_cell, s_rel;
+    int32_t rows_tx, rows_rel;
+};
+hipError_t launch_mlp_init(float* params, float* ff, uint64_t seed, const MlpFourier& fs, const MlpLayout& lay,
+                           hipStream_t s);
 hipError_t launch_refresh_bf16(const float* params, const MlpLayout& lay, __bf16* wbf, __bf16* wtbf, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2,
                        float eps, float c1, float c2, hipStream_t s);

@@ -31,15 +31,20 @@ class MLP:
     """Handle on the library's Fourier-feature MLP (weights live on the GPU)."""
 
     def __init__(self, ctx: Context, batch=32768, ff_scale=4.0, seed=0, center=(0, 0, 0, 0, 0),
-                 half=(1, 1, 1, 1, 1), ff_scale_cell=0.0, prior=None):
+                 half=(1, 1, 1, 1, 1), ff_scale_cell=0.0, prior=None, ff_rows_tx=0, ff_rows_rel=0, ff_scale_rel=0.0):
         """ff_scale: Fourier std on the transmitter inputs; ff_scale_cell on the
-        cell inputs (0 = ff_scale); prior = (freq_hz, rx_z) adds the free-space
-        gain of the link to the output (the network learns the residual)."""
+        cell inputs (0 = ff_scale); ff_rows_tx / ff_rows_rel > 0 give a
+        structured matrix with transmitter-only and relative-position rows
+        (std ff_scale_rel); prior = (freq_hz, rx_z) adds the free-space gain of
+        the link to the output (the network learns the residual)."""
         self.ctx = ctx
         cfg = L.rt_mlp_config()
         cfg.batch = int(batch)
         cfg.ff_scale = float(ff_scale)
         cfg.ff_scale_cell = float(ff_scale_cell)
+        cfg.ff_rows_tx = int(ff_rows_tx)
+        cfg.ff_rows_rel = int(ff_rows_rel)
+        cfg.ff_scale_rel = float(ff_scale_rel)
         if prior is not None:
             cfg.prior_freq_hz = float(prior[0])
             cfg.prior_rx_z = float(prior[1])

@@ -38,20 +38,22 @@ def test_struct_layouts_match_header(tmp_path):
     assert ctypes.sizeof(_lib.rt_trace_params) == 56
     assert ctypes.sizeof(_lib.rt_grid) == 40
     assert ctypes.sizeof(_lib.rt_scene_info_t) == 40
-    assert ctypes.sizeof(_lib.rt_mlp_config) == 72
+    assert ctypes.sizeof(_lib.rt_mlp_config) == 88
     src = (
         "#include <stddef.h>\n#include <stdio.h>\n#include \"rt.h\"\n"
-        "int main(){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(rt_material), sizeof(rt_device),"
+        "int main(){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(rt_material), sizeof(rt_device),"
         " sizeof(rt_trace_params), sizeof(rt_grid), sizeof(rt_scene_info_t),"
         " offsetof(rt_trace_params, num_rays), offsetof(rt_grid, nx), sizeof(rt_mlp_config),"
-        " offsetof(rt_mlp_config, ff_scale_cell), offsetof(rt_mlp_config, prior_freq_hz)); return 0;}\n")
+        " offsetof(rt_mlp_config, ff_scale_cell), offsetof(rt_mlp_config, prior_freq_hz),"
+        " offsetof(rt_mlp_config, ff_scale_rel)); return 0;}\n")
     c = tmp_path / "layout_check.c"
     exe = tmp_path / "layout_check"
     c.write_text(src)
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
     vals = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()))
-    assert vals == [8, 32, 56, 40, 40, _lib.rt_trace_params.num_rays.offset, _lib.rt_grid.nx.offset, 72,
-                    _lib.rt_mlp_config.ff_scale_cell.offset, _lib.rt_mlp_config.prior_freq_hz.offset]
+    assert vals == [8, 32, 56, 40, 40, _lib.rt_trace_params.num_rays.offset, _lib.rt_grid.nx.offset, 88,
+                    _lib.rt_mlp_config.ff_scale_cell.offset, _lib.rt_mlp_config.prior_freq_hz.offset,
+                    _lib.rt_mlp_config.ff_scale_rel.offset]
 
 
 def test_null_and_invalid_arguments_fail_on_host():

@@ -183,6 +183,13 @@ def test_free_space_prior_and_per_input_fourier_scales():
                           rng.uniform(-200, 200, size=(512, 2))], 1).astype(np.float32)
     y = m.forward(torch.tensor(raw, device="cuda")).cpu().double().numpy()
     vn = (raw.astype(np.float64) - (lo + hi) / 2) / ((hi - lo) / 2)
+    # structured rows: transmitter only, cell only, cell relative to the transmitter
+    ms = MLP(ctx(), batch=1024, ff_scale=1.0, ff_scale_cell=4.0, seed=21, ff_rows_tx=8, ff_rows_rel=40,
+             ff_scale_rel=32.0)
+    Bs = ms.get_params()[1].cpu().double().numpy()
+    assert np.all(Bs[:8, 3:] == 0) and np.all(Bs[8:24, :3] == 0)
+    assert np.array_equal(Bs[24:, 0:2], -Bs[24:, 3:5]) and 20 < Bs[24:, 3:].std() < 45
+    ms.close()
     theta = p.cpu().double().numpy()
     q = []
     for li, (W, b) in enumerate(omlp.unpack(theta)):
