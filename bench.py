@@ -55,7 +55,7 @@ COPY_PROBE_BYTES = 256 << 20
 # Sources that make up the shoot-and-bounce kernel: HBM traffic measured with
 # counters is reported only while they are unchanged.
 KERNEL_SOURCES = ["paper_2303_11103_amd/csrc/" + f for f in
-                  ("trace.hip", "traverse.h", "device.h", "kernels.h", "layout.h", "api.hip")]
+                  ("trace.hip", "traverse.h", "device.h", "kernels.h", "layout.h", "api.hip", "scene.cpp")]
 TRAFFIC_PROFILE = "profiles/sbr_bounce_urban_hbm_traffic.md"
 
 

@@ -100,27 +100,29 @@ private:
         return id;
     }
 
-    // Binned SAH over 16 bins per axis.  Returns the split position, -2 when
-    // a leaf is cheaper (only allowed when count <= kMaxLeaf), -1 when no
-    // valid split exists.
+    // Binned SAH, count / 8 bins per axis clamped to [16, 128] (large nodes,
+    // where a coarse split costs most, get fine bins).  Returns the split
+    // position, -2 when a leaf is cheaper (only allowed when count <=
+    // kMaxLeaf), -1 when no valid split exists.
     int32_t sah_split(int32_t first, int32_t count, const Box& cb, const Box& b, bool leaf_ok) {
-        constexpr int kBins = 16;
+        constexpr int kMaxBins = 128;
+        const int kBins = std::min(kMaxBins, std::max(16, count / 8));
         constexpr double kTrav = 1.0, kIsect = 1.5;
         double best = INFINITY;
         int best_axis = -1, best_bin = -1;
         for (int ax = 0; ax < 3; ++ax) {
             double lo = cb.lo[ax], ext = cb.hi[ax] - cb.lo[ax];
             if (!(ext > 0.0)) continue;
-            Box bins[kBins];
-            int cnt[kBins] = {0};
+            Box bins[kMaxBins];
+            int cnt[kMaxBins] = {0};
             for (int32_t i = first; i < first + count; ++i) {
                 int k = (int)((prims_[i].c[ax] - lo) / ext * kBins);
                 k = std::min(std::max(k, 0), kBins - 1);
                 bins[k].grow(prims_[i].box);
                 cnt[k]++;
             }
-            double right_area[kBins];
-            int right_cnt[kBins];
+            double right_area[kMaxBins];
+            int right_cnt[kMaxBins];
             Box acc;
             int n = 0;
             for (int k = kBins - 1; k > 0; --k) {
