@@ -32,8 +32,8 @@ sys.path.insert(0, ROOT)
 BJ_METRIC = "M ray-bounces/s + coverage-map ms vs oracle; surrogate maps/s at <=3 dB RMSE"
 # Algorithmic work per unit (floating-point operations the method needs; an
 # FMA counts 2, an add/mul/min/max/compare 1):
-#   BVH inner-node visit = two fp32 ray/box slab tests: 12 FMA + 24 min/max
-#     + 6 for the interval tests = 54;
+#   BVH inner-node visit = four fp32 ray/box slab tests (the children of a
+#     4-wide node): 24 FMA + 48 min/max + 12 for the interval tests = 108;
 #   triangle test = fp64 Moller-Trumbore without division: 46;
 #   every traced segment: coverage-plane crossing, cell index, receive
 #     pattern and |F_rx . E|^2 deposit: 40;
@@ -42,7 +42,7 @@ BJ_METRIC = "M ray-bounces/s + coverage-map ms vs oracle; surrogate maps/s at <=
 #     direction and hit point, 3-vector complex field update: 160;
 #   every ray at depth 0: Fibonacci direction (z, rho, sincos of the golden
 #     phase) and transmit pattern: 70.
-FLOP_NODE = 54.0
+FLOP_NODE = 108.0
 FLOP_TRI = 46.0
 FLOP_DEPOSIT = 40.0
 FLOP_REFLECT = 160.0
