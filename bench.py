@@ -129,7 +129,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the shoot-and-bounce workload of one transmitter runs on a single "
-              "MI355X (see DESIGN.md for how it would shard); got --gpus %d" % args.gpus, file=sys.stderr)
+              "MI355X (rays would shard by lattice range, maps reduce with one all-reduce); got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import ctypes
