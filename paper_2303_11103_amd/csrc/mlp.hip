@@ -594,9 +594,11 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
                 __syncthreads();
             }
             // software pipeline over the 8 output groups (32 features each): the
-            // MFMAs of group q are issued before the GELU of group q - 1
+            // GELU of group q - 1 is interleaved with the MFMAs of group q, one of
+            // its four packed pairs per n-tile after each k-step
             f16x8 Bn[2][8];
             floatx4 accp[2][2];
+            f16x2 hp[2][4];
 #pragma unroll
             for (int q = 0; q <= 8; ++q) {
                 floatx4 acc[2][2];
@@ -609,8 +611,10 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
                         acc[mi][0] = b;
                         acc[mi][1] = b;
                     }
+                }
 #pragma unroll
-                    for (int s = 0; s < S; ++s) {
+                for (int s = 0; s < 8; ++s) {
+                    if (q < 8 && s < S) {
                         const f16x8 A0 =
                             *reinterpret_cast<const f16x8*>(wl + ((2 * q) * S + s) * kFragHalves + lane * 8);
                         const f16x8 A1 =
@@ -621,16 +625,17 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
                             acc[1][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, B[t][s], acc[1][t], 0, 0, 0);
                         }
                     }
+                    if (q > 0 && s < 4) {  // pair s of the previous group, both n-tiles
+                        const int mi = s >> 1, r = (s & 1) * 2;
+#pragma unroll
+                        for (int t = 0; t < 2; ++t) hp[t][s] = gelu2(to_f16x2(accp[mi][t][r], accp[mi][t][r + 1]));
+                    }
                 }
                 if (q > 0) {
 #pragma unroll
-                    for (int t = 0; t < 2; ++t) {
-                        const f16x2 h0 = gelu2(to_f16x2(accp[0][t][0], accp[0][t][1]));
-                        const f16x2 h1 = gelu2(to_f16x2(accp[0][t][2], accp[0][t][3]));
-                        const f16x2 h2 = gelu2(to_f16x2(accp[1][t][0], accp[1][t][1]));
-                        const f16x2 h3 = gelu2(to_f16x2(accp[1][t][2], accp[1][t][3]));
-                        Bn[t][q - 1] = (f16x8){h0[0], h0[1], h1[0], h1[1], h2[0], h2[1], h3[0], h3[1]};
-                    }
+                    for (int t = 0; t < 2; ++t)
+                        Bn[t][q - 1] = (f16x8){hp[t][0][0], hp[t][0][1], hp[t][1][0], hp[t][1][1],
+                                               hp[t][2][0], hp[t][2][1], hp[t][3][0], hp[t][3][1]};
                 }
                 if (q < 8) {
 #pragma unroll
