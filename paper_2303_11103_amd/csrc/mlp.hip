@@ -467,12 +467,13 @@ struct InferV2Args {
 };
 
 __device__ __forceinline__ f16x2 gelu2(f16x2 x) {
-    const f16x2 q = {(_Float16)0.25f, (_Float16)0.25f};
-    f16x2 u = x * q;
-    u = __builtin_elementwise_min(__builtin_elementwise_max(u, (f16x2){(_Float16)-1.0f, (_Float16)-1.0f}),
-                                  (f16x2){(_Float16)1.0f, (_Float16)1.0f});
-    const f16x2 t = u * u;
     auto c = [](float v) { return (f16x2){(_Float16)v, (_Float16)v}; };
+    // u = x / 4 is not clamped: t = min(u^2, 1) bounds the polynomial's argument,
+    // and for |u| > 1 the value 1/2 + u Q(1) lies outside [0, 1] (Q(1) > 1/2), so
+    // the clamp of the result gives 0 or 1 exactly as with u clamped to [-1, 1].
+    // Both clamps to [0, 1] become the instructions' clamp bits.
+    const f16x2 u = x * c(0.25f);
+    const f16x2 t = __builtin_elementwise_min(__builtin_elementwise_max(u * u, c(0.0f)), c(1.0f));
     f16x2 p = c(1.60618985f);
     p = __builtin_elementwise_fma(p, t, c(-6.98037448f));
     p = __builtin_elementwise_fma(p, t, c(12.9487521f));
@@ -522,6 +523,24 @@ __global__ void v2_weights_kernel(const float* __restrict__ params, MlpLayout la
     for (int j = 0; j < 8; ++j) wfrag[e * 8 + j] = (_Float16)W[(int64_t)mrow * K + v2_column(layer, s, g, j)];
 }
 
+// Copies N fragments (N * 64 16-byte lanes), starting at byte `first` of the
+// fragment buffer, into LDS with the block's 512 threads by buffer loads that
+// write LDS directly: no registers are held and all of a thread's loads are in
+// flight at once (the caller waits and synchronises).  The buffer descriptor's
+// size bound makes any read past the fragments return zeros.
+template <int N>
+__device__ __forceinline__ void stage_frags(__amdgpu_buffer_rsrc_t rsrc, uint32_t first, _Float16* dst, int tid) {
+    constexpr int kPer = N * 64 / 512;
+    const int wave = tid >> 6;
+    uint4* d = reinterpret_cast<uint4*>(dst) + wave * 64;  // lane l of the wave lands at d + l
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void*)(d + k * 512), 16,
+                                                 (uint32_t)tid * 16u, first + (uint32_t)k * 8192u, 0, 0);
+}
+
+__device__ __forceinline__ void stage_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
     __shared__ __attribute__((aligned(16))) _Float16 wl[kLFrags * kFragHalves];  // 128 KB: one layer
     __shared__ float bias_s[4][256];
@@ -532,6 +551,8 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
     for (int i = tid; i < kFreq * 5; i += 512) ff_s[i] = a.ff[i];
     for (int i = tid; i < 256; i += 512) w5_s[i] = a.params[a.lay.w_off[4] + i];
     const float b5 = a.params[a.lay.b_off[4]];
+    const __amdgpu_buffer_rsrc_t wrsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)a.wfrag, (short)0, (int)((kL1Frags + 3 * kLFrags) * kFragHalves * 2), 0x00020000);
     const int64_t cells = (int64_t)a.gnx * a.gny;
     for (int64_t base = (int64_t)blockIdx.x * kV2Rows; base < a.total; base += (int64_t)gridDim.x * kV2Rows) {
         int64_t row[2];
@@ -550,12 +571,7 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
             v[t][4] = (float)(a.gy0 + (iy + 0.5) * a.gcell);
         }
         __syncthreads();  // previous pass done with the LDS weights (and the small tables are written)
-        // layer 1 weights
-        {
-            const uint4* src = reinterpret_cast<const uint4*>(a.wfrag);
-            uint4* dst = reinterpret_cast<uint4*>(wl);
-            for (int i = tid; i < kL1Frags * 64; i += 512) dst[i] = src[i];
-        }
+        stage_frags<kL1Frags>(wrsrc, 0u, wl, tid);  // layer 1 weights, waited for after the features
         // Fourier features as the first B operand: lane (g, nn), k-step s holds sin and
         // cos of frequencies 16 s + 4 g + 0..3 of its row
         f16x8 B[2][8];
@@ -581,16 +597,15 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
                 B[t][s] = (f16x8){h0[0], h0[1], h1[0], h1[1], h2[0], h2[1], h3[0], h3[1]};
             }
         }
+        stage_wait();
         __syncthreads();
 #pragma unroll
         for (int layer = 0; layer < 4; ++layer) {
             const int S = layer == 0 ? 4 : 8;
             if (layer > 0) {
                 __syncthreads();  // every wave is done with the previous layer's weights
-                const uint4* src = reinterpret_cast<const uint4*>(a.wfrag + (int64_t)(kL1Frags + (layer - 1) * kLFrags) *
-                                                                            kFragHalves);
-                uint4* dst = reinterpret_cast<uint4*>(wl);
-                for (int i = tid; i < kLFrags * 64; i += 512) dst[i] = src[i];
+                stage_frags<kLFrags>(wrsrc, (uint32_t)((kL1Frags + (layer - 1) * kLFrags) * kFragHalves * 2), wl, tid);
+                stage_wait();
                 __syncthreads();
             }
             // software pipeline over the 8 output groups (32 features each): the
