@@ -466,24 +466,35 @@ struct InferV2Args {
     float* out;
 };
 
-__device__ __forceinline__ f16x2 gelu2(f16x2 x) {
+// Two independent GELU pairs evaluated in lockstep: each step of one chain
+// fills the slot that a dependent packed instruction of the other must wait.
+// u = x / 4 is not clamped: t = min(u^2, 1) bounds the polynomial's argument,
+// and for |u| > 1 the value 1/2 + u Q(1) lies outside [0, 1] (Q(1) > 1/2), so
+// the clamp of the result gives 0 or 1 exactly as with u clamped to [-1, 1].
+// Both clamps to [0, 1] become the instructions' clamp bits.
+__device__ __forceinline__ void gelu2x2(f16x2& x0, f16x2& x1) {
     auto c = [](float v) { return (f16x2){(_Float16)v, (_Float16)v}; };
-    // u = x / 4 is not clamped: t = min(u^2, 1) bounds the polynomial's argument,
-    // and for |u| > 1 the value 1/2 + u Q(1) lies outside [0, 1] (Q(1) > 1/2), so
-    // the clamp of the result gives 0 or 1 exactly as with u clamped to [-1, 1].
-    // Both clamps to [0, 1] become the instructions' clamp bits.
-    const f16x2 u = x * c(0.25f);
-    const f16x2 t = __builtin_elementwise_min(__builtin_elementwise_max(u * u, c(0.0f)), c(1.0f));
-    f16x2 p = c(1.60618985f);
-    p = __builtin_elementwise_fma(p, t, c(-6.98037448f));
-    p = __builtin_elementwise_fma(p, t, c(12.9487521f));
-    p = __builtin_elementwise_fma(p, t, c(-13.5802262f));
-    p = __builtin_elementwise_fma(p, t, c(9.05178404f));
-    p = __builtin_elementwise_fma(p, t, c(-4.1370718f));
-    p = __builtin_elementwise_fma(p, t, c(1.59098072f));
-    f16x2 ph = __builtin_elementwise_fma(u, p, c(0.5f));
-    ph = __builtin_elementwise_min(__builtin_elementwise_max(ph, c(0.0f)), c(1.0f));
-    return x * ph;
+    auto clamp01 = [](f16x2 v) {
+        return __builtin_elementwise_min(__builtin_elementwise_max(v, (f16x2){(_Float16)0.0f, (_Float16)0.0f}),
+                                         (f16x2){(_Float16)1.0f, (_Float16)1.0f});
+    };
+    const f16x2 u0 = x0 * c(0.25f), u1 = x1 * c(0.25f);
+    const f16x2 t0 = clamp01(u0 * u0), t1 = clamp01(u1 * u1);
+    f16x2 p0 = c(1.60618985f), p1 = c(1.60618985f);
+    p0 = __builtin_elementwise_fma(p0, t0, c(-6.98037448f));
+    p1 = __builtin_elementwise_fma(p1, t1, c(-6.98037448f));
+    p0 = __builtin_elementwise_fma(p0, t0, c(12.9487521f));
+    p1 = __builtin_elementwise_fma(p1, t1, c(12.9487521f));
+    p0 = __builtin_elementwise_fma(p0, t0, c(-13.5802262f));
+    p1 = __builtin_elementwise_fma(p1, t1, c(-13.5802262f));
+    p0 = __builtin_elementwise_fma(p0, t0, c(9.05178404f));
+    p1 = __builtin_elementwise_fma(p1, t1, c(9.05178404f));
+    p0 = __builtin_elementwise_fma(p0, t0, c(-4.1370718f));
+    p1 = __builtin_elementwise_fma(p1, t1, c(-4.1370718f));
+    p0 = __builtin_elementwise_fma(p0, t0, c(1.59098072f));
+    p1 = __builtin_elementwise_fma(p1, t1, c(1.59098072f));
+    x0 = x0 * clamp01(__builtin_elementwise_fma(u0, p0, c(0.5f)));
+    x1 = x1 * clamp01(__builtin_elementwise_fma(u1, p1, c(0.5f)));
 }
 
 __device__ __forceinline__ f16x2 to_f16x2(float a, float b) {
@@ -642,8 +653,9 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
                     }
                     if (q > 0 && s < 4) {  // pair s of the previous group, both n-tiles
                         const int mi = s >> 1, r = (s & 1) * 2;
-#pragma unroll
-                        for (int t = 0; t < 2; ++t) hp[t][s] = gelu2(to_f16x2(accp[mi][t][r], accp[mi][t][r + 1]));
+                        hp[0][s] = to_f16x2(accp[mi][0][r], accp[mi][0][r + 1]);
+                        hp[1][s] = to_f16x2(accp[mi][1][r], accp[mi][1][r + 1]);
+                        gelu2x2(hp[0][s], hp[1][s]);
                     }
                 }
                 if (q > 0) {
