@@ -552,8 +552,21 @@ __device__ __forceinline__ void stage_frags(__amdgpu_buffer_rsrc_t rsrc, uint32_
 
 __device__ __forceinline__ void stage_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Half h of layer L: output groups 4h..4h+3, i.e. fragments [h, h + 1) * (half
+// of the layer's fragments); layer 1 has 32 fragments per half, the others 64.
+template <int L, int H>
+__device__ __forceinline__ void stage_half(__amdgpu_buffer_rsrc_t rsrc, _Float16* dst, int tid) {
+    constexpr int kHalf = (L == 0 ? kL1Frags : kLFrags) / 2;
+    constexpr uint32_t first = (uint32_t)((L == 0 ? 0 : kL1Frags + (L - 1) * kLFrags) + H * kHalf) * kFragHalves * 2;
+    stage_frags<kHalf>(rsrc, first, dst, tid);
+}
+
 __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
-    __shared__ __attribute__((aligned(16))) _Float16 wl[kLFrags * kFragHalves];  // 128 KB: one layer
+    // The weights of a layer in two 64 KB halves: wa holds output groups 0-3, wb
+    // groups 4-7.  Each half is refilled with the next half as soon as every wave
+    // is done with it, so a copy overlaps half a layer of MFMAs.
+    __shared__ __attribute__((aligned(16))) _Float16 wa[kLFrags / 2 * kFragHalves];
+    __shared__ __attribute__((aligned(16))) _Float16 wb[kLFrags / 2 * kFragHalves];
     __shared__ float bias_s[4][256];
     __shared__ float ff_s[kFreq * 5];
     __shared__ float w5_s[256];
@@ -565,7 +578,9 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
     const __amdgpu_buffer_rsrc_t wrsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void*)a.wfrag, (short)0, (int)((kL1Frags + 3 * kLFrags) * kFragHalves * 2), 0x00020000);
     const int64_t cells = (int64_t)a.gnx * a.gny;
-    for (int64_t base = (int64_t)blockIdx.x * kV2Rows; base < a.total; base += (int64_t)gridDim.x * kV2Rows) {
+    const int64_t step = (int64_t)gridDim.x * kV2Rows;
+    if ((int64_t)blockIdx.x * kV2Rows < a.total) stage_half<0, 0>(wrsrc, wa, tid);
+    for (int64_t base = (int64_t)blockIdx.x * kV2Rows; base < a.total; base += step) {
         int64_t row[2];
         float v[2][5];
 #pragma unroll
@@ -581,8 +596,9 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
             v[t][3] = (float)(a.gx0 + (ix + 0.5) * a.gcell);
             v[t][4] = (float)(a.gy0 + (iy + 0.5) * a.gcell);
         }
-        __syncthreads();  // previous pass done with the LDS weights (and the small tables are written)
-        stage_frags<kL1Frags>(wrsrc, 0u, wl, tid);  // layer 1 weights, waited for after the features
+        stage_wait();     // first half of layer 1 in wa
+        __syncthreads();  // every wave done with wb (and the small tables are written)
+        stage_half<0, 1>(wrsrc, wb, tid);
         // Fourier features as the first B operand: lane (g, nn), k-step s holds sin and
         // cos of frequencies 16 s + 4 g + 0..3 of its row
         f16x8 B[2][8];
@@ -608,16 +624,15 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
                 B[t][s] = (f16x8){h0[0], h0[1], h1[0], h1[1], h2[0], h2[1], h3[0], h3[1]};
             }
         }
-        stage_wait();
-        __syncthreads();
 #pragma unroll
         for (int layer = 0; layer < 4; ++layer) {
             const int S = layer == 0 ? 4 : 8;
             if (layer > 0) {
-                __syncthreads();  // every wave is done with the previous layer's weights
-                stage_frags<kLFrags>(wrsrc, (uint32_t)((kL1Frags + (layer - 1) * kLFrags) * kFragHalves * 2), wl, tid);
-                stage_wait();
-                __syncthreads();
+                stage_wait();     // first half of this layer in wa
+                __syncthreads();  // every wave done with wb
+                if (layer == 1) stage_half<1, 1>(wrsrc, wb, tid);
+                if (layer == 2) stage_half<2, 1>(wrsrc, wb, tid);
+                if (layer == 3) stage_half<3, 1>(wrsrc, wb, tid);
             }
             // software pipeline over the 8 output groups (32 features each): the
             // GELU of group q - 1 is interleaved with the MFMAs of group q, one of
@@ -627,6 +642,14 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
             f16x2 hp[2][4];
 #pragma unroll
             for (int q = 0; q <= 8; ++q) {
+                if (q == 4) {
+                    stage_wait();     // second half of this layer in wb
+                    __syncthreads();  // every wave done with wa
+                    if (layer == 0) stage_half<1, 0>(wrsrc, wa, tid);
+                    if (layer == 1) stage_half<2, 0>(wrsrc, wa, tid);
+                    if (layer == 2) stage_half<3, 0>(wrsrc, wa, tid);
+                    if (layer == 3 && base + step < a.total) stage_half<0, 0>(wrsrc, wa, tid);  // next pass
+                }
                 floatx4 acc[2][2];
                 if (q < 8) {
 #pragma unroll
@@ -641,10 +664,12 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
 #pragma unroll
                 for (int s = 0; s < 8; ++s) {
                     if (q < 8 && s < S) {
+                        const _Float16* w = q < 4 ? wa : wb;
+                        const int qq = q & 3;
                         const f16x8 A0 =
-                            *reinterpret_cast<const f16x8*>(wl + ((2 * q) * S + s) * kFragHalves + lane * 8);
+                            *reinterpret_cast<const f16x8*>(w + ((2 * qq) * S + s) * kFragHalves + lane * 8);
                         const f16x8 A1 =
-                            *reinterpret_cast<const f16x8*>(wl + ((2 * q + 1) * S + s) * kFragHalves + lane * 8);
+                            *reinterpret_cast<const f16x8*>(w + ((2 * qq + 1) * S + s) * kFragHalves + lane * 8);
 #pragma unroll
                         for (int t = 0; t < 2; ++t) {
                             acc[0][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, B[t][s], acc[0][t], 0, 0, 0);
