@@ -442,8 +442,10 @@ __global__ void map_inputs_kernel(const float* __restrict__ tx, int32_t T, doubl
 // k-step, 16 bytes per lane) that a block stages layer by layer in LDS.
 // GELU (the tanh form) is evaluated in packed f16 as x clamp(1/2 + u Q(u^2),
 // 0, 1), u = clamp(x / 4, -1, 1), Q a degree-6 least-squares fit (largest
-// deviation 2e-4 in exact arithmetic); the Fourier features use the hardware
-// sine and cosine of the phase in turns.
+// deviation 2e-4 in exact arithmetic); the factor 1/4 is folded into the
+// weights and biases, so each layer's accumulators hold u and it passes on
+// gelu / 4.  The Fourier features use the hardware sine and cosine of the
+// phase in turns.
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef __fp16 fp16x2 __attribute__((ext_vector_type(2)));
@@ -468,17 +470,16 @@ struct InferV2Args {
 
 // Two independent GELU pairs evaluated in lockstep: each step of one chain
 // fills the slot that a dependent packed instruction of the other must wait.
-// u = x / 4 is not clamped: t = min(u^2, 1) bounds the polynomial's argument,
-// and for |u| > 1 the value 1/2 + u Q(1) lies outside [0, 1] (Q(1) > 1/2), so
-// the clamp of the result gives 0 or 1 exactly as with u clamped to [-1, 1].
-// Both clamps to [0, 1] become the instructions' clamp bits.
-__device__ __forceinline__ void gelu2x2(f16x2& x0, f16x2& x1) {
+// In: u = x / 4; out: gelu(x) / 4 = u clamp(1/2 + u Q(min(u^2, 1)), 0, 1).  For
+// |u| > 1 the value 1/2 + u Q(1) lies outside [0, 1] (Q(1) > 1/2), so the
+// clamp gives 0 or 1 exactly as with u clamped to [-1, 1].  Both clamps to
+// [0, 1] become the instructions' clamp bits.
+__device__ __forceinline__ void gelu2x2(f16x2& u0, f16x2& u1) {
     auto c = [](float v) { return (f16x2){(_Float16)v, (_Float16)v}; };
     auto clamp01 = [](f16x2 v) {
         return __builtin_elementwise_min(__builtin_elementwise_max(v, (f16x2){(_Float16)0.0f, (_Float16)0.0f}),
                                          (f16x2){(_Float16)1.0f, (_Float16)1.0f});
     };
-    const f16x2 u0 = x0 * c(0.25f), u1 = x1 * c(0.25f);
     const f16x2 t0 = clamp01(u0 * u0), t1 = clamp01(u1 * u1);
     f16x2 p0 = c(1.60618985f), p1 = c(1.60618985f);
     p0 = __builtin_elementwise_fma(p0, t0, c(-6.98037448f));
@@ -493,8 +494,8 @@ __device__ __forceinline__ void gelu2x2(f16x2& x0, f16x2& x1) {
     p1 = __builtin_elementwise_fma(p1, t1, c(-4.1370718f));
     p0 = __builtin_elementwise_fma(p0, t0, c(1.59098072f));
     p1 = __builtin_elementwise_fma(p1, t1, c(1.59098072f));
-    x0 = x0 * clamp01(__builtin_elementwise_fma(u0, p0, c(0.5f)));
-    x1 = x1 * clamp01(__builtin_elementwise_fma(u1, p1, c(0.5f)));
+    u0 = u0 * clamp01(__builtin_elementwise_fma(u0, p0, c(0.5f)));
+    u1 = u1 * clamp01(__builtin_elementwise_fma(u1, p1, c(0.5f)));
 }
 
 __device__ __forceinline__ f16x2 to_f16x2(float a, float b) {
@@ -531,7 +532,10 @@ __global__ void v2_weights_kernel(const float* __restrict__ params, MlpLayout la
     const int mrow = mt * 16 + (lane & 15), g = lane >> 4;
     const int K = lay.fan_in[layer];
     const float* W = params + lay.w_off[layer];
-    for (int j = 0; j < 8; ++j) wfrag[e * 8 + j] = (_Float16)W[(int64_t)mrow * K + v2_column(layer, s, g, j)];
+    // layer 1 is scaled by 1/4 (the kernel's accumulators hold z / 4); the inputs
+    // of layers 2..4 arrive divided by 4, so their weights stay as they are
+    const float sc = layer == 0 ? 0.25f : 1.0f;
+    for (int j = 0; j < 8; ++j) wfrag[e * 8 + j] = (_Float16)(sc * W[(int64_t)mrow * K + v2_column(layer, s, g, j)]);
 }
 
 // Copies N fragments (N * 64 16-byte lanes), starting at byte `first` of the
@@ -571,9 +575,13 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
     __shared__ float ff_s[kFreq * 5];
     __shared__ float w5_s[256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, nn = lane & 15;
-    for (int i = tid; i < 4 * 256; i += 512) bias_s[i / 256][i % 256] = a.params[a.lay.b_off[i / 256] + i % 256];
+    // Every layer computes u = z / 4 and passes on gelu(z) / 4 (powers of two, so
+    // exact): biases are scaled by 1/4 here, layer 1's weights by 1/4 in the
+    // fragment copy, and the head's weights by 4.
+    for (int i = tid; i < 4 * 256; i += 512)
+        bias_s[i / 256][i % 256] = 0.25f * a.params[a.lay.b_off[i / 256] + i % 256];
     for (int i = tid; i < kFreq * 5; i += 512) ff_s[i] = a.ff[i];
-    for (int i = tid; i < 256; i += 512) w5_s[i] = a.params[a.lay.w_off[4] + i];
+    for (int i = tid; i < 256; i += 512) w5_s[i] = 4.0f * a.params[a.lay.w_off[4] + i];
     const float b5 = a.params[a.lay.b_off[4]];
     const __amdgpu_buffer_rsrc_t wrsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void*)a.wfrag, (short)0, (int)((kL1Frags + 3 * kLFrags) * kFragHalves * 2), 0x00020000);
