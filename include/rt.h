@@ -320,7 +320,8 @@ rt_status rt_mlp_sample_batch(rt_mlp* mlp, const float* maps, const uint32_t* in
                               int32_t T, const rt_grid* grid, uint64_t seed, uint64_t step, float* v, float* t,
                               float* m, int64_t n);
 /* Predicted maps [T][ny][nx] (dev, dB) for transmitters tx [T][3] (dev) on the
- * grid's cell centres. */
+ * grid's cell centres.  RT_ERR_ARG for an empty stack or one of 2^40 cells or
+ * more. */
 rt_status rt_mlp_predict_maps(rt_mlp* mlp, const float* tx, int32_t T, const rt_grid* grid, float* maps);
 
 #ifdef __cplusplus

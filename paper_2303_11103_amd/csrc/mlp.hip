@@ -573,7 +573,8 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
     __shared__ __attribute__((aligned(16))) _Float16 wb[kLFrags / 2 * kFragHalves];
     __shared__ float bias_s[4][256];
     __shared__ float ff_s[kFreq * 5];
-    __shared__ float w5_s[256];
+    // head weights (times 4) as row 0 of a 16-row A operand, one fragment per k-step
+    __shared__ __attribute__((aligned(16))) _Float16 head_s[8 * kFragHalves];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, nn = lane & 15;
     // Every layer computes u = z / 4 and passes on gelu(z) / 4 (powers of two, so
     // exact): biases are scaled by 1/4 here, layer 1's weights by 1/4 in the
@@ -581,11 +582,20 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
     for (int i = tid; i < 4 * 256; i += 512)
         bias_s[i / 256][i % 256] = 0.25f * a.params[a.lay.b_off[i / 256] + i % 256];
     for (int i = tid; i < kFreq * 5; i += 512) ff_s[i] = a.ff[i];
-    for (int i = tid; i < 256; i += 512) w5_s[i] = 4.0f * a.params[a.lay.w_off[4] + i];
+    for (int i = tid; i < 8 * 64; i += 512) {
+        const int s = i >> 6, l = i & 63;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            head_s[i * 8 + j] =
+                (l & 15) == 0 ? (_Float16)(4.0f * a.params[a.lay.w_off[4] + v2_column(1, s, l >> 4, j)]) : (_Float16)0.0f;
+    }
     const float b5 = a.params[a.lay.b_off[4]];
     const __amdgpu_buffer_rsrc_t wrsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void*)a.wfrag, (short)0, (int)((kL1Frags + 3 * kLFrags) * kFragHalves * 2), 0x00020000);
     const int64_t cells = (int64_t)a.gnx * a.gny;
+    // row -> (map, cell) by fp64 reciprocals: rows stay below 2^40, so the
+    // quotient is off by at most one and a single correction makes it exact
+    const double inv_cells = 1.0 / (double)cells, inv_gnx = 1.0 / (double)a.gnx;
     const int64_t step = (int64_t)gridDim.x * kV2Rows;
     if ((int64_t)blockIdx.x * kV2Rows < a.total) stage_half<0, 0>(wrsrc, wa, tid);
     for (int64_t base = (int64_t)blockIdx.x * kV2Rows; base < a.total; base += step) {
@@ -596,8 +606,24 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
             int64_t r = base + wave * 32 + t * 16 + nn;
             row[t] = r;
             if (r >= a.total) r = a.total - 1;
-            const int64_t ti = r / cells, c = r - ti * cells;
-            const int64_t iy = c / a.gnx, ix = c - iy * a.gnx;
+            int64_t ti = (int64_t)((double)r * inv_cells);
+            int64_t c = r - ti * cells;
+            if (c < 0) {
+                --ti;
+                c += cells;
+            } else if (c >= cells) {
+                ++ti;
+                c -= cells;
+            }
+            int32_t iy = (int32_t)((double)c * inv_gnx);
+            int32_t ix = (int32_t)c - iy * a.gnx;
+            if (ix < 0) {
+                --iy;
+                ix += a.gnx;
+            } else if (ix >= a.gnx) {
+                ++iy;
+                ix -= a.gnx;
+            }
             v[t][0] = a.tx[3 * ti];
             v[t][1] = a.tx[3 * ti + 1];
             v[t][2] = a.tx[3 * ti + 2];
@@ -709,19 +735,18 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
 #pragma unroll
                 for (int q = 0; q < 8; ++q) B[t][q] = Bn[t][q];
         }
-        // head: lane's features of B[t][q] are 32 q + 4 g + j (j < 4) and 32 q + 16 + 4 g + j - 4
+        // head: output row 0 of C = W5 B lands in element 0 of the lanes with g = 0
+        floatx4 hy[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            float y = 0.0f;
+        for (int s = 0; s < 8; ++s) {
+            const f16x8 A = *reinterpret_cast<const f16x8*>(head_s + s * kFragHalves + lane * 8);
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-#pragma unroll
-                for (int j = 0; j < 8; ++j) y = fmaf(w5_s[v2_column(1, q, g, j)], (float)B[t][q][j], y);
-            y += __shfl_xor(y, 16);
-            y += __shfl_xor(y, 32);
-            if (g == 0 && row[t] < a.total)
-                a.out[row[t]] = y + b5 + prior_db(a.norm, v[t][0], v[t][1], v[t][2], v[t][3], v[t][4]);
+            for (int t = 0; t < 2; ++t) hy[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B[t][s], hy[t], 0, 0, 0);
         }
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+            if (g == 0 && row[t] < a.total)
+                a.out[row[t]] = hy[t][0] + b5 + prior_db(a.norm, v[t][0], v[t][1], v[t][2], v[t][3], v[t][4]);
     }
 }
 

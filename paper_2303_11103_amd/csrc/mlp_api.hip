@@ -366,6 +366,7 @@ rt_status rt_mlp_sample_batch(rt_mlp* h, const float* maps, const uint32_t* inde
 rt_status rt_mlp_predict_maps(rt_mlp* h, const float* tx, int32_t T, const rt_grid* g, float* maps) {
     if (!h || !tx || !g || !maps) return rt_internal_fail(RT_ERR_ARG, "NULL argument");
     if (T < 1 || g->nx < 1 || g->ny < 1) return rt_internal_fail(RT_ERR_ARG, "empty map stack");
+    if ((double)T * g->nx * g->ny >= 0x1p40) return rt_internal_fail(RT_ERR_ARG, "map stack of 2^40 cells or more");
     hipStream_t s = rt_internal_stream(h->ctx);
     MLP_HIP(hipSetDevice(rt_internal_device(h->ctx)));
     MLP_HIP(rt::launch_infer_v2(tx, T, g->x0, g->y0, g->cell, g->nx, g->ny, h->ff, h->norm, h->wfrag, h->lay,
