@@ -11,8 +11,11 @@ constexpr int kBlock = 256;       // block size of kernels that do not stage nod
 constexpr int kTraceBlock = 512;  // block size of the shoot-and-bounce kernels
 constexpr int kStack = kStackEntries;
 constexpr int kLdsNodes = 128;    // top BVH nodes (breadth-first order) staged in LDS, 16 KB
-constexpr float kDn = 1.0f - 1e-6f;  // conservative slab interval factors
-constexpr float kUp = 1.0f + 1e-6f;
+// Conservative slab interval: a box is entered when near <= far (1 + 3e-6).
+// This accepts every box that near (1 - 1e-6) <= far (1 + 1e-6) accepts, each
+// product rounded, at one multiplication per box.
+constexpr float kWiden = 1.0f + 3e-6f;
+constexpr float kAnyFar = 1.0f + 1e-6f;  // far limit of a segment query (t <= 1), slightly widened
 
 // Smallest float >= t for t >= 0 (inf stays inf).
 __device__ __forceinline__ float f_up(double t) {
@@ -88,7 +91,7 @@ __device__ __forceinline__ float slab(float lx, float hx, float ly, float hy, fl
     const float c0 = fmaf(lz, iz, -oiz), c1 = fmaf(hz, iz, -oiz);
     const float n = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), 0.0f));
     const float f = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), tfar));
-    return n * kDn <= f * kUp ? n : __builtin_inff();
+    return n <= f * kWiden ? n : __builtin_inff();
 }
 
 __device__ __forceinline__ void cswap(float& ka, int& va, float& kb, int& vb) {
@@ -116,7 +119,7 @@ __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_node
     const float ox = (float)o.x, oy = (float)o.y, oz = (float)o.z;
     const float ix = safe_inv(d.x), iy = safe_inv(d.y), iz = safe_inv(d.z);
     const float oix = ox * ix, oiy = oy * iy, oiz = oz * iz;
-    float tfar = ANY ? kUp : f_up(tbest);
+    float tfar = ANY ? kAnyFar : f_up(tbest);
     int best = -1;
     int node = 0, sp = 0;
     if constexpr (!OVF) {
