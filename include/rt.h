@@ -246,6 +246,24 @@ rt_status rt_paths_power_grad(rt_ctx* ctx, rt_scene* scene, const rt_trace_param
                               const rt_device* rx, int32_t nrx, int32_t P, const int32_t* depth,
                               const int32_t* faces, const double* dL_dP, double* grad);
 
+/* Coverage-map gradient (Sec. III-B: gradient steps on a transmitter's
+ * orientation; Sec. III-A: on radio materials).  For the coverage map of
+ * rt_coverage_map with the same p, tx, rx_ant and grid, the path gain summed
+ * over the region cells,
+ *   G = sum over cells c with region[c] != 0 of gain[c]   (linear),
+ * and its derivatives with respect to (eps_r, sigma) of every material and the
+ * transmitter yaw and pitch.  The rays are fixed by their recorded hits
+ * (hit_tri, hit_t from rt_trace_record with the same p and tx): ray geometry
+ * does not depend on these parameters, and every ray is replayed in fp64 with
+ * forward-mode field tangents.
+ *   region [ny][nx] (dev, nullable: every cell) uint8;
+ *   out [2*nm + 3] (dev) float64 = (G, dG/d eps_r_0, dG/d sigma_0, ...,
+ *   dG/d yaw, dG/d pitch), cleared first.
+ * RT_ERR_ARG for more than 4 materials.  Enqueued, not synchronous. */
+rt_status rt_coverage_grad(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p, const rt_device* tx,
+                           const rt_device* rx_ant, const rt_grid* grid, const uint8_t* region,
+                           const int32_t* hit_tri, const double* hit_t, double* out);
+
 /* ------------------------------------------------------------------ surrogate */
 
 /* Learned coverage-map surrogate (the paper motivates neural propagation

@@ -25,5 +25,6 @@ Modules
   sbr       shoot-and-bounce tracing and the coverage-map estimator
   image     image-method paths (exhaustive and candidate-driven)
   grad      received-power loss and central finite differences
+  covgrad   coverage-map region gain and its central finite differences
   mlp       float64 Fourier-feature MLP with manual backward (surrogate)
 """

@@ -85,6 +85,8 @@ SIGNATURES = {
     "rt_paths_power": [P, P, P, I64, I32, P],
     "rt_paths_power_grad": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), P, I32, I32, P, P,
                             P, P],
+    "rt_coverage_grad": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), ctypes.POINTER(rt_device),
+                         ctypes.POINTER(rt_grid), P, P, P, P],
     "rt_mlp_param_count": [ctypes.POINTER(I64)],
     "rt_mlp_create": [P, ctypes.POINTER(rt_mlp_config), ctypes.POINTER(P)],
     "rt_mlp_destroy": [P],

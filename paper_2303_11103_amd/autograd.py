@@ -45,3 +45,34 @@ class ReceivedPower(torch.autograd.Function):
 def received_power(theta, ctx, scene, params, tx, rxs):
     """Differentiable P_r (float64 tensor [nrx]) as a function of theta."""
     return ReceivedPower.apply(theta, ctx, scene, params, tx, rxs)
+
+
+class CoverageRegionGain(torch.autograd.Function):
+    """G = linear path gain of the coverage map summed over a region of cells,
+    as a function of theta = ((eps_r, sigma) per material, tx yaw, tx pitch)
+    (float64, 2*nm + 2).  The forward records the rays' hits and replays them
+    with field tangents (rt_coverage_grad); G and dG/dtheta come from the same
+    replay, and the backward scales the saved gradient."""
+
+    @staticmethod
+    def forward(fctx, theta, ctx, scene, params, tx, grid, region, rx_ant):
+        th = theta.detach().to("cpu", torch.float64).numpy()
+        nm = scene.nm
+        scene.set_materials(th[:2 * nm].reshape(nm, 2))
+        dev = SimpleNamespace(pos=tuple(float(x) for x in tx.pos), yaw=float(th[2 * nm]), pitch=float(th[2 * nm + 1]),
+                              roll=float(tx.roll), pattern=int(tx.pattern))
+        hit_tri, hit_t = rt.trace_record(ctx, scene, params, dev)
+        out = rt.coverage_grad(ctx, scene, params, dev, grid, hit_tri, hit_t, region=region, rx_ant=rx_ant)
+        fctx.save_for_backward(out[1:].clone())
+        return out[0].clone()
+
+    @staticmethod
+    def backward(fctx, grad_g):
+        (g,) = fctx.saved_tensors
+        return grad_g.to(torch.float64) * g, None, None, None, None, None, None, None
+
+
+def coverage_region_gain(theta, ctx, scene, params, tx, grid, region=None, rx_ant=None):
+    """Differentiable summed path gain (float64 scalar tensor) of the region
+    cells (uint8 mask [ny][nx], None: every cell) as a function of theta."""
+    return CoverageRegionGain.apply(theta, ctx, scene, params, tx, grid, region, rx_ant)

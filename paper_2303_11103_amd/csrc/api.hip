@@ -85,7 +85,7 @@ struct rt_scene {
     rt_ctx* ctx = nullptr;
     rt::HostScene host;
     std::vector<rt_material> mats;
-    DevBuf nodes, tris, shades, faces, face_tris;
+    DevBuf nodes, tris, shades, faces, face_tris, leaf_of_input;
     rt::DevScene dev{};
 };
 
@@ -362,6 +362,9 @@ rt_status rt_scene_create(rt_ctx* c, const float* V, int64_t nv, const int32_t* 
     up(s->shades, h.shades.data(), h.shades.size() * sizeof(rt::Shade));
     up(s->faces, h.faces.data(), h.faces.size() * sizeof(rt::Face));
     up(s->face_tris, h.face_tris.data(), h.face_tris.size() * sizeof(int32_t));
+    std::vector<int32_t> leaf(h.tris.size());
+    for (size_t k = 0; k < h.tris.size(); ++k) leaf[h.tris[k].orig] = (int32_t)k;
+    up(s->leaf_of_input, leaf.data(), leaf.size() * sizeof(int32_t));
     if (e != hipSuccess) {
         rt_scene_destroy(s);
         return fail(e == hipErrorOutOfMemory ? RT_ERR_OOM : RT_ERR_DEVICE, hipGetErrorString(e));
@@ -375,6 +378,7 @@ rt_status rt_scene_create(rt_ctx* c, const float* V, int64_t nv, const int32_t* 
     s->dev.nt = (int32_t)nt;
     s->dev.num_nodes = (int32_t)h.nodes.size();
     s->dev.stack_need = h.stack_need;
+    s->dev.leaf_of_input = (const int32_t*)s->leaf_of_input.p;
     *out = s;
     return RT_OK;
 }
@@ -764,6 +768,54 @@ rt_status rt_paths_power_grad(rt_ctx* c, rt_scene* s, const rt_trace_params* p, 
     g.grad = grad;
     g.nm = nm;
     RT_HIP(rt::launch_power_grad(g, make_mats(s, p->freq_hz), c->stream));
+    return RT_OK;
+}
+
+rt_status rt_coverage_grad(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx,
+                           const rt_device* rx_ant, const rt_grid* g, const uint8_t* region, const int32_t* hit_tri,
+                           const double* hit_t, double* out) {
+    if (!c || !s || !g || !hit_tri || !hit_t || !out) return fail(RT_ERR_ARG, "NULL argument");
+    rt_status st = check_params(p);
+    if (st != RT_OK) return st;
+    if ((st = check_device(tx, "tx", s->host.max_abs)) != RT_OK) return st;
+    if ((st = check_device(rx_ant, "rx_ant", 0)) != RT_OK) return st;
+    if (g->nx < 1 || g->ny < 1 || (int64_t)g->nx * g->ny > (int64_t(1) << 31))
+        return fail(RT_ERR_ARG, "grid size must be positive and below 2^31 cells");
+    if (!(g->cell > 0) || !std::isfinite(g->cell) || !std::isfinite(g->x0) || !std::isfinite(g->y0) ||
+        !std::isfinite(g->z))
+        return fail(RT_ERR_ARG, "grid origin, cell size and height must be finite, cell > 0");
+    const int nm = (int)s->mats.size();
+    if (nm > rt::kCovMaxMat) return fail(RT_ERR_ARG, "coverage gradient supports at most 4 materials");
+    RT_HIP(hipSetDevice(c->device));
+    RT_HIP(hipMemsetAsync(out, 0, (size_t)(2 * nm + 3) * sizeof(double), c->stream));
+    rt::CovGradArgs a{};
+    a.sc = s->dev;
+    a.num_rays = p->num_rays;
+    a.begin = p->ray_begin;
+    a.stride = p->ray_stride;
+    a.count = traced_count(p);
+    a.max_depth = p->max_depth;
+    a.nm = nm;
+    for (int k = 0; k < 3; ++k) a.tx[k] = tx->pos[k];
+    a.yaw = tx->yaw;
+    a.pitch = tx->pitch;
+    a.roll = tx->roll;
+    a.tx_pattern = tx->pattern;
+    a.gnx = g->nx;
+    a.gny = g->ny;
+    a.rx_ant = make_antenna(rx_ant);
+    a.gx0 = g->x0;
+    a.gy0 = g->y0;
+    a.gcell = g->cell;
+    a.gz = g->z;
+    const double lam = kC0 / p->freq_hz;
+    a.wscale = (lam / (4.0 * M_PI)) * (lam / (4.0 * M_PI)) * (4.0 * M_PI / (double)p->num_rays) / (g->cell * g->cell);
+    a.omega = 2.0 * M_PI * p->freq_hz;
+    a.region = region;
+    a.hit_tri = hit_tri;
+    a.hit_t = hit_t;
+    a.out = out;
+    RT_HIP(rt::launch_coverage_grad(a, make_mats(s, p->freq_hz), grid_for(c), c->stream));
     return RT_OK;
 }
 

@@ -166,6 +166,17 @@ __device__ __forceinline__ d3 antenna_field(const Antenna& ant, d3 d) {
     return d3{R[0] * tx + R[1] * ty + R[2] * tz, R[3] * tx + R[4] * ty + R[5] * tz, R[6] * tx + R[7] * ty + R[8] * tz};
 }
 
+// Direction of Fibonacci-lattice ray i of N (Sec. II-B): z = 1 - (2i+1)/N,
+// azimuth 2 pi frac(i g) with frac(i g) = (i * 0x9E3779B97F4A7C15 mod 2^64) / 2^64.
+__device__ __forceinline__ d3 fib_dir(int64_t i, int64_t N) {
+    const double z = 1.0 - (2.0 * (double)i + 1.0) / (double)N;
+    const double rho = sqrt((1.0 - z) * (1.0 + z));
+    const uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+    double s, c;
+    sincospi(2.0 * ((double)h * 0x1p-64), &s, &c);  // angle 2 pi frac(i g)
+    return d3{rho * c, rho * s, z};
+}
+
 // ---------------------------------------------------------------- Fresnel
 __device__ __forceinline__ void fresnel(const Mat& m, float cos_i, cf& r_perp, cf& r_par) {
     if (m.pec) {

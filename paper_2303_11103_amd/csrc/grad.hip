@@ -351,6 +351,155 @@ __global__ void power_grad_kernel(GradArgs g, MatTable mats) {
     }
 }
 
+// ------------------------------------------------------------------ coverage
+// Gradient of the path gain summed over a region of coverage-map cells with
+// respect to the radio materials and the transmitter orientation (the
+// coverage analogue of the received-power gradient; Sec. III-B optimises a
+// transmitter orientation by gradient steps).  Ray geometry does not depend
+// on these parameters, so the recorded hits (triangle and distance per
+// segment) fix every ray; one thread per ray replays it in fp64 with the
+// same formulas as the shoot-and-bounce kernel and carries, beside the field
+// E, its tangents dE/dtheta:
+//   * at launch, d F_tx / d(yaw, pitch) from the dual-number transmit pattern;
+//   * at a reflection off material m, E' = R E gives
+//     dE'/dtheta = R dE/dtheta + [theta of m] (dR/d eta) E (d eta/d theta),
+//     with dR/d eta from d r_perp / d eta and d r_par / d eta as above;
+//   * every crossing of the grid plane inside the region adds
+//     w = wscale |F_rx . E|^2 / |d_z| and dw = wscale 2 Re(conj(a) F_rx . dE) / |d_z|.
+__device__ __forceinline__ cd dot3(const cd* v, d3 u) {
+    return cd{v[0].re * u.x + v[1].re * u.y + v[2].re * u.z, v[0].im * u.x + v[1].im * u.y + v[2].im * u.z};
+}
+
+__global__ __launch_bounds__(256) void coverage_grad_kernel(CovGradArgs g, MatTable mats) {
+    __shared__ double red[4][1 + kCovT];
+    double acc[1 + kCovT];
+#pragma unroll
+    for (int i = 0; i <= kCovT; ++i) acc[i] = 0.0;
+    const int yaw_t = 2 * kCovMaxMat, pitch_t = 2 * kCovMaxMat + 1;
+    // transmit pattern tangents are those of dantenna's slots 3 (yaw) and 4 (pitch)
+    D yaw = dc(g.yaw), pitch = dc(g.pitch);
+    yaw.d[3] = 1.0;
+    pitch.d[4] = 1.0;
+    const DRot Rt = drot(yaw, pitch, dc(g.roll));
+    const double dsig = 1.0 / (kEps0 * g.omega);
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < g.count;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        d3 d = fib_dir(g.begin + j * g.stride, g.num_rays);
+        d3 o{g.tx[0], g.tx[1], g.tx[2]};
+        const D3 F0 = dantenna(Rt, g.tx_pattern, dconst(d));
+        cd E[3] = {cd{F0.x.v, 0.0}, cd{F0.y.v, 0.0}, cd{F0.z.v, 0.0}};
+        cd dE[kCovT][3];
+#pragma unroll
+        for (int i = 0; i < kCovT; ++i) dE[i][0] = dE[i][1] = dE[i][2] = cd{0.0, 0.0};
+        dE[yaw_t][0] = cd{F0.x.d[3], 0.0};
+        dE[yaw_t][1] = cd{F0.y.d[3], 0.0};
+        dE[yaw_t][2] = cd{F0.z.d[3], 0.0};
+        dE[pitch_t][0] = cd{F0.x.d[4], 0.0};
+        dE[pitch_t][1] = cd{F0.y.d[4], 0.0};
+        dE[pitch_t][2] = cd{F0.z.d[4], 0.0};
+        for (int k = 0; k <= g.max_depth; ++k) {
+            const int32_t tri = g.hit_tri[(int64_t)k * g.count + j];
+            if (tri == -2) break;
+            const double t = g.hit_t[(int64_t)k * g.count + j];
+            const double dz = d.z;
+            if (fabs(dz) >= 1e-12) {
+                const double tc = (g.gz - o.z) / dz;
+                if (tc > 0.0 && tc < t) {
+                    const double x = o.x + tc * d.x, y = o.y + tc * d.y;
+                    const double fx = floor((x - g.gx0) / g.gcell), fy = floor((y - g.gy0) / g.gcell);
+                    if (fx >= 0.0 && fx < (double)g.gnx && fy >= 0.0 && fy < (double)g.gny) {
+                        const int64_t cell = (int64_t)fy * g.gnx + (int64_t)fx;
+                        if (!g.region || g.region[cell]) {
+                            const d3 fr = antenna_field(g.rx_ant, d3{-d.x, -d.y, -d.z});
+                            const cd a = dot3(E, fr);
+                            const double w0 = g.wscale / fabs(dz);
+                            acc[0] += w0 * (a.re * a.re + a.im * a.im);
+#pragma unroll
+                            for (int i = 0; i < kCovT; ++i) {
+                                const cd da = dot3(dE[i], fr);
+                                acc[1 + i] += 2.0 * w0 * (a.re * da.re + a.im * da.im);
+                            }
+                        }
+                    }
+                }
+            }
+            if (tri < 0 || k == g.max_depth || tri >= g.sc.nt) break;
+            const Shade sh = g.sc.shades[g.sc.leaf_of_input[tri]];
+            d3 n{sh.n[0], sh.n[1], sh.n[2]};
+            if (dot(d, n) > 0.0) n = scale(n, -1.0);
+            const double cos_i = -dot(d, n);
+            const d3 dr = add(d, scale(n, 2.0 * cos_i));
+            const d3 p = add(o, scale(d, t));
+            const d3 ep = perp_basis(d, n);
+            const d3 eli = cross(ep, d);
+            const d3 elr = cross(ep, dr);
+            const Mat mt = mats.m[sh.mat];
+            cd rp, rl;
+            fresnel(mt, cos_i, rp, rl);
+            cd drp{0.0, 0.0}, drl{0.0, 0.0};
+            if (!mt.pec) {
+                const cd eta{mt.eta_re_d, mt.eta_im_d};
+                const double sin2 = 1.0 - cos_i * cos_i;
+                const cd s = csqrt(cd{eta.re - sin2, eta.im});
+                const cd cps = cadd(cd{cos_i, 0.0}, s), ecs = cadd(cmulr(eta, cos_i), s);
+                drp = cdiv(cd{-cos_i, 0.0}, cmul(s, cmul(cps, cps)));
+                drl = cdiv(cmulr(csub(eta, cd{2.0 * sin2, 0.0}), cos_i), cmul(s, cmul(ecs, ecs)));
+            }
+            const cd ap = dot3(E, ep), al = dot3(E, eli);
+            const cd sp = cmul(rp, ap), sl = cmul(rl, al);
+            const cd dsp = cmul(drp, ap), dsl = cmul(drl, al);  // d(r a)/d eta
+#pragma unroll
+            for (int i = 0; i < kCovT; ++i) {
+                const cd api = cmul(rp, dot3(dE[i], ep)), ali = cmul(rl, dot3(dE[i], eli));
+                dE[i][0] = cadd(cmulr(api, ep.x), cmulr(ali, elr.x));
+                dE[i][1] = cadd(cmulr(api, ep.y), cmulr(ali, elr.y));
+                dE[i][2] = cadd(cmulr(api, ep.z), cmulr(ali, elr.z));
+            }
+            if (sh.mat < kCovMaxMat && !mt.pec) {
+                const cd de[3] = {cadd(cmulr(dsp, ep.x), cmulr(dsl, elr.x)), cadd(cmulr(dsp, ep.y), cmulr(dsl, elr.y)),
+                                  cadd(cmulr(dsp, ep.z), cmulr(dsl, elr.z))};
+                const cd mj{0.0, -dsig};  // d eta / d sigma = -j / (eps0 w)
+#pragma unroll
+                for (int m = 0; m < kCovMaxMat; ++m)
+                    if (m == sh.mat) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            dE[2 * m][c] = cadd(dE[2 * m][c], de[c]);
+                            dE[2 * m + 1][c] = cadd(dE[2 * m + 1][c], cmul(de[c], mj));
+                        }
+                    }
+            }
+            E[0] = cadd(cmulr(sp, ep.x), cmulr(sl, elr.x));
+            E[1] = cadd(cmulr(sp, ep.y), cmulr(sl, elr.y));
+            E[2] = cadd(cmulr(sp, ep.z), cmulr(sl, elr.z));
+            o = p;
+            d = dr;
+        }
+    }
+    // block reduction (wave shuffles, then the four waves through LDS), one
+    // fp64 atomic per block and output
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i <= kCovT; ++i) {
+        double v = acc[i];
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[wave][i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x <= kCovT) {
+        // slot 0 the region sum, 1 + 2m + {0, 1} material m, then yaw, pitch;
+        // out has 2 nm + 3 entries in the same order
+        const int i = threadIdx.x;
+        int o = -1;
+        if (i == 0) o = 0;
+        else if (i - 1 < 2 * g.nm) o = i;
+        else if (i - 1 == yaw_t) o = 1 + 2 * g.nm;
+        else if (i - 1 == pitch_t) o = 2 + 2 * g.nm;
+        const double v = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+        if (o >= 0 && v != 0.0) atomicAdd(g.out + o, v);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_power_grad(const GradArgs& a, const MatTable& mats, hipStream_t s) {
@@ -358,6 +507,14 @@ hipError_t launch_power_grad(const GradArgs& a, const MatTable& mats, hipStream_
     const int64_t blocks = (n + 127) / 128;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(power_grad_kernel, dim3((unsigned)blocks), dim3(128), 0, s, a, mats);
+    return hipGetLastError();
+}
+
+hipError_t launch_coverage_grad(const CovGradArgs& a, const MatTable& mats, int grid, hipStream_t s) {
+    if (a.count <= 0) return hipSuccess;
+    const int64_t need = (a.count + 255) / 256;
+    const unsigned blocks = (unsigned)(need < grid ? need : grid);
+    hipLaunchKernelGGL(coverage_grad_kernel, dim3(blocks), dim3(256), 0, s, a, mats);
     return hipGetLastError();
 }
 

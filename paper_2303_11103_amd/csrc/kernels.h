@@ -34,6 +34,7 @@ struct DevScene {
     int32_t nt;
     int32_t num_nodes;
     int32_t stack_need;  // worst-case traversal stack entries of the tree
+    const int32_t* leaf_of_input;  // [nt] leaf-order index of each input triangle
 };
 
 struct SbrArgs {
@@ -159,5 +160,28 @@ struct GradArgs {
     int32_t nm;
 };
 hipError_t launch_power_grad(const GradArgs& a, const MatTable& mats, hipStream_t s);
+
+// Coverage-map gradient: replay of recorded rays with field tangents.
+constexpr int kCovMaxMat = 4;                 // materials with tangents
+constexpr int kCovT = 2 * kCovMaxMat + 2;     // (eps_r, sigma) per material, yaw, pitch
+struct CovGradArgs {
+    DevScene sc;
+    int64_t num_rays, begin, stride, count;
+    int32_t max_depth;
+    int32_t nm;
+    double tx[3];
+    double yaw, pitch, roll;
+    int32_t tx_pattern;
+    int32_t gnx, gny;
+    Antenna rx_ant;
+    double gx0, gy0, gcell, gz;
+    double wscale;            // (lambda/4pi)^2 (4pi/N) / cell^2
+    double omega;             // 2 pi f
+    const uint8_t* region;    // [gny][gnx] (nullable: every cell)
+    const int32_t* hit_tri;   // [max_depth+1][count] input triangle ids (-1 miss, -2 terminated)
+    const double* hit_t;      // [max_depth+1][count]
+    double* out;              // [2 nm + 3]: region sum, d/d(eps_r, sigma) per material, d/d yaw, d/d pitch
+};
+hipError_t launch_coverage_grad(const CovGradArgs& a, const MatTable& mats, int grid, hipStream_t s);
 
 }  // namespace rt

@@ -16,15 +16,6 @@
 namespace rt {
 namespace {
 
-__device__ __forceinline__ d3 fib_dir(int64_t i, int64_t N) {
-    const double z = 1.0 - (2.0 * (double)i + 1.0) / (double)N;
-    const double rho = sqrt((1.0 - z) * (1.0 + z));
-    const uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull;
-    double s, c;
-    sincospi(2.0 * ((double)h * 0x1p-64), &s, &c);  // angle 2 pi frac(i g)
-    return d3{rho * c, rho * s, z};
-}
-
 // q = floor(x / F), r = x - q F for 0 <= x < 2^52 and F < 2^26, using the
 // precomputed double 1/F and one correction step.
 __device__ __forceinline__ void divmod(int64_t x, int64_t F, double invF, int64_t& q, int64_t& r) {

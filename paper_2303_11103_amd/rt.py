@@ -212,6 +212,31 @@ def last_candidate_count(ctx: Context) -> int:
     return int(n.value)
 
 
+def coverage_grad(ctx: Context, scene: Scene, params: TraceParams, tx, grid, hit_tri, hit_t, region=None,
+                  rx_ant=None):
+    """(G, dG/dtheta) with G the linear path gain summed over the region's cells
+    and theta = (eps_r, sigma) per material, tx yaw, tx pitch; the rays are
+    fixed by the records (hit_tri, hit_t) of trace_record with the same params
+    and tx.  Returns a float64 device tensor [1 + 2 nm + 2]."""
+    from types import SimpleNamespace
+    rx_ant = rx_ant or SimpleNamespace(pos=(0.0, 0.0, 0.0), yaw=0.0, pitch=0.0, roll=0.0, pattern=0)
+    n = params.traced()
+    if tuple(hit_tri.shape) != (params.max_depth + 1, n) or tuple(hit_t.shape) != (params.max_depth + 1, n):
+        raise ValueError("hit records must be [max_depth + 1][traced rays]")
+    hit_tri = hit_tri.contiguous().to(torch.int32)
+    hit_t = hit_t.contiguous().to(torch.float64)
+    if region is not None:
+        region = region.contiguous().to(torch.uint8)
+        if tuple(region.shape) != (grid.ny, grid.nx):
+            raise ValueError("region must be [ny][nx]")
+    out = torch.empty(2 * scene.nm + 3, dtype=torch.float64, device=ctx.torch_device)
+    ctx._bind_stream()
+    p, t, r, g = params.c(), device_struct(tx), device_struct(rx_ant), grid_struct(grid)
+    check(lib.rt_coverage_grad(ctx.h, scene.h, ctypes.byref(p), ctypes.byref(t), ctypes.byref(r), ctypes.byref(g),
+                               _ptr(region), _ptr(hit_tri), _ptr(hit_t), _ptr(out)))
+    return out
+
+
 def paths_power_grad(ctx: Context, scene: Scene, params: TraceParams, tx, rxs, depth, faces, dL_dP):
     """sum_r dL_dP[r] dP_r/dtheta for theta = (eps_r, sigma) per material, tx xyz, yaw, pitch (float64 tensor)."""
     nrx = len(rxs)
