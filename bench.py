@@ -310,6 +310,28 @@ def extras(rt, ctx, scene, w, torch):
     torch.cuda.synchronize()
     res["grad_ms"] = round((time.perf_counter() - t0) * 1e3 / 10, 4)
     res["grad_paths"] = int((od["depth"][0] >= 0).sum())
+    # coverage-map gradient (materials, tx yaw and pitch) of the whole map at
+    # the workload's lattice: record the hits, then replay with field tangents
+    pg = rt.TraceParams(d.scene.freq_hz, w.max_depth, w.num_rays)
+    tri, tt = rt.trace_record(ctx, sd, pg, d.tx[0])
+    rt.coverage_grad(ctx, sd, pg, d.tx[0], w.grid, tri, tt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        tri, tt = rt.trace_record(ctx, sd, pg, d.tx[0])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(3):
+        og = rt.coverage_grad(ctx, sd, pg, d.tx[0], w.grid, tri, tt)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    segs = int((tri != -2).sum())
+    res["coverage_grad"] = {"workload": "urban coverage map, 1e7 rays, depth 3, 400x400 cells; d/d(eps_r, sigma) "
+                                        "of 2 materials, tx yaw, pitch",
+                            "record_ms": round((t1 - t0) * 1e3 / 3, 3), "replay_ms": round((t2 - t1) * 1e3 / 3, 3),
+                            "segments": segs, "M_segments_per_s": round(segs / ((t2 - t1) / 3) / 1e6, 1),
+                            "region_gain": float(og[0])}
+    log("bench: coverage grad %s" % res["coverage_grad"])
     # large procedural city: coverage map at full size
     c = sg.city_workload()
     t0 = time.perf_counter()
