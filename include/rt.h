@@ -246,6 +246,58 @@ rt_status rt_paths_power_grad(rt_ctx* ctx, rt_scene* scene, const rt_trace_param
                               const rt_device* rx, int32_t nrx, int32_t P, const int32_t* depth,
                               const int32_t* faces, const double* dL_dP, double* grad);
 
+/* Gradient of any real function L of the path coefficients: given for every
+ * path slot the complex adjoint g = dL/da in the sense dL = Re(g da)
+ * (coef_adj [nrx][P][2] (dev) float64), writes
+ *   grad [2*nm + 5] (dev) float64 = sum over slots of Re(g da/dtheta)
+ * for theta as in rt_paths_power_grad.  Only the coefficients a are
+ * differentiated: the delays are held fixed, which is exact for the materials
+ * (paths keep their geometry) but not for the transmitter position.  Other
+ * arguments and behaviour as rt_paths_power_grad. */
+rt_status rt_paths_coef_grad(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p, const rt_device* tx,
+                             const rt_device* rx, int32_t nrx, int32_t P, const int32_t* depth,
+                             const int32_t* faces, const double* coef_adj, double* grad);
+
+/* ---------------------------------------------------------------- channels */
+
+/* Channel frequency responses of paths (Sec. II-A: paths become channel
+ * impulse responses, optionally with synthetic arrays, i.e. one traced
+ * antenna per array with plane-wave phase shifts per element, and with
+ * Doppler from device velocities; Sec. III-A: frequency responses of an OFDM
+ * system).  Inputs as written by rt_compute_paths for ntx transmitters and
+ * nrx receivers: a [ntx][nrx][P][2], tau, aod, aoa, depth (dev).  For time
+ * step n < T (t = n / fs), receive element j, transmit element i and
+ * subcarrier k < K (frequency f_k = (k - floor(K/2)) spacing_hz from the
+ * carrier freq_hz):
+ *   H = sum over paths of a exp(j 2 pi (-(f_c + f_k) tau + (k_t . r_i + k_r . r_j) / lambda + f_D t)),
+ *   f_D = (v_tx . k_t + v_rx . k_r) / lambda,
+ * with k_t the unit vector of the angles of departure, k_r that of the angles
+ * of arrival (towards the arriving wave), r_i, r_j the element offsets from
+ * the array centres (global frame, m).  tx_el [nt_el][3], rx_el [nr_el][3],
+ * v_tx [ntx][3], v_rx [nrx][3] (m/s) are host arrays (nullable: a single
+ * element at the centre, devices at rest).
+ *   H [ntx][nrx][T][nr_el][nt_el][K][2] (dev) float32.
+ * RT_ERR_ARG for empty dimensions, fs <= 0 with T > 1, or non-finite
+ * offsets or velocities.  Enqueued after a synchronous upload of the small
+ * host arrays. */
+rt_status rt_paths_cfr(rt_ctx* ctx, int32_t ntx, int32_t nrx, int32_t P, const float* a, const float* tau,
+                       const float* aod, const float* aoa, const int32_t* depth, double freq_hz, int32_t K,
+                       double spacing_hz, int32_t nt_el, const double* tx_el, int32_t nr_el, const double* rx_el,
+                       const double* v_tx, const double* v_rx, int32_t T, double fs, float* H);
+
+/* Adjoint of rt_paths_cfr in the path coefficients: for an upstream
+ * gradient G of a real loss with respect to H (G [..] (dev) float32 in H's
+ * layout, dL = Re(conj(G) dH)), writes the coefficient adjoint
+ *   g [ntx][nrx][P][2] (dev) float64 = sum over the (tx, rx) entries of
+ *   conj(G) exp(j 2 pi phase), zero for empty slots,
+ * so that dL = Re(g da) (the input of rt_paths_coef_grad).  Arguments as
+ * rt_paths_cfr. */
+rt_status rt_paths_cfr_adjoint(rt_ctx* ctx, int32_t ntx, int32_t nrx, int32_t P, const float* a, const float* tau,
+                               const float* aod, const float* aoa, const int32_t* depth, double freq_hz, int32_t K,
+                               double spacing_hz, int32_t nt_el, const double* tx_el, int32_t nr_el,
+                               const double* rx_el, const double* v_tx, const double* v_rx, int32_t T, double fs,
+                               const float* G, double* g);
+
 /* Coverage-map gradient (Sec. III-B: gradient steps on a transmitter's
  * orientation; Sec. III-A: on radio materials).  For the coverage map of
  * rt_coverage_map with the same p, tx, rx_ant and grid, the path gain summed

@@ -26,5 +26,6 @@ Modules
   image     image-method paths (exhaustive and candidate-driven)
   grad      received-power loss and central finite differences
   covgrad   coverage-map region gain and its central finite differences
+  channel   channel frequency responses of paths (synthetic arrays, Doppler, OFDM)
   mlp       float64 Fourier-feature MLP with manual backward (surrogate)
 """

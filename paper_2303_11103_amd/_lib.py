@@ -85,6 +85,12 @@ SIGNATURES = {
     "rt_paths_power": [P, P, P, I64, I32, P],
     "rt_paths_power_grad": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), P, I32, I32, P, P,
                             P, P],
+    "rt_paths_coef_grad": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), P, I32, I32, P, P,
+                           P, P],
+    "rt_paths_cfr": [P, I32, I32, I32, P, P, P, P, P, ctypes.c_double, I32, ctypes.c_double, I32, P, I32, P, P, P,
+                     I32, ctypes.c_double, P],
+    "rt_paths_cfr_adjoint": [P, I32, I32, I32, P, P, P, P, P, ctypes.c_double, I32, ctypes.c_double, I32, P, I32, P,
+                             P, P, I32, ctypes.c_double, P, P],
     "rt_coverage_grad": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), ctypes.POINTER(rt_device),
                          ctypes.POINTER(rt_grid), P, P, P, P],
     "rt_mlp_param_count": [ctypes.POINTER(I64)],

@@ -76,3 +76,34 @@ def coverage_region_gain(theta, ctx, scene, params, tx, grid, region=None, rx_an
     """Differentiable summed path gain (float64 scalar tensor) of the region
     cells (uint8 mask [ny][nx], None: every cell) as a function of theta."""
     return CoverageRegionGain.apply(theta, ctx, scene, params, tx, grid, region, rx_ant)
+
+
+class ChannelFrequencyResponse(torch.autograd.Function):
+    """Channel frequency responses H (complex64 [nrx, T, nr_el, nt_el, K]) of
+    one transmitter's paths as a function of the materials theta = (eps_r,
+    sigma) per material (float64, 2*nm); Sec. III-A learns materials from such
+    responses.  Backward: the adjoint of the response map gives every path's
+    coefficient adjoint (rt_paths_cfr_adjoint), and the coefficient gradient
+    kernel turns it into d/dtheta (rt_paths_coef_grad); the paths' geometry and
+    delays do not depend on the materials."""
+
+    @staticmethod
+    def forward(fctx, theta, ctx, scene, params, tx, rxs, cfr_kw):
+        nm = scene.nm
+        scene.set_materials(theta.detach().to("cpu", torch.float64).numpy().reshape(nm, 2))
+        paths = rt.compute_paths(ctx, scene, params, [tx], rxs)
+        H = rt.paths_cfr(ctx, paths, params.freq_hz, **cfr_kw)
+        fctx.rt = (ctx, scene, params, tx, rxs, cfr_kw, paths)
+        return H[0]
+
+    @staticmethod
+    def backward(fctx, G):
+        ctx, scene, params, tx, rxs, cfr_kw, paths = fctx.rt
+        g = rt.paths_cfr_adjoint(ctx, paths, G[None], params.freq_hz, **cfr_kw)
+        grad = rt.paths_coef_grad(ctx, scene, params, tx, rxs, paths["depth"][0], paths["faces"][0], g[0])
+        return grad[:2 * scene.nm], None, None, None, None, None, None
+
+
+def channel_frequency_response(theta, ctx, scene, params, tx, rxs, **cfr_kw):
+    """Differentiable H of one transmitter (see rt.paths_cfr for cfr_kw)."""
+    return ChannelFrequencyResponse.apply(theta, ctx, scene, params, tx, rxs, cfr_kw)

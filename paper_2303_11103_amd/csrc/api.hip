@@ -69,6 +69,7 @@ struct rt_ctx {
     DevBuf rx;         // double [nrx][3]
     DevBuf rx_ant;     // Antenna [nrx]
     DevBuf paths;      // unsorted path records
+    DevBuf chan;       // channel responses: element offsets and velocities
     int64_t last_candidates = 0;
     // launch timing of the shoot-and-bounce kernels
     bool profiling = false;
@@ -723,10 +724,12 @@ rt_status rt_last_candidate_count(rt_ctx* c, int64_t* count) {
     return RT_OK;
 }
 
-rt_status rt_paths_power_grad(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx,
-                              const rt_device* rx, int32_t nrx, int32_t P, const int32_t* depth,
-                              const int32_t* faces, const double* dL_dP, double* grad) {
-    if (!c || !s || !rx || !depth || !faces || !dL_dP || !grad) return fail(RT_ERR_ARG, "NULL argument");
+// Gradient of received powers (dL_dP) or of any function of the path
+// coefficients given their complex adjoints (coef_adj); exactly one is set.
+static rt_status paths_grad_impl(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx,
+                                 const rt_device* rx, int32_t nrx, int32_t P, const int32_t* depth,
+                                 const int32_t* faces, const double* dL_dP, const double* coef_adj, double* grad) {
+    if (!c || !s || !rx || !depth || !faces || !(dL_dP || coef_adj) || !grad) return fail(RT_ERR_ARG, "NULL argument");
     rt_status st = check_params(p);
     if (st != RT_OK) return st;
     if ((st = check_device(tx, "tx", s->host.max_abs)) != RT_OK) return st;
@@ -765,10 +768,18 @@ rt_status rt_paths_power_grad(rt_ctx* c, rt_scene* s, const rt_trace_params* p, 
     g.depth = depth;
     g.faces = faces;
     g.dL_dP = dL_dP;
+    g.coef_adj = coef_adj;
     g.grad = grad;
     g.nm = nm;
     RT_HIP(rt::launch_power_grad(g, make_mats(s, p->freq_hz), c->stream));
     return RT_OK;
+}
+
+rt_status rt_paths_power_grad(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx,
+                              const rt_device* rx, int32_t nrx, int32_t P, const int32_t* depth,
+                              const int32_t* faces, const double* dL_dP, double* grad) {
+    if (!dL_dP) return fail(RT_ERR_ARG, "NULL argument");
+    return paths_grad_impl(c, s, p, tx, rx, nrx, P, depth, faces, dL_dP, nullptr, grad);
 }
 
 rt_status rt_coverage_grad(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx,
@@ -817,6 +828,105 @@ rt_status rt_coverage_grad(rt_ctx* c, rt_scene* s, const rt_trace_params* p, con
     a.out = out;
     RT_HIP(rt::launch_coverage_grad(a, make_mats(s, p->freq_hz), grid_for(c), c->stream));
     return RT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Validates the channel-response arguments and stages the small host arrays
+// (element offsets, velocities) in the context's device buffer.
+rt_status cfr_setup(rt_ctx* c, int32_t ntx, int32_t nrx, int32_t P, const float* a, const float* tau,
+                    const float* aod, const float* aoa, const int32_t* depth, double freq_hz, int32_t K,
+                    double spacing_hz, int32_t nt_el, const double* tx_el, int32_t nr_el, const double* rx_el,
+                    const double* v_tx, const double* v_rx, int32_t T, double fs, rt::CfrArgs& cf) {
+    if (!c || !a || !tau || !aod || !aoa || !depth) return fail(RT_ERR_ARG, "NULL argument");
+    if (ntx < 1 || nrx < 1 || P < 1) return fail(RT_ERR_ARG, "ntx, nrx and P must be >= 1");
+    if (!(freq_hz > 0) || !std::isfinite(freq_hz)) return fail(RT_ERR_ARG, "frequency must be positive");
+    if (K < 1 || !(spacing_hz >= 0) || !std::isfinite(spacing_hz))
+        return fail(RT_ERR_ARG, "need K >= 1 subcarriers and a finite spacing >= 0");
+    if (nt_el < 1 || nr_el < 1 || (nt_el > 1 && !tx_el) || (nr_el > 1 && !rx_el))
+        return fail(RT_ERR_ARG, "arrays need >= 1 element and offsets for more than one");
+    if (T < 1 || (T > 1 && !(fs > 0 && std::isfinite(fs))))
+        return fail(RT_ERR_ARG, "need T >= 1 time steps and a positive sampling frequency for T > 1");
+    std::vector<double> h;
+    auto put = [&](const double* src, int64_t n) {
+        for (int64_t i = 0; i < n; ++i) {
+            const double v = src ? src[i] : 0.0;
+            h.push_back(v);
+        }
+    };
+    put(tx_el, 3 * (int64_t)nt_el);
+    put(rx_el, 3 * (int64_t)nr_el);
+    put(v_tx, 3 * (int64_t)ntx);
+    put(v_rx, 3 * (int64_t)nrx);
+    for (double v : h)
+        if (!std::isfinite(v)) return fail(RT_ERR_ARG, "element offsets and velocities must be finite");
+    RT_HIP(hipSetDevice(c->device));
+    RT_HIP(ensure(c->chan, h.size() * sizeof(double)));
+    RT_HIP(hipMemcpyAsync(c->chan.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    RT_HIP(hipStreamSynchronize(c->stream));  // the staging vector goes out of scope
+    const double* d = (const double*)c->chan.p;
+    cf = rt::CfrArgs{};
+    cf.npairs = (int64_t)ntx * nrx;
+    cf.nrx = nrx;
+    cf.P = P;
+    cf.a = a;
+    cf.tau = tau;
+    cf.aod = aod;
+    cf.aoa = aoa;
+    cf.depth = depth;
+    cf.freq = freq_hz;
+    cf.lambda = kC0 / freq_hz;
+    cf.spacing = spacing_hz;
+    cf.fs = T > 1 ? fs : 1.0;
+    cf.K = K;
+    cf.T = T;
+    cf.nt_el = nt_el;
+    cf.nr_el = nr_el;
+    cf.tx_el = d;
+    cf.rx_el = d + 3 * nt_el;
+    cf.v_tx = d + 3 * (nt_el + nr_el);
+    cf.v_rx = d + 3 * (nt_el + nr_el + ntx);
+    cf.total = cf.npairs * T * nr_el * nt_el * K;
+    return RT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+rt_status rt_paths_cfr(rt_ctx* c, int32_t ntx, int32_t nrx, int32_t P, const float* a, const float* tau,
+                       const float* aod, const float* aoa, const int32_t* depth, double freq_hz, int32_t K,
+                       double spacing_hz, int32_t nt_el, const double* tx_el, int32_t nr_el, const double* rx_el,
+                       const double* v_tx, const double* v_rx, int32_t T, double fs, float* H) {
+    if (!H) return fail(RT_ERR_ARG, "NULL argument");
+    rt::CfrArgs cf;
+    rt_status st = cfr_setup(c, ntx, nrx, P, a, tau, aod, aoa, depth, freq_hz, K, spacing_hz, nt_el, tx_el, nr_el,
+                             rx_el, v_tx, v_rx, T, fs, cf);
+    if (st != RT_OK) return st;
+    cf.H = H;
+    RT_HIP(rt::launch_cfr(cf, c->stream));
+    return RT_OK;
+}
+
+rt_status rt_paths_cfr_adjoint(rt_ctx* c, int32_t ntx, int32_t nrx, int32_t P, const float* a, const float* tau,
+                               const float* aod, const float* aoa, const int32_t* depth, double freq_hz, int32_t K,
+                               double spacing_hz, int32_t nt_el, const double* tx_el, int32_t nr_el,
+                               const double* rx_el, const double* v_tx, const double* v_rx, int32_t T, double fs,
+                               const float* G, double* g) {
+    if (!G || !g) return fail(RT_ERR_ARG, "NULL argument");
+    rt::CfrArgs cf;
+    rt_status st = cfr_setup(c, ntx, nrx, P, a, tau, aod, aoa, depth, freq_hz, K, spacing_hz, nt_el, tx_el, nr_el,
+                             rx_el, v_tx, v_rx, T, fs, cf);
+    if (st != RT_OK) return st;
+    RT_HIP(rt::launch_cfr_adjoint(cf, G, g, c->stream));
+    return RT_OK;
+}
+
+rt_status rt_paths_coef_grad(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx,
+                             const rt_device* rx, int32_t nrx, int32_t P, const int32_t* depth, const int32_t* faces,
+                             const double* coef_adj, double* grad) {
+    if (!coef_adj) return fail(RT_ERR_ARG, "NULL argument");
+    return paths_grad_impl(c, s, p, tx, rx, nrx, P, depth, faces, nullptr, coef_adj, grad);
 }
 
 }  // extern "C"

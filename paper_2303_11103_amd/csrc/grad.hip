@@ -220,8 +220,11 @@ __global__ void power_grad_kernel(GradArgs g, MatTable mats) {
     const int r = (int)(item / g.P);
     const int K = g.depth[item];
     if (K < 0 || K > g.fd || K > kMaxK) return;  // empty slot (or not a path of this depth range)
-    const double w_up = g.dL_dP[r];
-    if (w_up == 0.0) return;
+    // adjoint of the path coefficient: the contribution of the path is
+    // Re(gc * da/dtheta), gc given (coef_adj) or 2 w conj(a) for the power
+    // |a|^2 weighted by the upstream w = dL/dP_r
+    const double w_up = g.coef_adj ? 0.0 : g.dL_dP[r];
+    if (g.coef_adj ? (g.coef_adj[2 * item] == 0.0 && g.coef_adj[2 * item + 1] == 0.0) : w_up == 0.0) return;
     int fc[kMaxK];
     for (int i = 0; i < K; ++i) {
         fc[i] = g.faces[item * g.fd + i];
@@ -319,14 +322,12 @@ __global__ void power_grad_kernel(GradArgs g, MatTable mats) {
     const D amp = dc(g.lambda / (4.0 * kPi)) / L;
     const C pr = cdot(E, Fr);
     const C a{pr.re * amp, pr.im * amp};
+    const double gre = g.coef_adj ? g.coef_adj[2 * item] : 2.0 * w_up * a.re.v;
+    const double gim = g.coef_adj ? g.coef_adj[2 * item + 1] : -2.0 * w_up * a.im.v;
     double* out = g.grad;
     const int base = 2 * g.nm;
-    for (int i = 0; i < NT; ++i) {
-        const double dP = 2.0 * (a.re.v * a.re.d[i] + a.im.v * a.im.d[i]);
-        atomicAdd(out + base + i, w_up * dP);
-    }
+    for (int i = 0; i < NT; ++i) atomicAdd(out + base + i, gre * a.re.d[i] - gim * a.im.d[i]);
     // material sweep
-    const cd av{a.re.v, a.im.v};
     cd gv[3] = {cd{amp.v * Fr.x.v, 0.0}, cd{amp.v * Fr.y.v, 0.0}, cd{amp.v * Fr.z.v, 0.0}};
     const double w = 2.0 * kPi * g.freq;
     for (int k = K; k >= 1; --k) {
@@ -334,13 +335,13 @@ __global__ void power_grad_kernel(GradArgs g, MatTable mats) {
         const cd gp = cdotv(gv, ep_v[i]);
         const cd gl = cdotv(gv, elr_v[i]);
         const cd da = cadd(cmul(cmul(gp, aperp[i]), drp[i]), cmul(cmul(gl, apar[i]), drl[i]));
-        // dP/deps_r = 2 Re(conj(a) da); dP/dsigma = 2 Re(conj(a) da (-j / (eps0 w)))
-        const double re_cd = av.re * da.re + av.im * da.im;   // Re(conj(a) da)
-        const double im_cd = av.re * da.im - av.im * da.re;   // Im(conj(a) da)
+        // d/deps_r: Re(gc da); d/dsigma: Re(gc da (-j / (eps0 w))) = Im(gc da) / (eps0 w)
+        const double re_gd = gre * da.re - gim * da.im;
+        const double im_gd = gre * da.im + gim * da.re;
         const double dsig = 1.0 / (kEps0 * w);
         if (drp[i].re != 0.0 || drp[i].im != 0.0 || drl[i].re != 0.0 || drl[i].im != 0.0) {
-            atomicAdd(out + 2 * mat_k[i], w_up * 2.0 * re_cd);
-            atomicAdd(out + 2 * mat_k[i] + 1, w_up * 2.0 * im_cd * dsig);
+            atomicAdd(out + 2 * mat_k[i], re_gd);
+            atomicAdd(out + 2 * mat_k[i] + 1, im_gd * dsig);
         }
         // g <- R_k^T g
         const cd p1 = cmul(rp_v[i], gp), p2 = cmul(rl_v[i], gl);

@@ -155,11 +155,33 @@ struct GradArgs {
     int32_t nrx, P, fd;
     const int32_t* depth;   // [nrx][P]
     const int32_t* faces;   // [nrx][P][fd]
-    const double* dL_dP;    // [nrx]
+    const double* dL_dP;    // [nrx] (used when coef_adj is null)
+    const double* coef_adj; // [nrx][P][2] complex adjoint g of each path's coefficient (nullable)
     double* grad;           // [2 nm + 5]
     int32_t nm;
 };
 hipError_t launch_power_grad(const GradArgs& a, const MatTable& mats, hipStream_t s);
+
+// Channel frequency responses of paths (synthetic arrays, Doppler, OFDM).
+struct CfrArgs {
+    int64_t npairs;           // ntx * nrx
+    int32_t nrx, P;
+    const float* a;           // [npairs][P][2]
+    const float* tau;         // [npairs][P]
+    const float* aod;         // [npairs][P][2] (theta, phi)
+    const float* aoa;
+    const int32_t* depth;     // [npairs][P], < 0 for an empty slot
+    double freq, lambda, spacing, fs;
+    int32_t K, T, nt_el, nr_el;
+    const double* tx_el;      // [nt_el][3] element offsets [m] (dev)
+    const double* rx_el;      // [nr_el][3]
+    const double* v_tx;       // [ntx][3] velocities [m/s] (dev)
+    const double* v_rx;       // [nrx][3]
+    float* H;                 // [npairs][T][nr_el][nt_el][K][2]
+    int64_t total;            // entries of H
+};
+hipError_t launch_cfr(const CfrArgs& c, hipStream_t s);
+hipError_t launch_cfr_adjoint(const CfrArgs& c, const float* G, double* g, hipStream_t s);
 
 // Coverage-map gradient: replay of recorded rays with field tangents.
 constexpr int kCovMaxMat = 4;                 // materials with tangents

@@ -237,6 +237,80 @@ def coverage_grad(ctx: Context, scene: Scene, params: TraceParams, tx, grid, hit
     return out
 
 
+def _host_f64(x, rows):
+    """None or a contiguous float64 ctypes array of shape [rows][3]."""
+    if x is None:
+        return None, 0
+    arr = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1, 3))
+    if rows is not None and arr.shape[0] != rows:
+        raise ValueError("expected %d rows of 3 values" % rows)
+    return arr, arr.shape[0]
+
+
+def _cfr_args(paths, freq_hz, num_subcarriers, spacing, tx_el, rx_el, v_tx, v_rx, num_time_steps, fs):
+    a = paths["a"].contiguous()
+    ntx, nrx, P = a.shape[0], a.shape[1], a.shape[2]
+    te, nte = _host_f64(tx_el, None)
+    re, nre = _host_f64(rx_el, None)
+    vt, _ = _host_f64(v_tx, ntx)
+    vr, _ = _host_f64(v_rx, nrx)
+    keep = (a, paths["tau"].contiguous(), paths["aod"].contiguous(), paths["aoa"].contiguous(),
+            paths["depth"].contiguous().to(torch.int32), te, re, vt, vr)
+    hp = lambda x: None if x is None else x.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    args = [ntx, nrx, P, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]), _ptr(keep[3]), _ptr(keep[4]), float(freq_hz),
+            int(num_subcarriers), float(spacing), max(nte, 1), hp(te), max(nre, 1), hp(re), hp(vt), hp(vr),
+            int(num_time_steps), float(fs or 0.0)]
+    shape = (ntx, nrx, int(num_time_steps), max(nre, 1), max(nte, 1), int(num_subcarriers))
+    return args, shape, keep
+
+
+def paths_cfr(ctx: Context, paths, freq_hz, num_subcarriers=128, spacing=30e3, tx_el=None, rx_el=None, v_tx=None,
+              v_rx=None, num_time_steps=1, fs=None):
+    """Channel frequency responses of the paths of compute_paths: complex64
+    tensor [ntx, nrx, T, nr_el, nt_el, K] (synthetic arrays from element
+    offsets tx_el / rx_el [n][3] in metres, Doppler from velocities v_tx
+    [ntx][3] / v_rx [nrx][3] in m/s, T time steps at fs Hz)."""
+    args, shape, keep = _cfr_args(paths, freq_hz, num_subcarriers, spacing, tx_el, rx_el, v_tx, v_rx,
+                                  num_time_steps, fs)
+    H = torch.empty(shape + (2,), dtype=torch.float32, device=ctx.torch_device)
+    ctx._bind_stream()
+    check(lib.rt_paths_cfr(ctx.h, *args, _ptr(H)))
+    return torch.view_as_complex(H)
+
+
+def paths_cfr_adjoint(ctx: Context, paths, G, freq_hz, num_subcarriers=128, spacing=30e3, tx_el=None, rx_el=None,
+                      v_tx=None, v_rx=None, num_time_steps=1, fs=None):
+    """Coefficient adjoint g [ntx, nrx, P, 2] (float64) of an upstream
+    gradient G (complex, H's shape; dL = Re(conj(G) dH))."""
+    args, shape, keep = _cfr_args(paths, freq_hz, num_subcarriers, spacing, tx_el, rx_el, v_tx, v_rx,
+                                  num_time_steps, fs)
+    if tuple(G.shape) != shape:
+        raise ValueError("G must have the shape of the responses %s" % (shape,))
+    Gf = torch.view_as_real(G.to(torch.complex64).contiguous()).contiguous()
+    a = paths["a"]
+    g = torch.empty((a.shape[0], a.shape[1], a.shape[2], 2), dtype=torch.float64, device=ctx.torch_device)
+    ctx._bind_stream()
+    check(lib.rt_paths_cfr_adjoint(ctx.h, *args, _ptr(Gf), _ptr(g)))
+    return g
+
+
+def paths_coef_grad(ctx: Context, scene: Scene, params: TraceParams, tx, rxs, depth, faces, coef_adj):
+    """sum over paths of Re(g da/dtheta) for theta = (eps_r, sigma) per
+    material, tx xyz, yaw, pitch (delays held fixed); coef_adj [nrx, P, 2]."""
+    nrx = len(rxs)
+    depth = depth.contiguous().to(torch.int32)
+    faces = faces.contiguous().to(torch.int32)
+    coef_adj = coef_adj.contiguous().to(torch.float64)
+    P = depth.shape[-1]
+    grad = torch.empty(2 * scene.nm + 5, dtype=torch.float64, device=ctx.torch_device)
+    rx_arr = (L.rt_device * nrx)(*[device_struct(r) for r in rxs])
+    ctx._bind_stream()
+    p, t = params.c(), device_struct(tx)
+    check(lib.rt_paths_coef_grad(ctx.h, scene.h, ctypes.byref(p), ctypes.byref(t), rx_arr, nrx, P, _ptr(depth),
+                                 _ptr(faces), _ptr(coef_adj), _ptr(grad)))
+    return grad
+
+
 def paths_power_grad(ctx: Context, scene: Scene, params: TraceParams, tx, rxs, depth, faces, dL_dP):
     """sum_r dL_dP[r] dP_r/dtheta for theta = (eps_r, sigma) per material, tx xyz, yaw, pitch (float64 tensor)."""
     nrx = len(rxs)

@@ -1,0 +1,182 @@
+"""Channel frequency responses of paths (synthetic arrays, Doppler, OFDM
+subcarriers) against the FP64 oracle on the same paths; the adjoint of the
+response map; the coefficient gradient; and the paper's learning of radio
+materials from frequency responses (Sec. III-A: 128 subcarriers 30 kHz apart,
+materials initialised to sigma = 0.1 S/m and eps_r = 3.0) in synthetic form."""
+import numpy as np
+import pytest
+import torch
+
+import scenegen as sg
+from oracle import channel, geom, image
+from oracle.consts import C0
+
+from gpu_common import ctx, lib, params, requires_gpu, scene
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+KW = dict(num_subcarriers=128, spacing=30e3)
+
+
+def _pairs(o):
+    a = o["a"].cpu().numpy()
+    tau = o["tau"].cpu().numpy()
+    aod = o["aod"].cpu().numpy()
+    aoa = o["aoa"].cpu().numpy()
+    depth = o["depth"].cpu().numpy()
+    out = {}
+    for t in range(a.shape[0]):
+        for r in range(a.shape[1]):
+            out[t, r] = [(complex(a[t, r, p, 0], a[t, r, p, 1]), float(tau[t, r, p]), tuple(aod[t, r, p].astype(float)),
+                          tuple(aoa[t, r, p].astype(float))) for p in range(a.shape[2]) if depth[t, r, p] >= 0]
+    return out
+
+
+def _urban_paths(m, nrx=16):
+    w = sg.urban_workload(num_rays=200_000)
+    p = params(w, max_paths_per_rx=64)
+    sc = scene(w.scene)
+    return w, p, sc, m.compute_paths(ctx(), sc, p, w.tx, w.rx[:nrx])
+
+
+def test_cfr_with_arrays_and_doppler_matches_oracle():
+    m = lib()
+    w, p, sc, o = _urban_paths(m)
+    lam = C0 / w.scene.freq_hz
+    tx_el = [[0.0, y, z] for y in (-lam / 4, lam / 4) for z in (-lam / 4, lam / 4)]
+    rx_el = [[-lam / 4, 0.0, 0.0], [lam / 4, 0.0, 0.0]]
+    rng = np.random.default_rng(7)
+    v_tx = [[3.0, 0.0, 0.0]]
+    v_rx = rng.uniform(-20.0, 20.0, (16, 3))
+    H = m.paths_cfr(ctx(), o, w.scene.freq_hz, tx_el=tx_el, rx_el=rx_el, v_tx=v_tx, v_rx=v_rx, num_time_steps=3,
+                    fs=1e6, **KW).cpu().numpy()
+    assert H.shape == (1, 16, 3, 2, 4, 128)
+    pairs = _pairs(o)
+    n_paths = 0
+    for r in range(16):
+        ref = channel.cfr(pairs[0, r], w.scene.freq_hz, 128, 30e3, tx_el, rx_el, v_tx[0], v_rx[r], 3, 1e6)
+        scale = sum(abs(x[0]) for x in pairs[0, r]) + 1e-30
+        assert np.max(np.abs(H[0, r] - ref)) <= 1e-5 * scale, r
+        n_paths += len(pairs[0, r])
+    assert n_paths > 10
+
+
+def test_cfr_adjoint_satisfies_the_dot_product_identity():
+    m = lib()
+    w, p, sc, o = _urban_paths(m)
+    kw = dict(KW, num_time_steps=2, fs=1e6, rx_el=[[0.0, 0.0, 0.0], [0.04, 0.0, 0.0]], v_rx=np.ones((16, 3)))
+    H = m.paths_cfr(ctx(), o, w.scene.freq_hz, **kw)
+    g0 = torch.Generator().manual_seed(3)
+    G = torch.complex(torch.randn(H.shape, generator=g0), torch.randn(H.shape, generator=g0)).to(H.device)
+    g = m.paths_cfr_adjoint(ctx(), o, G, w.scene.freq_hz, **kw)
+    a = torch.view_as_complex(o["a"].contiguous()).to(torch.complex128)
+    lhs = torch.real(torch.sum(torch.conj(G.to(torch.complex128)) * H.to(torch.complex128))).item()
+    rhs = torch.real(torch.sum(torch.view_as_complex(g.contiguous()) * a)).item()
+    assert abs(lhs - rhs) <= 1e-5 * (abs(lhs) + 1e-30), (lhs, rhs)
+
+
+def test_coefficient_gradient_with_the_power_adjoint_equals_the_power_gradient():
+    m = lib()
+    w = sg.diff_workload(num_rays=100_000)
+    rxs = w.rx[:40]
+    p = params(w, max_paths_per_rx=64)
+    sc = scene(w.scene)
+    o = m.compute_paths(ctx(), sc, p, w.tx, rxs)
+    dL = torch.linspace(0.5, 1.5, len(rxs), dtype=torch.float64, device=ctx().torch_device)
+    g_pow = m.paths_power_grad(ctx(), sc, p, w.tx[0], rxs, o["depth"][0], o["faces"][0], dL).cpu().numpy()
+    a = o["a"][0].to(torch.float64)
+    adj = torch.stack([2.0 * a[..., 0], -2.0 * a[..., 1]], -1) * dL[:, None, None]
+    g_coef = m.paths_coef_grad(ctx(), sc, p, w.tx[0], rxs, o["depth"][0], o["faces"][0], adj).cpu().numpy()
+    assert np.allclose(g_coef, g_pow, rtol=1e-5, atol=1e-6 * np.abs(g_pow).max())
+
+
+def _setup_learning(m, nrx):
+    w = sg.diff_workload(num_rays=200_000)
+    rxs = w.rx[:nrx]
+    p = params(w, max_paths_per_rx=64)
+    sc = scene(w.scene)
+    true = np.asarray(w.scene.materials, dtype=np.float64)
+    from paper_2303_11103_amd.autograd import channel_frequency_response
+    with torch.no_grad():
+        th = torch.tensor(true.reshape(-1), dtype=torch.float64, device=ctx().torch_device)
+        H_ref = channel_frequency_response(th, ctx(), sc, p, w.tx[0], rxs, **KW).to(torch.complex128)
+    return w, rxs, p, sc, true, H_ref, channel_frequency_response
+
+
+def test_cfr_material_gradient_matches_oracle_central_differences():
+    m = lib()
+    w, rxs, p, sc, true, H_ref, cfr_fn = _setup_learning(m, 32)
+    try:
+        theta0 = np.array([3.0, 0.1, 3.0, 0.1])
+        th = torch.tensor(theta0, dtype=torch.float64, device=ctx().torch_device, requires_grad=True)
+        H = cfr_fn(th, ctx(), sc, p, w.tx[0], rxs, **KW).to(torch.complex128)
+        L = torch.sum(torch.abs(H - H_ref) ** 2) / torch.sum(torch.abs(H_ref) ** 2)
+        L.backward()
+        g_gpu = th.grad.cpu().numpy()
+        # oracle: the same face sequences (paths do not depend on the materials), FP64 responses
+        o = m.compute_paths(ctx(), sc, p, w.tx, rxs)
+        depth, faces = o["depth"][0].cpu().numpy(), o["faces"][0].cpu().numpy()
+        seqs = {tuple(int(f) for f in faces[r, j, :depth[r, j]]) for r in range(len(rxs))
+                for j in range(depth.shape[1]) if depth[r, j] >= 0}
+        Href = H_ref.cpu().numpy()[:, 0, 0, 0, :]
+        # the responses are defined with the delays as compute_paths reports them
+        # (float32: 1e-3 rad of carrier phase at 1 us and 3.5 GHz), so the
+        # oracle uses those delays, matched by (rx, face sequence), with its own
+        # fp64 coefficients and angles
+        tau_g = o["tau"][0].cpu().numpy()
+        gpu_tau = {(r, tuple(int(f) for f in faces[r, j, :depth[r, j]])): float(tau_g[r, j])
+                   for r in range(len(rxs)) for j in range(depth.shape[1]) if depth[r, j] >= 0}
+
+        def loss(mats):
+            geo = geom.Geometry(w.scene)
+            geo.materials = mats.reshape(-1, 2).copy()
+            P = image.paths(geo, w.tx[0], rxs, seqs)
+            assert sum(len(x) for x in P) == len(gpu_tau)
+            Hs = np.stack([channel.cfr([(q.a, gpu_tau[r, tuple(q.faces)], q.aod, q.aoa) for q in P[r]],
+                                       w.scene.freq_hz, 128, 30e3)[0, 0, 0] for r in range(len(rxs))])
+            return np.sum(np.abs(Hs - Href) ** 2) / np.sum(np.abs(Href) ** 2)
+
+        g_fd = np.empty(4)
+        for k in range(4):
+            h = 1e-5 * max(abs(theta0[k]), 1.0)
+            tp, tm = theta0.copy(), theta0.copy()
+            tp[k] += h
+            tm[k] -= h
+            g_fd[k] = (loss(tp) - loss(tm)) / (2 * h)
+        print("gpu", g_gpu, "\noracle fd", g_fd, flush=True)
+        assert abs(loss(theta0) - float(L)) < 1e-4 * float(L)
+        assert np.max(np.abs(g_gpu - g_fd) / np.abs(g_fd)) < 1e-3
+    finally:
+        sc.set_materials(true)
+
+
+def test_learning_radio_materials_from_frequency_responses():
+    m = lib()
+    w, rxs, p, sc, true, H_ref, cfr_fn = _setup_learning(m, 64)
+    dev = ctx().torch_device
+    try:
+        # eps_r = 1 + exp(u), sigma = exp(v) keep every trial physical; start at (3.0, 0.1)
+        u = torch.tensor([np.log(2.0), np.log(0.1)] * 2, dtype=torch.float64, device=dev, requires_grad=True)
+        opt = torch.optim.LBFGS([u], lr=1.0, max_iter=60, history_size=10, line_search_fn="strong_wolfe",
+                                tolerance_grad=1e-14, tolerance_change=1e-16)
+        hist = []
+
+        def mats(x):
+            return torch.stack([1.0 + torch.exp(x[0]), torch.exp(x[1]), 1.0 + torch.exp(x[2]), torch.exp(x[3])])
+
+        def closure():
+            opt.zero_grad()
+            H = cfr_fn(mats(u), ctx(), sc, p, w.tx[0], rxs, **KW).to(torch.complex128)
+            L = torch.sum(torch.abs(H - H_ref) ** 2) / torch.sum(torch.abs(H_ref) ** 2)
+            L.backward()
+            hist.append(float(L))
+            return L
+
+        for _ in range(3):
+            opt.step(closure)
+        learned = mats(u.detach()).cpu().numpy().reshape(2, 2)
+        print("NMSE", hist[0], "->", min(hist), "learned", learned.tolist(), "true", true.tolist(), flush=True)
+        assert min(hist) < 1e-4 * hist[0]
+        assert np.all(np.abs(learned - true) / true < 1e-2)
+    finally:
+        sc.set_materials(true)
