@@ -332,6 +332,31 @@ def extras(rt, ctx, scene, w, torch):
                             "segments": segs, "M_segments_per_s": round(segs / ((t2 - t1) / 3) / 1e6, 1),
                             "region_gain": float(og[0])}
     log("bench: coverage grad %s" % res["coverage_grad"])
+    # channel frequency responses (128 subcarriers, 30 kHz) of the 256 receivers
+    # of the differentiation case, their adjoint and the material gradient
+    od = rt.compute_paths(ctx, sd, pd, d.tx, d.rx)
+    kw = dict(num_subcarriers=128, spacing=30e3)
+    H = rt.paths_cfr(ctx, od, pd.freq_hz, **kw)
+    G = torch.ones_like(H)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        H = rt.paths_cfr(ctx, od, pd.freq_hz, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(10):
+        g = rt.paths_cfr_adjoint(ctx, od, G, pd.freq_hz, **kw)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(10):
+        rt.paths_coef_grad(ctx, sd, pd, d.tx[0], d.rx, od["depth"][0], od["faces"][0], g[0])
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    res["cfr"] = {"workload": "256 rx of the differentiation case, %d paths, 128 subcarriers" %
+                              int((od["depth"] >= 0).sum()),
+                  "cfr_ms": round((t1 - t0) * 1e2, 4), "adjoint_ms": round((t2 - t1) * 1e2, 4),
+                  "coef_grad_ms": round((t3 - t2) * 1e2, 4)}
+    log("bench: cfr %s" % res["cfr"])
     # large procedural city: coverage map at full size
     c = sg.city_workload()
     t0 = time.perf_counter()
