@@ -59,11 +59,19 @@ typedef struct {
     float sigma;  /* conductivity [S/m], >= 0 or +INFINITY */
 } rt_material;
 
-/* Antenna patterns (Sec. II, Listing 2: preconfigured patterns such as the
- * 3GPP TR 38.901 element).  Polarisation is vertical (RT_POL_V). */
-#define RT_PATTERN_ISO      0  /* isotropic, C_theta = 1, C_phi = 0 */
+/* Antenna patterns and polarisations (Sec. II, Listing 2: preconfigured
+ * patterns such as the 3GPP TR 38.901 element and the dipole; single- and
+ * dual-polarised antennas, "VH" and "cross").  A single-port antenna radiates
+ * C_theta = g cos(zeta), C_phi = g sin(zeta) in its own frame, g the pattern's
+ * amplitude and zeta the polarisation angle; a dual-polarised antenna is two
+ * devices with orthogonal zeta (V and H, or +45 and -45 degrees). */
+#define RT_PATTERN_ISO      0  /* isotropic, g = 1 */
 #define RT_PATTERN_TR38901  1  /* TR 38.901 Table 7.3-1 element, 8 dBi, 65 deg beamwidths */
-#define RT_POL_V            0
+#define RT_PATTERN_DIPOLE   2  /* short dipole along the local z axis, g = sqrt(1.5) sin(theta) (1.76 dBi) */
+#define RT_POL_V            0  /* zeta = 0: along theta-hat */
+#define RT_POL_H            1  /* zeta = 90 degrees: along phi-hat */
+#define RT_POL_SLANT_P45    2  /* zeta = +45 degrees */
+#define RT_POL_SLANT_M45    3  /* zeta = -45 degrees */
 
 /* A transmitter or receiver (Sec. II-A: position and orientation given by
  * yaw, pitch, roll; orientation R = Rz(yaw) Ry(pitch) Rx(roll), positive
@@ -72,7 +80,7 @@ typedef struct {
     float pos[3];
     float yaw, pitch, roll;
     int32_t pattern;  /* RT_PATTERN_* */
-    int32_t pol;      /* RT_POL_V */
+    int32_t pol;      /* RT_POL_* */
 } rt_device;
 
 /* Tracing parameters. */

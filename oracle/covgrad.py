@@ -50,7 +50,7 @@ def perturbed(geo, tx, k, delta):
         g2.materials[k // 2, k % 2] += delta
     else:
         t2 = SimpleNamespace(pos=tuple(float(x) for x in tx.pos), yaw=float(tx.yaw), pitch=float(tx.pitch),
-                             roll=float(tx.roll), pattern=tx.pattern)
+                             roll=float(tx.roll), pattern=tx.pattern, pol=getattr(tx, "pol", 0))
         if k == 2 * nm:
             t2.yaw += delta
         else:

@@ -37,6 +37,10 @@ from .consts import EPS0
 
 PATTERN_ISO = 0
 PATTERN_TR38901 = 1
+PATTERN_DIPOLE = 2
+# single-port polarisation: C_theta = g cos(zeta), C_phi = g sin(zeta)
+# (the polarisation model 2 of 3GPP TR 38.901 Sec. 7.3.2)
+POL_ANGLE = {0: 0.0, 1: np.pi / 2, 2: np.pi / 4, 3: -np.pi / 4}   # V, H, +45 deg, -45 deg
 
 
 def eta(eps_r, sigma, freq_hz):
@@ -89,20 +93,31 @@ def phi_hat(ph):
     return np.stack([-np.sin(ph), np.cos(ph), np.zeros_like(ph)], axis=-1)
 
 
-def pattern(pid, th, ph):
-    """(C_theta, C_phi) for local angles (radians)."""
+def amplitude(pid, th, ph):
+    """Field amplitude g of a pattern for local angles (radians): isotropic 1;
+    TR 38.901 Table 7.3-1 element; short dipole along the local z axis,
+    sqrt(1.5) sin(theta) (directivity 1.5, i.e. 1.76 dBi)."""
     th = np.asarray(th, dtype=np.float64)
     ph = np.asarray(ph, dtype=np.float64)
     if pid == PATTERN_ISO:
-        return np.ones_like(th), np.zeros_like(th)
+        return np.ones_like(th)
     if pid == PATTERN_TR38901:
         tdeg = np.degrees(th)
         pdeg = np.degrees(ph)
         a_v = -np.minimum(12.0 * ((tdeg - 90.0) / 65.0) ** 2, 30.0)
         a_h = -np.minimum(12.0 * (pdeg / 65.0) ** 2, 30.0)
         a = -np.minimum(-(a_v + a_h), 30.0)
-        return 10.0 ** ((8.0 + a) / 20.0), np.zeros_like(th)
+        return 10.0 ** ((8.0 + a) / 20.0)
+    if pid == PATTERN_DIPOLE:
+        return np.sqrt(1.5) * np.sin(th)
     raise ValueError("unknown pattern %r" % (pid,))
+
+
+def pattern(pid, th, ph, pol=0):
+    """(C_theta, C_phi) for local angles (radians) and a polarisation code."""
+    g = amplitude(pid, th, ph)
+    zeta = POL_ANGLE[int(pol)]
+    return g * np.cos(zeta), g * np.sin(zeta)
 
 
 def antenna_field(dev, d):
@@ -111,7 +126,7 @@ def antenna_field(dev, d):
     R = rot_matrix(dev.yaw, dev.pitch, dev.roll)
     dl = np.asarray(d, dtype=np.float64) @ R  # = (R^T d) per row
     th, ph = theta_phi(dl)
-    ct, cp = pattern(dev.pattern, th, ph)
+    ct, cp = pattern(dev.pattern, th, ph, getattr(dev, "pol", 0))
     f_local = ct[..., None] * theta_hat(th, ph) + cp[..., None] * phi_hat(ph)
     return f_local @ R.T
 

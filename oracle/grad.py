@@ -90,7 +90,7 @@ def _perturbed(geo, tx, k, delta):
     else:
         j = k - 2 * nm
         t2 = SimpleNamespace(pos=tuple(float(x) for x in tx.pos), yaw=float(tx.yaw), pitch=float(tx.pitch),
-                             roll=float(tx.roll), pattern=tx.pattern)
+                             roll=float(tx.roll), pattern=tx.pattern, pol=getattr(tx, "pol", 0))
         if j < 3:
             pos = list(t2.pos)
             pos[j] += delta

@@ -26,7 +26,8 @@ class ReceivedPower(torch.autograd.Function):
         nm = scene.nm
         scene.set_materials(th[:2 * nm].reshape(nm, 2))
         dev = SimpleNamespace(pos=tuple(float(x) for x in th[2 * nm:2 * nm + 3]), yaw=float(th[2 * nm + 3]),
-                              pitch=float(th[2 * nm + 4]), roll=float(tx.roll), pattern=int(tx.pattern))
+                              pitch=float(th[2 * nm + 4]), roll=float(tx.roll), pattern=int(tx.pattern),
+                              pol=int(getattr(tx, "pol", 0)))
         paths = rt.compute_paths(ctx, scene, params, [dev], rxs)
         power = rt.paths_power(ctx, paths)[0]
         fctx.save_for_backward(paths["depth"][0].clone(), paths["faces"][0].clone())
@@ -60,7 +61,8 @@ class CoverageRegionGain(torch.autograd.Function):
         nm = scene.nm
         scene.set_materials(th[:2 * nm].reshape(nm, 2))
         dev = SimpleNamespace(pos=tuple(float(x) for x in tx.pos), yaw=float(th[2 * nm]), pitch=float(th[2 * nm + 1]),
-                              roll=float(tx.roll), pattern=int(tx.pattern))
+                              roll=float(tx.roll), pattern=int(tx.pattern),
+                              pol=int(getattr(tx, "pol", 0)))
         hit_tri, hit_t = rt.trace_record(ctx, scene, params, dev)
         out = rt.coverage_grad(ctx, scene, params, dev, grid, hit_tri, hit_t, region=region, rx_ant=rx_ant)
         fctx.save_for_backward(out[1:].clone())

@@ -98,9 +98,10 @@ rt_status check_device(const rt_device* d, const char* what, double max_abs) {
     if (!d) return fail(RT_ERR_ARG, std::string(what) + " is NULL");
     if (!finite3(d->pos) || !std::isfinite(d->yaw) || !std::isfinite(d->pitch) || !std::isfinite(d->roll))
         return fail(RT_ERR_ARG, std::string(what) + " has a non-finite position or orientation");
-    if (d->pattern != RT_PATTERN_ISO && d->pattern != RT_PATTERN_TR38901)
+    if (d->pattern != RT_PATTERN_ISO && d->pattern != RT_PATTERN_TR38901 && d->pattern != RT_PATTERN_DIPOLE)
         return fail(RT_ERR_ARG, std::string(what) + " has an unknown antenna pattern");
-    if (d->pol != RT_POL_V) return fail(RT_ERR_ARG, std::string(what) + " has an unsupported polarisation");
+    if (d->pol < RT_POL_V || d->pol > RT_POL_SLANT_M45)
+        return fail(RT_ERR_ARG, std::string(what) + " has an unknown polarisation");
     if (max_abs > 0)
         for (int i = 0; i < 3; ++i)
             if (std::fabs(d->pos[i]) > 4.0 * max_abs)
@@ -143,6 +144,7 @@ rt::Antenna make_antenna(const rt_device* d) {
     rot(d->yaw, d->pitch, d->roll, a.Rd);
     for (int i = 0; i < 9; ++i) a.R[i] = (float)a.Rd[i];
     a.pattern = d->pattern;
+    a.pol = d->pol;
     return a;
 }
 
@@ -760,6 +762,7 @@ static rt_status paths_grad_impl(rt_ctx* c, rt_scene* s, const rt_trace_params* 
     g.pitch = tx->pitch;
     g.roll = tx->roll;
     g.tx_pattern = tx->pattern;
+    g.tx_pol = tx->pol;
     g.rx = (const double*)c->rx.p;
     g.rx_ant = (const rt::Antenna*)c->rx_ant.p;
     g.nrx = nrx;
@@ -812,6 +815,7 @@ rt_status rt_coverage_grad(rt_ctx* c, rt_scene* s, const rt_trace_params* p, con
     a.pitch = tx->pitch;
     a.roll = tx->roll;
     a.tx_pattern = tx->pattern;
+    a.tx_pol = tx->pol;
     a.gnx = g->nx;
     a.gny = g->ny;
     a.rx_ant = make_antenna(rx_ant);

@@ -27,6 +27,7 @@ namespace rt {
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kPatIso = 0;
 constexpr int kPatTR38901 = 1;
+constexpr int kPatDipole = 2;
 constexpr int kMaxMaterials = 32;
 
 struct MatTable {
@@ -37,7 +38,7 @@ struct MatTable {
 struct Antenna {
     float R[9];
     int32_t pattern;
-    int32_t pad;
+    int32_t pol;       // polarisation code: 0 V, 1 H, 2 +45 degrees, 3 -45 degrees
     double Rd[9];
 };
 
@@ -111,6 +112,18 @@ __device__ __forceinline__ cd csqrt(cd z) {
 }
 
 // ---------------------------------------------------------------- antennas
+// (cos zeta, sin zeta) of a polarisation code, exact in the given precision.
+template <typename T>
+__device__ __forceinline__ void pol_angle(int pol, T& c, T& s) {
+    const T h = (T)0.70710678118654752440;
+    switch (pol) {
+        case 1: c = (T)0; s = (T)1; break;
+        case 2: c = h; s = h; break;
+        case 3: c = h; s = -h; break;
+        default: c = (T)1; s = (T)0; break;
+    }
+}
+
 __device__ __forceinline__ float tr38901_amp(float cos_t, float lx, float ly) {
     constexpr float kDeg = 57.29577951308232f;
     float th = acosf(fminf(fmaxf(cos_t, -1.0f), 1.0f)) * kDeg;
@@ -135,8 +148,13 @@ __device__ __forceinline__ f3 antenna_field(const Antenna& ant, f3 d) {
         cph = lx * ir;
         sph = ly * ir;
     }
-    float c = ant.pattern == kPatTR38901 ? tr38901_amp(lz, lx, ly) : 1.0f;
-    float tx = c * lz * cph, ty = c * lz * sph, tz = -c * rho;
+    float g = 1.0f;
+    if (ant.pattern == kPatTR38901) g = tr38901_amp(lz, lx, ly);
+    else if (ant.pattern == kPatDipole) g = 1.22474487f * rho;  // sqrt(1.5) sin(theta)
+    float zc, zs;
+    pol_angle(ant.pol, zc, zs);
+    const float ct = g * zc, cp = g * zs;  // theta-hat and phi-hat components
+    float tx = ct * lz * cph - cp * sph, ty = ct * lz * sph + cp * cph, tz = -ct * rho;
     return f3{R[0] * tx + R[1] * ty + R[2] * tz, R[3] * tx + R[4] * ty + R[5] * tz, R[6] * tx + R[7] * ty + R[8] * tz};
 }
 
@@ -161,8 +179,13 @@ __device__ __forceinline__ d3 antenna_field(const Antenna& ant, d3 d) {
         cph = lx / rho;
         sph = ly / rho;
     }
-    double c = ant.pattern == kPatTR38901 ? tr38901_amp_d(lz, lx, ly) : 1.0;
-    double tx = c * lz * cph, ty = c * lz * sph, tz = -c * rho;
+    double g = 1.0;
+    if (ant.pattern == kPatTR38901) g = tr38901_amp_d(lz, lx, ly);
+    else if (ant.pattern == kPatDipole) g = 1.2247448713915890 * rho;  // sqrt(1.5) sin(theta)
+    double zc, zs;
+    pol_angle(ant.pol, zc, zs);
+    const double ct = g * zc, cp = g * zs;
+    double tx = ct * lz * cph - cp * sph, ty = ct * lz * sph + cp * cph, tz = -ct * rho;
     return d3{R[0] * tx + R[1] * ty + R[2] * tz, R[3] * tx + R[4] * ty + R[5] * tz, R[6] * tx + R[7] * ty + R[8] * tz};
 }
 

@@ -170,7 +170,7 @@ __device__ DRot drot(D yaw, D pitch, D roll) {
     return o;
 }
 
-__device__ D3 dantenna(const DRot& Rr, int pattern, D3 d) {
+__device__ D3 dantenna(const DRot& Rr, int pattern, D3 d, int pol = 0) {
     const D* R = Rr.R;
     D lx = R[0] * d.x + R[3] * d.y + R[6] * d.z;
     D ly = R[1] * d.x + R[4] * d.y + R[7] * d.z;
@@ -192,8 +192,13 @@ __device__ D3 dantenna(const DRot& Rr, int pattern, D3 d) {
         D ah = -dmin(w * w * 12.0, dc(30.0));
         D a = -dmin(-(av + ah), dc(30.0));
         c = dexp10((a + dc(8.0)) * (1.0 / 20.0));
+    } else if (pattern == kPatDipole) {
+        c = rho * 1.2247448713915890;  // sqrt(1.5) sin(theta)
     }
-    D tx = c * lz * cph, ty = c * lz * sph, tz = -(c * rho);
+    double zc, zs;
+    pol_angle(pol, zc, zs);
+    const D ct = c * zc, cp = c * zs;
+    D tx = ct * lz * cph - cp * sph, ty = ct * lz * sph + cp * cph, tz = -(ct * rho);
     return D3{R[0] * tx + R[1] * ty + R[2] * tz, R[3] * tx + R[4] * ty + R[5] * tz, R[6] * tx + R[7] * ty + R[8] * tz};
 }
 
@@ -265,7 +270,7 @@ __global__ void power_grad_kernel(GradArgs g, MatTable mats) {
         L = L + l;
         dir[k] = s * (dc(1.0) / l);
     }
-    const D3 F0 = dantenna(Rt, g.tx_pattern, dir[0]);
+    const D3 F0 = dantenna(Rt, g.tx_pattern, dir[0], g.tx_pol);
     C3 E{C{F0.x, dc(0.0)}, C{F0.y, dc(0.0)}, C{F0.z, dc(0.0)}};
     // values kept for the material sweep
     d3 ep_v[kMaxK], eli_v[kMaxK], elr_v[kMaxK];
@@ -318,7 +323,7 @@ __global__ void power_grad_kernel(GradArgs g, MatTable mats) {
     const Antenna ra = g.rx_ant[r];
     DRot Rr;
     for (int i = 0; i < 9; ++i) Rr.R[i] = dc(ra.Rd[i]);
-    const D3 Fr = dantenna(Rr, ra.pattern, mdK);
+    const D3 Fr = dantenna(Rr, ra.pattern, mdK, ra.pol);
     const D amp = dc(g.lambda / (4.0 * kPi)) / L;
     const C pr = cdot(E, Fr);
     const C a{pr.re * amp, pr.im * amp};
@@ -387,7 +392,7 @@ __global__ __launch_bounds__(256) void coverage_grad_kernel(CovGradArgs g, MatTa
          j += (int64_t)gridDim.x * blockDim.x) {
         d3 d = fib_dir(g.begin + j * g.stride, g.num_rays);
         d3 o{g.tx[0], g.tx[1], g.tx[2]};
-        const D3 F0 = dantenna(Rt, g.tx_pattern, dconst(d));
+        const D3 F0 = dantenna(Rt, g.tx_pattern, dconst(d), g.tx_pol);
         cd E[3] = {cd{F0.x.v, 0.0}, cd{F0.y.v, 0.0}, cd{F0.z.v, 0.0}};
         cd dE[kCovT][3];
 #pragma unroll

@@ -149,7 +149,7 @@ struct GradArgs {
     double freq, lambda;
     double tx[3];
     double yaw, pitch, roll;
-    int32_t tx_pattern;
+    int32_t tx_pattern, tx_pol;
     const double* rx;
     const Antenna* rx_ant;
     int32_t nrx, P, fd;
@@ -193,7 +193,7 @@ struct CovGradArgs {
     int32_t nm;
     double tx[3];
     double yaw, pitch, roll;
-    int32_t tx_pattern;
+    int32_t tx_pattern, tx_pol;
     int32_t gnx, gny;
     Antenna rx_ant;
     double gx0, gy0, gcell, gz;

@@ -34,6 +34,8 @@ MATERIALS_28GHZ = {"concrete": (5.31, 0.4838), "glass": (6.27, 0.2290), "metal":
 
 PATTERN_ISO = 0
 PATTERN_TR38901 = 1
+PATTERN_DIPOLE = 2
+POL_V, POL_H, POL_SLANT_P45, POL_SLANT_M45 = 0, 1, 2, 3
 
 
 @dataclass

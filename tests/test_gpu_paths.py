@@ -58,7 +58,7 @@ def _check_paths(gp, op):
     return n
 
 
-@pytest.mark.parametrize("case", ["toy", "urban", "urban_tr38901"])
+@pytest.mark.parametrize("case", ["toy", "urban", "urban_tr38901", "urban_dipole_pol"])
 def test_paths_match_oracle(case):
     m = lib()
     if case == "toy":
@@ -71,6 +71,13 @@ def test_paths_match_oracle(case):
         w = sg.diff_workload(num_rays=100_000)
         w.rx = w.rx[:24]
         p = params(w, max_paths_per_rx=64)
+        if case == "urban_dipole_pol":  # H-pol dipole transmitter, +45 degree dipole receivers
+            w.tx[0].pattern = sg.PATTERN_DIPOLE
+            w.tx[0].pol = sg.POL_H
+            for r in w.rx:
+                r.pattern = sg.PATTERN_DIPOLE
+                r.pol = sg.POL_SLANT_P45
+                r.yaw = 0.7
     o = m.compute_paths(ctx(), scene(w.scene), p, w.tx, w.rx)
     g = geom.Geometry(w.scene)
     r = sbr.trace(w.scene, w.tx[0], oracle_params(p), candidates=True, geo=g)
@@ -180,13 +187,18 @@ def test_los_only_depth_zero():
     _check_paths(_gpu_paths(o), image.paths(g, w.tx[0], w.rx, []))
 
 
-@pytest.mark.parametrize("pattern", ["tr38901", "iso"])
+@pytest.mark.parametrize("pattern", ["tr38901", "iso", "tr38901_slant", "dipole_h"])
 def test_power_gradient_matches_finite_differences(pattern):
     m = lib()
     w = sg.diff_workload(num_rays=100_000)
     if pattern == "iso":  # untilted isotropic V-pol: rotating about z leaves its field unchanged
         w.tx[0].pattern = sg.PATTERN_ISO
         w.tx[0].pitch = 0.0
+    elif pattern == "tr38901_slant":
+        w.tx[0].pol = sg.POL_SLANT_P45
+    elif pattern == "dipole_h":
+        w.tx[0].pattern = sg.PATTERN_DIPOLE
+        w.tx[0].pol = sg.POL_H
     w.rx = w.rx[:40]
     p = params(w, max_paths_per_rx=64)
     sc = scene(w.scene)

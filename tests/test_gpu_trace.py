@@ -84,19 +84,26 @@ def _coverage_case(name):
     if name == "urban_tr38901":
         w = sg.diff_workload(num_rays=300_000)
         return w, params(w)
+    if name == "urban_dipole_slant":  # dipole transmitter at -45 degrees, H-pol receive pattern
+        w = sg.urban_workload(num_rays=1_000_000)
+        w.tx[0].pattern = sg.PATTERN_DIPOLE
+        w.tx[0].pol = sg.POL_SLANT_M45
+        w.tx[0].pitch = 0.3
+        w.rx_ant = sg.Device((0.0, 0.0, 0.0), pattern=sg.PATTERN_ISO, pol=sg.POL_H)
+        return w, params(w)
     raise KeyError(name)
 
 
-@pytest.mark.parametrize("name", ["toy", "urban", "urban_tr38901"])
+@pytest.mark.parametrize("name", ["toy", "urban", "urban_tr38901", "urban_dipole_slant"])
 def test_coverage_matches_oracle(name):
     m = lib()
     w, p = _coverage_case(name)
-    out = m.coverage_map(ctx(), scene(w.scene), p, w.tx[0], w.grid)
+    out = m.coverage_map(ctx(), scene(w.scene), p, w.tx[0], w.grid, rx_ant=w.rx_ant)
     gain = out["gain"].cpu().numpy().astype(np.float64)
     hits = out["hits"].cpu().numpy()
     db = out["gain_db"].cpu().numpy()
     rb = out["ray_bounces"].cpu().numpy()
-    g_ref, h_ref, n_amb = sbr.coverage(w.scene, w.tx[0], oracle_params(p), w.grid)
+    g_ref, h_ref, n_amb = sbr.coverage(w.scene, w.tx[0], oracle_params(p), w.grid, rx_ant=w.rx_ant)
     allowed = 2 * (p.max_depth + 1) * n_amb
     # hit counts are integers decided in fp64 on both sides
     assert int((hits != h_ref).sum()) <= allowed
