@@ -51,6 +51,15 @@ FLOP_RAYGEN = 70.0
 # FMA = 2 flops -> 78.6 TFLOP/s for fp64 and for non-packed fp32 (the build
 # disables packed fp32).
 PEAK_ALU_TFLOPS = 78.6
+PEAK_LANE_OPS = 39.3e12
+# Lane operations (one per issued lane instruction, an FMA counts once) of the
+# traversal terms, exact for the code: a 4-wide node visit is 4 x (6 FMA + 12
+# min/max + 3) = 84; a Moller-Trumbore test is 32 (two cross products 6 each,
+# four dot products 3 each, 3 subtractions, 5 comparisons).  The other terms
+# (deposit, reflection, ray generation) are left out, so the lane-op fraction
+# below is a lower bound.
+LANE_NODE = 84.0
+LANE_TRI = 32.0
 COPY_PROBE_BYTES = 256 << 20
 # Sources that make up the shoot-and-bounce kernel: HBM traffic measured with
 # counters is reported only while they are unchanged.
@@ -214,6 +223,8 @@ def main():
         "kernel": "sbr_bounce<coverage, first bounce> (depth-0 launch: %d rays)" % int(wk[0][0]),
         "kernel_ms": round(float(k_ms[0]), 4),
         "flop_per_launch": float(flops_depth[0]),
+        "traversal_lane_op_frac": round(float((LANE_NODE * wk[1][0] + LANE_TRI * wk[2][0]) / (k_ms[0] / 1e3)
+                                              / PEAK_LANE_OPS), 4),
         "longest_launch": "depth %d, %.3f ms" % (dom, float(k_ms[dom])),
         "all_launches": {"kernel_ms_per_depth": [round(float(x), 4) for x in k_ms],
                          "achieved": round(float(achieved_all), 3),
