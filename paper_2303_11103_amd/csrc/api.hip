@@ -842,7 +842,8 @@ namespace {
 rt_status cfr_setup(rt_ctx* c, int32_t ntx, int32_t nrx, int32_t P, const float* a, const float* tau,
                     const float* aod, const float* aoa, const int32_t* depth, double freq_hz, int32_t K,
                     double spacing_hz, int32_t nt_el, const double* tx_el, int32_t nr_el, const double* rx_el,
-                    const double* v_tx, const double* v_rx, int32_t T, double fs, rt::CfrArgs& cf) {
+                    const double* v_tx, const double* v_rx, int32_t T, double fs, const void* out_a,
+                    const void* out_b, rt::CfrArgs& cf) {
     if (!c || !a || !tau || !aod || !aoa || !depth) return fail(RT_ERR_ARG, "NULL argument");
     if (ntx < 1 || nrx < 1 || P < 1) return fail(RT_ERR_ARG, "ntx, nrx and P must be >= 1");
     if (!(freq_hz > 0) || !std::isfinite(freq_hz)) return fail(RT_ERR_ARG, "frequency must be positive");
@@ -865,6 +866,7 @@ rt_status cfr_setup(rt_ctx* c, int32_t ntx, int32_t nrx, int32_t P, const float*
     put(v_rx, 3 * (int64_t)nrx);
     for (double v : h)
         if (!std::isfinite(v)) return fail(RT_ERR_ARG, "element offsets and velocities must be finite");
+    if (!out_a || !out_b) return fail(RT_ERR_ARG, "NULL argument");
     RT_HIP(hipSetDevice(c->device));
     RT_HIP(ensure(c->chan, h.size() * sizeof(double)));
     RT_HIP(hipMemcpyAsync(c->chan.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -902,10 +904,9 @@ rt_status rt_paths_cfr(rt_ctx* c, int32_t ntx, int32_t nrx, int32_t P, const flo
                        const float* aod, const float* aoa, const int32_t* depth, double freq_hz, int32_t K,
                        double spacing_hz, int32_t nt_el, const double* tx_el, int32_t nr_el, const double* rx_el,
                        const double* v_tx, const double* v_rx, int32_t T, double fs, float* H) {
-    if (!H) return fail(RT_ERR_ARG, "NULL argument");
     rt::CfrArgs cf;
     rt_status st = cfr_setup(c, ntx, nrx, P, a, tau, aod, aoa, depth, freq_hz, K, spacing_hz, nt_el, tx_el, nr_el,
-                             rx_el, v_tx, v_rx, T, fs, cf);
+                             rx_el, v_tx, v_rx, T, fs, H, H, cf);
     if (st != RT_OK) return st;
     cf.H = H;
     RT_HIP(rt::launch_cfr(cf, c->stream));
@@ -917,10 +918,9 @@ rt_status rt_paths_cfr_adjoint(rt_ctx* c, int32_t ntx, int32_t nrx, int32_t P, c
                                double spacing_hz, int32_t nt_el, const double* tx_el, int32_t nr_el,
                                const double* rx_el, const double* v_tx, const double* v_rx, int32_t T, double fs,
                                const float* G, double* g) {
-    if (!G || !g) return fail(RT_ERR_ARG, "NULL argument");
     rt::CfrArgs cf;
     rt_status st = cfr_setup(c, ntx, nrx, P, a, tau, aod, aoa, depth, freq_hz, K, spacing_hz, nt_el, tx_el, nr_el,
-                             rx_el, v_tx, v_rx, T, fs, cf);
+                             rx_el, v_tx, v_rx, T, fs, G, g, cf);
     if (st != RT_OK) return st;
     RT_HIP(rt::launch_cfr_adjoint(cf, G, g, c->stream));
     return RT_OK;

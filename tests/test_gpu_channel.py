@@ -180,3 +180,26 @@ def test_learning_radio_materials_from_frequency_responses():
         assert np.all(np.abs(learned - true) / true < 1e-2)
     finally:
         sc.set_materials(true)
+
+
+def test_cfr_edge_cases():
+    m = lib()
+    w, p, sc, o = _urban_paths(m)
+    # receivers without paths give zero responses; time steps need a sampling frequency
+    H = m.paths_cfr(ctx(), o, w.scene.freq_hz, **KW).cpu()
+    none = (o["depth"][0] < 0).all(-1).cpu()
+    assert none.any() and torch.all(H[0][none] == 0)
+    with pytest.raises(RuntimeError, match="sampling frequency"):
+        m.paths_cfr(ctx(), o, w.scene.freq_hz, num_time_steps=2, **KW)
+    with pytest.raises(RuntimeError, match="subcarriers"):
+        m.paths_cfr(ctx(), o, w.scene.freq_hz, num_subcarriers=0, spacing=30e3)
+    with pytest.raises(RuntimeError, match="finite"):
+        m.paths_cfr(ctx(), o, w.scene.freq_hz, tx_el=[[np.inf, 0.0, 0.0], [0.0, 0.0, 0.0]], **KW)
+    with pytest.raises(ValueError):
+        m.paths_cfr(ctx(), o, w.scene.freq_hz, v_rx=np.zeros((3, 3)), **KW)
+    # one subcarrier at the carrier: H = sum a exp(-j 2 pi f_c tau)
+    H1 = m.paths_cfr(ctx(), o, w.scene.freq_hz, num_subcarriers=1, spacing=0.0).cpu().numpy()[0, :, 0, 0, 0, 0]
+    pairs = _pairs(o)
+    for r in range(16):
+        ref = sum(a * np.exp(-2j * np.pi * w.scene.freq_hz * tau) for a, tau, _, _ in pairs[0, r])
+        assert abs(H1[r] - ref) <= 1e-5 * (sum(abs(x[0]) for x in pairs[0, r]) + 1e-30)

@@ -122,3 +122,14 @@ def test_coverage_grad_argument_errors():
     tri5, t5 = m.trace_record(ctx(), sc5, p, w.tx[0])
     with pytest.raises(RuntimeError, match="at most 4 materials"):
         m.coverage_grad(ctx(), sc5, p, w.tx[0], GRID, tri5, t5)
+
+
+def test_coverage_gradient_of_sub_lattices_adds_up_and_empty_region_is_zero():
+    m = lib()
+    w = sg.diff_workload(num_rays=60_000)
+    sc = scene(w.scene)
+    full = _gpu(m, sc, params(w), w.tx[0], None)
+    parts = sum(_gpu(m, sc, params(w, ray_begin=b, ray_stride=3), w.tx[0], None) for b in range(3))
+    assert np.allclose(parts, full, rtol=1e-9, atol=1e-12 * np.abs(full).max())
+    zero = _gpu(m, sc, params(w), w.tx[0], np.zeros((GRID.ny, GRID.nx), dtype=np.uint8))
+    assert np.all(zero == 0.0)
