@@ -27,5 +27,6 @@ Modules
   grad      received-power loss and central finite differences
   covgrad   coverage-map region gain and its central finite differences
   channel   channel frequency responses of paths (synthetic arrays, Doppler, OFDM)
+  scatter   Lambertian diffuse scattering for coverage maps (SplitMix64 draws)
   mlp       float64 Fourier-feature MLP with manual backward (surrogate)
 """

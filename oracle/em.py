@@ -169,6 +169,21 @@ def transfer(E, d, d_r, n_f, r_perp, r_par):
             + np.asarray(r_par)[..., None] * a_par[..., None] * e_par_r)
 
 
+def transfer_scattered(E, d, d_s, n_f, r_perp, r_par):
+    """Field of a diffusely scattered ray leaving in direction d_s: the
+    reflected components r_perp a_perp, r_par a_par of the incident field,
+    carried by the transverse basis of d_s (e_perp' = d_s x n / |d_s x n|,
+    e_par' = e_perp' x d_s).  For d_s the specular direction this is transfer()."""
+    e_perp = perp_basis(d, n_f)
+    e_par_i = np.cross(e_perp, d)
+    s_perp = perp_basis(d_s, n_f)
+    s_par = np.cross(s_perp, d_s)
+    a_perp = np.einsum("...i,...i->...", E, e_perp)
+    a_par = np.einsum("...i,...i->...", E, e_par_i)
+    return (np.asarray(r_perp)[..., None] * a_perp[..., None] * s_perp
+            + np.asarray(r_par)[..., None] * a_par[..., None] * s_par)
+
+
 def wavelength(freq_hz):
     from .consts import C0
     return C0 / freq_hz

@@ -32,7 +32,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import em, fib, native
+from . import em, fib, native, scatter as scat
 from .consts import TMIN_DEFAULT
 from .geom import Geometry
 
@@ -78,7 +78,7 @@ def _cross_plane(o, d, t_hit, grid):
 
 
 def trace(scene, tx, params: TraceParams, grid=None, rx_ant=None, record=False, delta=1e-6,
-          candidates=False, threads=None, geo=None, idx=None, sphere=None) -> TraceResult:
+          candidates=False, threads=None, geo=None, idx=None, sphere=None, scattering=None) -> TraceResult:
     """Trace the (sub)set of lattice rays of one transmitter.
 
     With ``grid`` the coverage map (gain, hits) is accumulated; ``record``
@@ -96,6 +96,9 @@ def trace(scene, tx, params: TraceParams, grid=None, rx_ant=None, record=False, 
     ``res.sphere_sure[r]`` those accepted by a ray that never passed within
     delta of an edge, away from the radius, and ``res.sphere_borderline`` the
     (r, sequence) pairs decided within 1e-6 relative of the radius by some ray.
+
+    ``scattering = (S [nm], seed)`` makes reflections diffuse with probability
+    S^2 of the hit material (Lambertian, see oracle.scatter).
     """
     geo = geo or Geometry(scene)
     lam = em.wavelength(geo.freq)
@@ -193,7 +196,23 @@ def trace(scene, tx, params: TraceParams, grid=None, rx_ant=None, record=False, 
         d_r, n_f, cos_i = em.reflect(d, n_tri)
         m = geo.tri_mat[tri]
         r_perp, r_par = em.fresnel(eta_m[m], cos_i, pec=pec_m[m])
-        E = em.transfer(E, d, d_r, n_f, r_perp, r_par)
+        if scattering is not None:
+            S = np.asarray(scattering[0], dtype=np.float32).astype(np.float64)[m]
+            ray_i = idx[alive]
+            u = scat.uniform(scattering[1], scat.counter(ray_i, k, params.max_depth, 0))
+            dif = u < S * S
+            if np.any(dif):
+                u1 = scat.uniform(scattering[1], scat.counter(ray_i[dif], k, params.max_depth, 1))
+                u2 = scat.uniform(scattering[1], scat.counter(ray_i[dif], k, params.max_depth, 2))
+                d_s = d_r.copy()
+                d_s[dif] = scat.lambert_dirs(n_f[dif], u1, u2)
+                E_s = em.transfer(E, d, d_r, n_f, r_perp, r_par)
+                E_s[dif] = em.transfer_scattered(E[dif], d[dif], d_s[dif], n_f[dif], r_perp[dif], r_par[dif])
+                E, d_r = E_s, d_s
+            else:
+                E = em.transfer(E, d, d_r, n_f, r_perp, r_par)
+        else:
+            E = em.transfer(E, d, d_r, n_f, r_perp, r_par)
         o, d = p, d_r
         excl = geo.face[tri].astype(np.int32)
         if sphere is not None:
@@ -241,14 +260,15 @@ def _iso():
     return SimpleNamespace(yaw=0.0, pitch=0.0, roll=0.0, pattern=em.PATTERN_ISO)
 
 
-def coverage(scene, tx, params, grid, rx_ant=None, threads=None, geo=None, delta=1e-6):
+def coverage(scene, tx, params, grid, rx_ant=None, threads=None, geo=None, delta=1e-6, scattering=None):
     """(gain (ny, nx), hits (ny, nx), number of ambiguous rays) for one
     transmitter.  A ray is ambiguous when it passes within ``delta`` of a
     triangle edge it could hit, or crosses the grid plane within ``delta`` of
     a cell border, of its origin or of its hit point; an implementation that
     rounds differently may route such a ray differently, which changes at most
     2 (max_depth + 1) cells per ambiguous ray."""
-    r = trace(scene, tx, params, grid=grid, rx_ant=rx_ant, threads=threads, geo=geo, delta=delta)
+    r = trace(scene, tx, params, grid=grid, rx_ant=rx_ant, threads=threads, geo=geo, delta=delta,
+              scattering=scattering)
     return r.gain, r.hits, int(r.ambiguous.sum())
 
 
