@@ -149,6 +149,19 @@ const char* rt_last_error(void);
  * hierarchy on the host and uploads everything to the device (synchronous). */
 rt_status rt_scene_create(rt_ctx* ctx, const float* V, int64_t nv, const int32_t* F, int64_t nt,
                           const int32_t* tri_mat, const rt_material* mats, int32_t nm, rt_scene** out);
+/* Diffuse scattering (Sec. II-B lists diffuse reflections among the
+ * interactions; the model here is Lambertian).  S [nm] (host) scattering
+ * coefficient per material in [0, 1]: in coverage maps and rt_trace_record a
+ * reflection is diffuse with probability S^2 (the scattered power fraction)
+ * and the ray then leaves in a cosine-weighted direction around the normal,
+ * carrying the reflected field components in that direction's transverse
+ * basis; otherwise it is specular.  The draws come from the SplitMix64 stream
+ * with the given seed: draw (i (max_depth + 1) + k) 3 + j for lattice ray i,
+ * interaction depth k and j = 0 (diffuse or not), 1, 2 (direction).  Paths
+ * stay specular; rt_coverage_grad requires all S = 0.  RT_ERR_ARG for a count
+ * that differs from the scene's or S outside [0, 1]. */
+rt_status rt_scene_set_scattering(rt_scene* scene, const float* S, int32_t nm, uint64_t seed);
+
 /* Replace the material table (same count); no rebuild.  Synchronous. */
 rt_status rt_scene_set_materials(rt_scene* scene, const rt_material* mats, int32_t nm);
 rt_status rt_scene_info(const rt_scene* scene, rt_scene_info_t* out);

@@ -68,6 +68,7 @@ SIGNATURES = {
     "rt_synchronize": [P],
     "rt_last_error": [],
     "rt_scene_create": [P, P, I64, P, I64, P, P, I32, ctypes.POINTER(P)],
+    "rt_scene_set_scattering": [P, P, I32, ctypes.c_uint64],
     "rt_scene_set_materials": [P, P, I32],
     "rt_scene_info": [P, ctypes.POINTER(rt_scene_info_t)],
     "rt_scene_face_ids": [P, P],

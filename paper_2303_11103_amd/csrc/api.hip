@@ -86,6 +86,8 @@ struct rt_scene {
     rt_ctx* ctx = nullptr;
     rt::HostScene host;
     std::vector<rt_material> mats;
+    std::vector<float> scat;   // scattering coefficient per material (empty: none)
+    uint64_t scat_seed = 0;
     DevBuf nodes, tris, shades, faces, face_tris, leaf_of_input;
     rt::DevScene dev{};
 };
@@ -159,6 +161,7 @@ rt::MatTable make_mats(const rt_scene* s, double freq) {
         m.eta_im_d = m.pec ? 0.0 : -sg / (kEps0 * w);
         m.eta_re = (float)m.eta_re_d;
         m.eta_im = (float)m.eta_im_d;
+        m.scat = i < s->scat.size() ? s->scat[i] : 0.0f;
     }
     return t;
 }
@@ -216,6 +219,7 @@ rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_dev
     a.perm_full = a.perm_f ? (count / a.perm_f) * a.perm_f : 0;
     a.perm_inv = a.perm_f ? 1.0 / (double)a.perm_f : 0.0;
     a.tmin = p->t_min;
+    a.scat_seed = s->scat_seed;
     for (int i = 0; i < 3; ++i) a.tx[i] = tx->pos[i];
     a.tx_ant = make_antenna(tx);
     if (rx_ant) a.rx_ant = make_antenna(rx_ant);
@@ -392,6 +396,16 @@ rt_status rt_scene_set_materials(rt_scene* s, const rt_material* mats, int32_t n
     if (st != RT_OK) return st;
     if ((size_t)nm != s->mats.size()) return fail(RT_ERR_ARG, "material count differs from the scene's");
     s->mats.assign(mats, mats + nm);
+    return RT_OK;
+}
+
+rt_status rt_scene_set_scattering(rt_scene* s, const float* S, int32_t nm, uint64_t seed) {
+    if (!s || !S) return fail(RT_ERR_ARG, "NULL argument");
+    if ((size_t)nm != s->mats.size()) return fail(RT_ERR_ARG, "material count differs from the scene's");
+    for (int32_t i = 0; i < nm; ++i)
+        if (!(S[i] >= 0.0f && S[i] <= 1.0f)) return fail(RT_ERR_ARG, "scattering coefficients must lie in [0, 1]");
+    s->scat.assign(S, S + nm);
+    s->scat_seed = seed;
     return RT_OK;
 }
 
@@ -800,6 +814,8 @@ rt_status rt_coverage_grad(rt_ctx* c, rt_scene* s, const rt_trace_params* p, con
         return fail(RT_ERR_ARG, "grid origin, cell size and height must be finite, cell > 0");
     const int nm = (int)s->mats.size();
     if (nm > rt::kCovMaxMat) return fail(RT_ERR_ARG, "coverage gradient supports at most 4 materials");
+    for (float v : s->scat)
+        if (v > 0.0f) return fail(RT_ERR_ARG, "coverage gradient needs specular reflection (scattering coefficients 0)");
     RT_HIP(hipSetDevice(c->device));
     RT_HIP(hipMemsetAsync(out, 0, (size_t)(2 * nm + 3) * sizeof(double), c->stream));
     rt::CovGradArgs a{};

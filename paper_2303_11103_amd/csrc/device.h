@@ -189,6 +189,35 @@ __device__ __forceinline__ d3 antenna_field(const Antenna& ant, d3 d) {
     return d3{R[0] * tx + R[1] * ty + R[2] * tz, R[3] * tx + R[4] * ty + R[5] * tz, R[6] * tx + R[7] * ty + R[8] * tz};
 }
 
+// Draw c of the SplitMix64 stream seeded with s (the generator's stateless
+// form: the state after c + 1 steps is s + (c + 1) g), and a uniform in [0, 1)
+// from its top 53 bits.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t s, uint64_t c) {
+    uint64_t z = s + (c + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ double uniform01(uint64_t s, uint64_t c) {
+    return (double)(splitmix64(s, c) >> 11) * 0x1p-53;
+}
+
+// Cosine-weighted (Lambertian) direction around the unit normal n from two
+// uniforms: frame t = normalize(n x a) with a the coordinate axis least aligned
+// with n (lowest index on ties), b = n x t; direction
+// sqrt(u1) (cos 2 pi u2 t + sin 2 pi u2 b) + sqrt(1 - u1) n.
+__device__ __forceinline__ d3 lambert_dir(d3 n, double u1, double u2) {
+    const double ax = fabs(n.x), ay = fabs(n.y), az = fabs(n.z);
+    const d3 a = (ax <= ay && ax <= az) ? d3{1.0, 0.0, 0.0} : (ay <= az ? d3{0.0, 1.0, 0.0} : d3{0.0, 0.0, 1.0});
+    d3 t = cross(n, a);
+    t = scale(t, 1.0 / norm(t));
+    const d3 b = cross(n, t);
+    const double r = sqrt(u1), z = sqrt(1.0 - u1);
+    double s, c;
+    sincospi(2.0 * u2, &s, &c);
+    return add(add(scale(t, r * c), scale(b, r * s)), scale(n, z));
+}
+
 // Direction of Fibonacci-lattice ray i of N (Sec. II-B): z = 1 - (2i+1)/N,
 // azimuth 2 pi frac(i g) with frac(i g) = (i * 0x9E3779B97F4A7C15 mod 2^64) / 2^64.
 __device__ __forceinline__ d3 fib_dir(int64_t i, int64_t N) {

@@ -47,6 +47,7 @@ struct SbrArgs {
     int64_t perm_full;       // positions below this are permuted (whole bands)
     double perm_inv;         // 1 / F_m
     double tmin;
+    uint64_t scat_seed;  // SplitMix64 seed of the diffuse-scattering draws
     double tx[3];
     Antenna tx_ant, rx_ant;
     // coverage

@@ -71,7 +71,7 @@ static_assert(sizeof(Face) == 64, "face record size");
 struct Mat {
     float eta_re, eta_im;      // complex relative permittivity eps_r - j sigma/(eps0 w)
     int32_t pec;               // perfect conductor
-    int32_t pad;
+    float scat;                // scattering coefficient S: a reflection is diffuse with probability S^2
     double eta_re_d, eta_im_d; // the same in fp64
 };
 

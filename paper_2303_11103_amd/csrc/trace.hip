@@ -344,20 +344,37 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
                 fresnel(mats.m[sh.mat], (float)cos_i, rp, rl);
                 const f3 fep{(float)ep.x, (float)ep.y, (float)ep.z};
                 const f3 feli{(float)eli.x, (float)eli.y, (float)eli.z};
-                const f3 felr{(float)elr.x, (float)elr.y, (float)elr.z};
+                f3 felr{(float)elr.x, (float)elr.y, (float)elr.z};
+                // diffuse scattering (coverage and record modes): with probability
+                // S^2 the ray leaves in a Lambertian direction and the reflected
+                // components ride on that direction's transverse basis
+                d3 dout = dr;
+                f3 fepo = fep;
+                if ((MODE & (kModeCoverage | kModeRecord)) && mats.m[sh.mat].scat > 0.0f) {
+                    const uint64_t ri = (uint64_t)(a.begin + (int64_t)st.ray * a.stride);
+                    const uint64_t c0 = (ri * (uint64_t)(a.max_depth + 1) + (uint64_t)a.depth) * 3ull;
+                    const double S = (double)mats.m[sh.mat].scat;
+                    if (uniform01(a.scat_seed, c0) < S * S) {
+                        dout = lambert_dir(n, uniform01(a.scat_seed, c0 + 1), uniform01(a.scat_seed, c0 + 2));
+                        const d3 eps = perp_basis(dout, n);
+                        const d3 els = cross(eps, dout);
+                        fepo = f3{(float)eps.x, (float)eps.y, (float)eps.z};
+                        felr = f3{(float)els.x, (float)els.y, (float)els.z};
+                    }
+                }
                 const cf Ex{st.E[0], st.E[1]}, Ey{st.E[2], st.E[3]}, Ez{st.E[4], st.E[5]};
                 const cf ap{fep.x * Ex.re + fep.y * Ey.re + fep.z * Ez.re, fep.x * Ex.im + fep.y * Ey.im + fep.z * Ez.im};
                 const cf al{feli.x * Ex.re + feli.y * Ey.re + feli.z * Ez.re,
                             feli.x * Ex.im + feli.y * Ey.im + feli.z * Ez.im};
                 const cf sp = cmul(rp, ap), sl = cmul(rl, al);
-                st.E[0] = sp.re * fep.x + sl.re * felr.x;
-                st.E[1] = sp.im * fep.x + sl.im * felr.x;
-                st.E[2] = sp.re * fep.y + sl.re * felr.y;
-                st.E[3] = sp.im * fep.y + sl.im * felr.y;
-                st.E[4] = sp.re * fep.z + sl.re * felr.z;
-                st.E[5] = sp.im * fep.z + sl.im * felr.z;
+                st.E[0] = sp.re * fepo.x + sl.re * felr.x;
+                st.E[1] = sp.im * fepo.x + sl.im * felr.x;
+                st.E[2] = sp.re * fepo.y + sl.re * felr.y;
+                st.E[3] = sp.im * fepo.y + sl.im * felr.y;
+                st.E[4] = sp.re * fepo.z + sl.re * felr.z;
+                st.E[5] = sp.im * fepo.z + sl.im * felr.z;
                 st.o = p;
-                st.d = dr;
+                st.d = dout;
                 st.excl = sh.face;
                 if (MODE & kModeCandidates) {
                     if (st.prefix != -2) st.prefix = cand_insert(a.table, a.table_mask, st.prefix, sh.face, a.overflow);

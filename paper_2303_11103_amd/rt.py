@@ -105,6 +105,12 @@ class Scene:
     def from_scenegen(cls, ctx, s):
         return cls(ctx, s.V, s.F, s.tri_mat, s.materials)
 
+    def set_scattering(self, S, seed=0):
+        """Lambertian scattering coefficient per material (see rt_scene_set_scattering)."""
+        s = np.ascontiguousarray(np.asarray(S, dtype=np.float32).reshape(-1))
+        check(lib.rt_scene_set_scattering(self.h, s.ctypes.data_as(ctypes.c_void_p), int(s.size),
+                                          ctypes.c_uint64(int(seed))))
+
     def set_materials(self, materials):
         mats = np.ascontiguousarray(materials, dtype=np.float32).reshape(-1, 2)
         marr = (L.rt_material * len(mats))(*[L.rt_material(float(e), float(s)) for e, s in mats])

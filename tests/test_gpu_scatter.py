@@ -1,0 +1,80 @@
+"""Diffuse (Lambertian) scattering in the shoot-and-bounce kernel against the
+FP64 oracle that draws the same SplitMix64 numbers: per-bounce hits of the
+scattered rays, the coverage map, the specular limit S = 0, and the argument
+checks."""
+import numpy as np
+import pytest
+import torch
+
+import scenegen as sg
+from oracle import sbr
+
+from gpu_common import compare_hits, ctx, lib, oracle_params, params, requires_gpu
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+S = [0.6, 0.35]   # concrete, glass
+SEED = 11
+
+
+def _scene(m, w, s=S):
+    sc = m.Scene.from_scenegen(ctx(), w.scene)  # an instance of its own: scattering is scene state
+    sc.set_scattering(s, SEED)
+    return sc
+
+
+def test_scattered_ray_hits_match_oracle():
+    m = lib()
+    w = sg.urban_workload(num_rays=100_000)
+    p = params(w)
+    sc = _scene(m, w)
+    tri, t = m.trace_record(ctx(), sc, p, w.tx[0])
+    orc = sbr.trace(w.scene, w.tx[0], oracle_params(p), record=True, scattering=(S, SEED))
+    compared, excluded = compare_hits(tri.cpu().numpy(), t.cpu().numpy(), orc)
+    print("compared", compared, "excluded", excluded, flush=True)
+    assert compared > 150_000
+
+
+def test_scattering_coverage_matches_oracle():
+    m = lib()
+    w = sg.urban_workload(num_rays=400_003)
+    p = params(w)
+    sc = _scene(m, w)
+    out = m.coverage_map(ctx(), sc, p, w.tx[0], w.grid)
+    gain = out["gain"].cpu().numpy().astype(np.float64)
+    hits = out["hits"].cpu().numpy()
+    g_ref, h_ref, n_amb = sbr.coverage(w.scene, w.tx[0], oracle_params(p), w.grid, scattering=(S, SEED))
+    allowed = 2 * (p.max_depth + 1) * n_amb
+    assert int((hits != h_ref).sum()) <= allowed
+    both = (h_ref > 0) & (hits == h_ref)
+    rel = np.abs(gain[both] - g_ref[both]) / g_ref[both]
+    assert np.quantile(rel, 0.999) < 1e-4 and int((rel > 1e-3).sum()) <= allowed
+    # scattering changes the map
+    plain = m.coverage_map(ctx(), _scene(m, w, [0.0, 0.0]), p, w.tx[0], w.grid)
+    assert int((plain["hits"].cpu().numpy() != hits).sum()) > 1000
+
+
+def test_zero_coefficients_reproduce_the_specular_map():
+    m = lib()
+    w = sg.urban_workload(num_rays=200_000)
+    p = params(w)
+    a = m.coverage_map(ctx(), m.Scene.from_scenegen(ctx(), w.scene), p, w.tx[0], w.grid)
+    b = m.coverage_map(ctx(), _scene(m, w, [0.0, 0.0]), p, w.tx[0], w.grid)
+    assert torch.equal(a["hits"], b["hits"])
+    ga, gb = a["gain"].double(), b["gain"].double()
+    assert torch.allclose(ga, gb, rtol=1e-6, atol=0.0)
+
+
+def test_scattering_argument_errors():
+    m = lib()
+    w = sg.urban_workload(num_rays=10_000)
+    sc = m.Scene.from_scenegen(ctx(), w.scene)
+    with pytest.raises(RuntimeError, match="\\[0, 1\\]"):
+        sc.set_scattering([0.5, 1.5])
+    with pytest.raises(RuntimeError, match="material count"):
+        sc.set_scattering([0.5])
+    sc.set_scattering([0.2, 0.0])
+    p = params(w)
+    tri, t = m.trace_record(ctx(), sc, p, w.tx[0])
+    with pytest.raises(RuntimeError, match="specular"):
+        m.coverage_grad(ctx(), sc, p, w.tx[0], w.grid, tri, t)
