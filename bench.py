@@ -368,6 +368,22 @@ def extras(rt, ctx, scene, w, torch):
                   "cfr_ms": round((t1 - t0) * 1e2, 4), "adjoint_ms": round((t2 - t1) * 1e2, 4),
                   "coef_grad_ms": round((t3 - t2) * 1e2, 4)}
     log("bench: cfr %s" % res["cfr"])
+    # the urban map with diffuse scattering (S = 0.6 concrete, 0.35 glass)
+    ss = rt.Scene.from_scenegen(ctx, w.scene)
+    ss.set_scattering([0.6, 0.35], 11)
+    outs = rt.coverage_map(ctx, ss, rt.TraceParams(w.scene.freq_hz, w.max_depth, w.num_rays), w.tx[0], w.grid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        outs = rt.coverage_map(ctx, ss, rt.TraceParams(w.scene.freq_hz, w.max_depth, w.num_rays), w.tx[0], w.grid)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / 5
+    rbs = int(outs["ray_bounces"].sum())
+    res["scattering"] = {"workload": "urban coverage map with Lambertian scattering S = (0.6, 0.35), 1e7 rays, depth 3",
+                         "coverage_map_ms": round(ms, 3), "ray_bounces": rbs,
+                         "M_ray_bounces_per_s": round(rbs / (ms / 1e3) / 1e6, 1)}
+    log("bench: scattering %s" % res["scattering"])
+    ss.close()
     # large procedural city: coverage map at full size
     c = sg.city_workload()
     t0 = time.perf_counter()
