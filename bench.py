@@ -131,7 +131,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the paths/gradient side measurements")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate measurement")
     ap.add_argument("--surrogate-steps", type=int, default=20000)
-    ap.add_argument("--surrogate-tx", type=int, default=4096)
+    ap.add_argument("--surrogate-tx", type=int, default=4096,
+                    help="training maps of the surrogate (plus 1/16 as many validation and test maps each)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy %d MiB once (reference kernel for HBM counters)" % (
                         256))
@@ -281,7 +282,7 @@ def main():
     if not args.no_surrogate:
         try:
             result["surrogate"] = surrogate_bench(rt, ctx, scene, w, torch, steps=args.surrogate_steps,
-                                                  n_tx=args.surrogate_tx)
+                                                  n_train=args.surrogate_tx)
         except Exception as e:
             log("bench: surrogate failed: %r" % (e,))
             result["surrogate_error"] = repr(e)
@@ -425,10 +426,10 @@ def extras(rt, ctx, scene, w, torch):
     return res
 
 
-def surrogate_bench(rt, ctx, scene, w, torch, steps=20000, n_tx=4096, seed=3):
+def surrogate_bench(rt, ctx, scene, w, torch, steps=20000, n_train=4096, seed=3):
     """Learned surrogate on the urban scene: ray-traced maps (1e7 rays, depth 3,
-    200x200 cells of 2 m) for transmitters uniform over the rooftops, split
-    7/8 train, 1/16 validation, 1/16 test; trained with the library's MFMA
+    200x200 cells of 2 m) for transmitters uniform over the rooftops, n_train
+    training maps plus n_train/16 validation and n_train/16 test maps; trained with the library's MFMA
     kernels; reports test RMSE in dB over cells with >= 16 hits, the
     fallback mask (cells whose validation RMSE exceeds 6 dB) and maps/s of
     the surrogate and of the ray tracer at the same resolution."""
@@ -436,6 +437,8 @@ def surrogate_bench(rt, ctx, scene, w, torch, steps=20000, n_tx=4096, seed=3):
     import scenegen as sg
     from paper_2303_11103_amd import surrogate as S
     grid = sg.Grid(-200.0, -200.0, 2.0, 200, 200, 1.5)
+    n_val = n_test = max(1, n_train // 16)
+    n_tx = n_train + n_val + n_test
     tx_np = sg.rooftop_tx_positions(w.scene, n_tx, seed=seed)
     dev = ctx.torch_device
     tx = torch.tensor(tx_np, device=dev)
@@ -445,8 +448,7 @@ def surrogate_bench(rt, ctx, scene, w, torch, steps=20000, n_tx=4096, seed=3):
     maps, mask = S.ray_traced_maps(ctx, scene, p, tx_np, grid)
     torch.cuda.synchronize()
     rt_s = time.perf_counter() - t0
-    n_val = n_test = max(1, n_tx // 16)
-    n_tr = n_tx - n_val - n_test
+    n_tr = n_train
     tr, va, te = slice(0, n_tr), slice(n_tr, n_tr + n_val), slice(n_tr + n_val, n_tx)
     # targets: cells with >= 16 hits; the dB values there are finite
     maps = torch.where(mask.bool(), maps, torch.zeros_like(maps))
