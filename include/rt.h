@@ -158,7 +158,7 @@ rt_status rt_scene_create(rt_ctx* ctx, const float* V, int64_t nv, const int32_t
  * basis; otherwise it is specular.  The draws come from the SplitMix64 stream
  * with the given seed: draw (i (max_depth + 1) + k) 3 + j for lattice ray i,
  * interaction depth k and j = 0 (diffuse or not), 1, 2 (direction).  Paths
- * stay specular; rt_coverage_grad requires all S = 0.  RT_ERR_ARG for a count
+ * stay specular; rt_coverage_grad replays the same draws.  RT_ERR_ARG for a count
  * that differs from the scene's or S outside [0, 1]. */
 rt_status rt_scene_set_scattering(rt_scene* scene, const float* S, int32_t nm, uint64_t seed);
 

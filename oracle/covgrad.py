@@ -27,10 +27,12 @@ from . import sbr
 from .geom import Geometry
 
 
-def region_gain(geo, scene, tx, params, grid, region=None, rx_ant=None, threads=None):
+def region_gain(geo, scene, tx, params, grid, region=None, rx_ant=None, threads=None, scattering=None):
     """Sum of the linear path gain over the cells with region != 0 (all cells
-    when region is None)."""
-    gain, _, _ = sbr.coverage(scene, tx, params, grid, rx_ant=rx_ant, threads=threads, geo=geo)
+    when region is None); ``scattering`` as in oracle.sbr.trace (its draws fix
+    every diffuse direction, so G stays smooth in theta)."""
+    gain, _, _ = sbr.coverage(scene, tx, params, grid, rx_ant=rx_ant, threads=threads, geo=geo,
+                              scattering=scattering)
     if region is None:
         return float(gain.sum())
     return float(gain[np.asarray(region) != 0].sum())
@@ -58,17 +60,17 @@ def perturbed(geo, tx, k, delta):
     return g2, t2
 
 
-def region_gain_fd(scene, tx, params, grid, region=None, rx_ant=None, rel_h=1e-4, threads=None):
+def region_gain_fd(scene, tx, params, grid, region=None, rx_ant=None, rel_h=1e-4, threads=None, scattering=None):
     """(G, dG/dtheta) with the gradient by central differences."""
     geo = Geometry(scene)
-    G0 = region_gain(geo, scene, tx, params, grid, region, rx_ant, threads)
+    G0 = region_gain(geo, scene, tx, params, grid, region, rx_ant, threads, scattering)
     theta = theta_of(geo, tx)
     grad = np.empty(theta.size)
     for k in range(theta.size):
         h = rel_h * max(abs(theta[k]), 1.0)
         gp, tp = perturbed(geo, tx, k, +h)
         gm, tm = perturbed(geo, tx, k, -h)
-        Gp = region_gain(gp, scene, tp, params, grid, region, rx_ant, threads)
-        Gm = region_gain(gm, scene, tm, params, grid, region, rx_ant, threads)
+        Gp = region_gain(gp, scene, tp, params, grid, region, rx_ant, threads, scattering)
+        Gm = region_gain(gm, scene, tm, params, grid, region, rx_ant, threads, scattering)
         grad[k] = (Gp - Gm) / (2.0 * h)
     return G0, grad

@@ -814,8 +814,6 @@ rt_status rt_coverage_grad(rt_ctx* c, rt_scene* s, const rt_trace_params* p, con
         return fail(RT_ERR_ARG, "grid origin, cell size and height must be finite, cell > 0");
     const int nm = (int)s->mats.size();
     if (nm > rt::kCovMaxMat) return fail(RT_ERR_ARG, "coverage gradient supports at most 4 materials");
-    for (float v : s->scat)
-        if (v > 0.0f) return fail(RT_ERR_ARG, "coverage gradient needs specular reflection (scattering coefficients 0)");
     RT_HIP(hipSetDevice(c->device));
     RT_HIP(hipMemsetAsync(out, 0, (size_t)(2 * nm + 3) * sizeof(double), c->stream));
     rt::CovGradArgs a{};
@@ -842,6 +840,7 @@ rt_status rt_coverage_grad(rt_ctx* c, rt_scene* s, const rt_trace_params* p, con
     const double lam = kC0 / p->freq_hz;
     a.wscale = (lam / (4.0 * M_PI)) * (lam / (4.0 * M_PI)) * (4.0 * M_PI / (double)p->num_rays) / (g->cell * g->cell);
     a.omega = 2.0 * M_PI * p->freq_hz;
+    a.scat_seed = s->scat_seed;
     a.region = region;
     a.hit_tri = hit_tri;
     a.hit_t = hit_t;

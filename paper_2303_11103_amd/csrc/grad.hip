@@ -438,7 +438,19 @@ __global__ __launch_bounds__(256) void coverage_grad_kernel(CovGradArgs g, MatTa
             const d3 p = add(o, scale(d, t));
             const d3 ep = perp_basis(d, n);
             const d3 eli = cross(ep, d);
-            const d3 elr = cross(ep, dr);
+            // the outgoing direction and transverse basis: specular, or diffuse
+            // with the forward kernel's draws (they depend on no parameter)
+            d3 dout = dr, epo = ep, elr = cross(ep, dr);
+            if (mats.m[sh.mat].scat > 0.0f) {
+                const uint64_t ri = (uint64_t)(g.begin + j * g.stride);
+                const uint64_t c0 = (ri * (uint64_t)(g.max_depth + 1) + (uint64_t)k) * 3ull;
+                const double S = (double)mats.m[sh.mat].scat;
+                if (uniform01(g.scat_seed, c0) < S * S) {
+                    dout = lambert_dir(n, uniform01(g.scat_seed, c0 + 1), uniform01(g.scat_seed, c0 + 2));
+                    epo = perp_basis(dout, n);
+                    elr = cross(epo, dout);
+                }
+            }
             const Mat mt = mats.m[sh.mat];
             cd rp, rl;
             fresnel(mt, cos_i, rp, rl);
@@ -457,13 +469,13 @@ __global__ __launch_bounds__(256) void coverage_grad_kernel(CovGradArgs g, MatTa
 #pragma unroll
             for (int i = 0; i < kCovT; ++i) {
                 const cd api = cmul(rp, dot3(dE[i], ep)), ali = cmul(rl, dot3(dE[i], eli));
-                dE[i][0] = cadd(cmulr(api, ep.x), cmulr(ali, elr.x));
-                dE[i][1] = cadd(cmulr(api, ep.y), cmulr(ali, elr.y));
-                dE[i][2] = cadd(cmulr(api, ep.z), cmulr(ali, elr.z));
+                dE[i][0] = cadd(cmulr(api, epo.x), cmulr(ali, elr.x));
+                dE[i][1] = cadd(cmulr(api, epo.y), cmulr(ali, elr.y));
+                dE[i][2] = cadd(cmulr(api, epo.z), cmulr(ali, elr.z));
             }
             if (sh.mat < kCovMaxMat && !mt.pec) {
-                const cd de[3] = {cadd(cmulr(dsp, ep.x), cmulr(dsl, elr.x)), cadd(cmulr(dsp, ep.y), cmulr(dsl, elr.y)),
-                                  cadd(cmulr(dsp, ep.z), cmulr(dsl, elr.z))};
+                const cd de[3] = {cadd(cmulr(dsp, epo.x), cmulr(dsl, elr.x)), cadd(cmulr(dsp, epo.y), cmulr(dsl, elr.y)),
+                                  cadd(cmulr(dsp, epo.z), cmulr(dsl, elr.z))};
                 const cd mj{0.0, -dsig};  // d eta / d sigma = -j / (eps0 w)
 #pragma unroll
                 for (int m = 0; m < kCovMaxMat; ++m)
@@ -475,11 +487,11 @@ __global__ __launch_bounds__(256) void coverage_grad_kernel(CovGradArgs g, MatTa
                         }
                     }
             }
-            E[0] = cadd(cmulr(sp, ep.x), cmulr(sl, elr.x));
-            E[1] = cadd(cmulr(sp, ep.y), cmulr(sl, elr.y));
-            E[2] = cadd(cmulr(sp, ep.z), cmulr(sl, elr.z));
+            E[0] = cadd(cmulr(sp, epo.x), cmulr(sl, elr.x));
+            E[1] = cadd(cmulr(sp, epo.y), cmulr(sl, elr.y));
+            E[2] = cadd(cmulr(sp, epo.z), cmulr(sl, elr.z));
             o = p;
-            d = dr;
+            d = dout;
         }
     }
     // block reduction (wave shuffles, then the four waves through LDS), one

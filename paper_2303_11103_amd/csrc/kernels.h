@@ -200,6 +200,7 @@ struct CovGradArgs {
     double gx0, gy0, gcell, gz;
     double wscale;            // (lambda/4pi)^2 (4pi/N) / cell^2
     double omega;             // 2 pi f
+    uint64_t scat_seed;       // draws of diffuse scattering (as in the forward kernel)
     const uint8_t* region;    // [gny][gnx] (nullable: every cell)
     const int32_t* hit_tri;   // [max_depth+1][count] input triangle ids (-1 miss, -2 terminated)
     const double* hit_t;      // [max_depth+1][count]

@@ -73,8 +73,21 @@ def test_scattering_argument_errors():
         sc.set_scattering([0.5, 1.5])
     with pytest.raises(RuntimeError, match="material count"):
         sc.set_scattering([0.5])
-    sc.set_scattering([0.2, 0.0])
+
+
+def test_coverage_gradient_with_scattering_matches_oracle_central_differences():
+    from oracle import covgrad
+    m = lib()
+    w = sg.diff_workload(num_rays=100_000)
     p = params(w)
+    sc = _scene(m, w)
+    grid = sg.Grid(-200.0, -200.0, 4.0, 100, 100, 1.5)
     tri, t = m.trace_record(ctx(), sc, p, w.tx[0])
-    with pytest.raises(RuntimeError, match="specular"):
-        m.coverage_grad(ctx(), sc, p, w.tx[0], w.grid, tri, t)
+    out = m.coverage_grad(ctx(), sc, p, w.tx[0], grid, tri, t).cpu().numpy()
+    G_ref, g_ref = covgrad.region_gain_fd(w.scene, w.tx[0], oracle_params(p), grid, scattering=(S, SEED))
+    assert abs(out[0] - G_ref) < 1e-4 * G_ref
+    scale = np.abs(g_ref)
+    big = scale > 1e-6 * scale.max()
+    err = np.abs(out[1:] - g_ref)[big] / scale[big]
+    print("gradient gpu", out[1:], "\noracle fd   ", g_ref, "\nrel", err, flush=True)
+    assert err.max() < 1e-3
