@@ -91,3 +91,24 @@ def test_coverage_gradient_with_scattering_matches_oracle_central_differences():
     err = np.abs(out[1:] - g_ref)[big] / scale[big]
     print("gradient gpu", out[1:], "\noracle fd   ", g_ref, "\nrel", err, flush=True)
     assert err.max() < 1e-3
+
+
+def test_scattered_hits_full_lattice_sampled():
+    """The bench configuration (urban, 1e7 rays, 3 bounces) with scattering:
+    every traced ray is recorded; a random sample of lattice indices is
+    re-traced by the oracle with the same draws."""
+    m = lib()
+    w = sg.urban_workload()
+    p = params(w)
+    tri, t = m.trace_record(ctx(), _scene(m, w), p, w.tx[0])
+    tri = tri.cpu().numpy()
+    t = t.cpu().numpy()
+    rng = np.random.default_rng(6)
+    pos = np.sort(rng.choice(p.num_rays, size=3000, replace=False))
+    total = 0
+    for k in range(len(pos) // 1000):
+        sub = pos[k * 1000:(k + 1) * 1000]
+        orc = sbr.trace(w.scene, w.tx[0], oracle_params(p), record=True, idx=sub, scattering=(S, SEED))
+        compared, _ = compare_hits(tri[:, sub], t[:, sub], orc)
+        total += compared
+    assert total > 4000
