@@ -205,6 +205,14 @@ rt_status rt_coverage_map(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p
                           const rt_device* rx_ant, const rt_grid* grid, float* gain, uint32_t* hits,
                           float* gain_db, uint64_t* ray_bounces);
 
+/* Coverage maps of ntx transmitters in one call (Sec. II-A: several
+ * transmitters per scene), each built as by rt_coverage_map with the same
+ * parameters, receive pattern and grid:
+ *   gain, hits [ntx][ny][nx] (dev); gain_db [ntx][ny][nx] (dev, nullable).
+ * Stops at the first transmitter that fails validation, with that error. */
+rt_status rt_coverage_maps(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p, const rt_device* tx, int32_t ntx,
+                           const rt_device* rx_ant, const rt_grid* grid, float* gain, uint32_t* hits, float* gain_db);
+
 /* rt_coverage_map that also counts, per depth k, the traced rays, the BVH
  * inner nodes visited and the triangles tested:
  *   work [3][max_depth+1] (dev) uint64 (rays, node visits, triangle tests).

@@ -75,6 +75,8 @@ SIGNATURES = {
     "rt_scene_destroy": [P],
     "rt_fibonacci_directions": [P, I64, I64, I64, I64, P],
     "rt_trace_record": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), P, P],
+    "rt_coverage_maps": [P, P, ctypes.POINTER(rt_trace_params), P, I32, ctypes.POINTER(rt_device),
+                         ctypes.POINTER(rt_grid), P, P, P],
     "rt_coverage_map": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), ctypes.POINTER(rt_device),
                         ctypes.POINTER(rt_grid), P, P, P, P],
     "rt_coverage_work": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), ctypes.POINTER(rt_device),

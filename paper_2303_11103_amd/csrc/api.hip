@@ -493,6 +493,19 @@ rt_status rt_coverage_map(rt_ctx* c, rt_scene* s, const rt_trace_params* p, cons
     return coverage_impl(c, s, p, tx, rx_ant, g, gain, hits, gain_db, ray_bounces, nullptr);
 }
 
+rt_status rt_coverage_maps(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx, int32_t ntx,
+                           const rt_device* rx_ant, const rt_grid* g, float* gain, uint32_t* hits, float* gain_db) {
+    if (!tx || ntx < 1) return fail(RT_ERR_ARG, "need at least one transmitter");
+    if (!g || !gain || !hits) return fail(RT_ERR_ARG, "NULL argument");
+    const int64_t cells = (int64_t)g->nx * g->ny;
+    for (int32_t k = 0; k < ntx; ++k) {
+        const rt_status st = coverage_impl(c, s, p, tx + k, rx_ant, g, gain + k * cells, hits + k * cells,
+                                           gain_db ? gain_db + k * cells : nullptr, nullptr, nullptr);
+        if (st != RT_OK) return st;
+    }
+    return RT_OK;
+}
+
 rt_status rt_coverage_work(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx,
                            const rt_device* rx_ant, const rt_grid* g, float* gain, uint32_t* hits, uint64_t* work) {
     if (!work) return fail(RT_ERR_ARG, "work is NULL");

@@ -177,6 +177,25 @@ def coverage_map(ctx: Context, scene: Scene, params: TraceParams, tx, grid, rx_a
     return out
 
 
+def coverage_maps(ctx: Context, scene: Scene, params: TraceParams, txs, grid, rx_ant=None, want_db=False):
+    """Coverage maps of several transmitters in one call: dict(gain, hits,
+    gain_db) of device tensors [ntx, ny, nx]."""
+    from types import SimpleNamespace
+    n = len(txs)
+    dev = ctx.torch_device
+    out = {"gain": torch.empty((n, grid.ny, grid.nx), dtype=torch.float32, device=dev),
+           "hits": torch.empty((n, grid.ny, grid.nx), dtype=torch.int32, device=dev)}
+    if want_db:
+        out["gain_db"] = torch.empty((n, grid.ny, grid.nx), dtype=torch.float32, device=dev)
+    rx_ant = rx_ant or SimpleNamespace(pos=(0.0, 0.0, 0.0), yaw=0.0, pitch=0.0, roll=0.0, pattern=0)
+    tx_arr = (L.rt_device * max(n, 1))(*[device_struct(t) for t in txs])
+    ctx._bind_stream()
+    p, r, g = params.c(), device_struct(rx_ant), grid_struct(grid)
+    check(lib.rt_coverage_maps(ctx.h, scene.h, ctypes.byref(p), tx_arr, n, ctypes.byref(r), ctypes.byref(g),
+                               _ptr(out["gain"]), _ptr(out["hits"]), _ptr(out.get("gain_db"))))
+    return out
+
+
 def compute_paths(ctx: Context, scene: Scene, params: TraceParams, txs, rxs):
     """Paths for every (tx, rx); returns dict of device tensors shaped [ntx, nrx, P, ...]."""
     ntx, nrx, P = len(txs), len(rxs), params.max_paths_per_rx

@@ -194,3 +194,20 @@ def test_argument_errors_are_reported():
         F = w.scene.F.copy()
         F[0, 0] = 10_000
         m.Scene(ctx(), w.scene.V, F, w.scene.tri_mat, w.scene.materials)
+
+
+def test_coverage_maps_of_several_transmitters_equal_single_calls():
+    m = lib()
+    w = sg.urban_workload(num_rays=300_000)
+    p = params(w)
+    sc = scene(w.scene)
+    pos = sg.rooftop_tx_positions(w.scene, 3, seed=4)
+    txs = [sg.Device(tuple(float(x) for x in q)) for q in pos]
+    many = m.coverage_maps(ctx(), sc, p, txs, w.grid, want_db=True)
+    for k, tx in enumerate(txs):
+        one = m.coverage_map(ctx(), sc, p, tx, w.grid)
+        assert torch.equal(many["hits"][k], one["hits"])
+        assert torch.allclose(many["gain"][k].double(), one["gain"].double(), rtol=1e-6, atol=0.0)
+        assert torch.allclose(many["gain_db"][k][one["hits"] > 0], one["gain_db"][one["hits"] > 0], atol=1e-5)
+    with pytest.raises(RuntimeError, match="at least one transmitter"):
+        m.coverage_maps(ctx(), sc, p, [], w.grid)
