@@ -1,28 +1,35 @@
 #!/usr/bin/env python3
 """Benchmark of the ray tracer's hot path on one MI355X.
 
-Workload (timed step): the coverage map of the urban-canyon scene -- 8x8 box
-buildings (770 triangles, concrete/glass at 3.5 GHz), one isotropic V-pol
-transmitter 2 m above a roof corner, 1e7 Fibonacci-lattice rays, up to 3
-specular reflections, 400x400 cells of 1 m at 1.5 m height.  One step =
-Fibonacci ray generation, closest-hit BVH traversal, coverage deposit,
-Fresnel reflection and queue compaction for every bounce, then the dB map.
+Headline workload (timed step): the coverage map of the large procedural
+city -- 50x50 blocks of extruded convex polygons (about 220k triangles,
+concrete/glass/metal at 28 GHz), a TR 38.901 transmitter (pitch +10 deg) 2 m
+above the tallest roof near the centre, 1e8 Fibonacci-lattice rays, up to 5
+specular reflections, 2000x2000 cells of 1 m at 1.5 m height.  One step =
+ray generation, closest-hit BVH traversal, coverage deposit, Fresnel
+reflection and queue compaction for every bounce (six chunks of 2^24 rays),
+then the dB map.  The urban canyon (8x8 boxes, 1e7 rays, depth 3, 400x400
+cells) is measured the same way as a secondary object.
 
 Prints one JSON line: value = ray-bounces (closest-hit queries, counted on
-the device) per second; roofline of the depth-0 shoot-and-bounce launch
-(algorithmic FLOPs from counted BVH node visits and triangle tests, divided
-by its HIP-event duration on the library's stream; all launches reported
-beside it); the FP64 CPU oracle timed on a
-bounded ray sample of the same workload; and side measurements of the paths
-(image method) and gradient kernels.
+the device) per second over the timed steps; the roofline of the
+shoot-and-bounce kernel with the largest share of the step time, from the
+work the method needs per unit (12 flop per child-box slab test, 46 per
+Moller-Trumbore test, 325 per ray-bounce for shading, crossing and deposit),
+with the units counted on the device, divided by that kernel's HIP-event
+durations on the library's stream; the FP64 CPU oracle timed on a strided
+lattice sample of the same workload (its rate per ray-bounce extrapolates to
+the full map); and side measurements (paths, gradients, channel responses,
+scattering, learned surrogate).
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -31,41 +38,28 @@ sys.path.insert(0, ROOT)
 
 BJ_METRIC = "M ray-bounces/s + coverage-map ms vs oracle; surrogate maps/s at <=3 dB RMSE"
 # Algorithmic work per unit (floating-point operations the method needs; an
-# FMA counts 2, an add/mul/min/max/compare 1):
-#   BVH inner-node visit = four fp32 ray/box slab tests (the children of a
-#     4-wide node): 24 FMA + 48 min/max + 12 for the interval tests = 108;
-#   triangle test = fp64 Moller-Trumbore without division: 46;
-#   every traced segment: coverage-plane crossing, cell index, receive
-#     pattern and |F_rx . E|^2 deposit: 40;
-#   every surviving ray (reflection): Fresnel r_perp/r_par (complex sqrt and
-#     two complex divisions), perpendicular/parallel bases, reflected
-#     direction and hit point, 3-vector complex field update: 160;
-#   every ray at depth 0: Fibonacci direction (z, rho, sincos of the golden
-#     phase) and transmit pattern: 70.
-FLOP_NODE = 108.0
+# FMA counts 2, min/max and compares are not counted):
+#   child-box slab test with a precomputed inverse direction: 6 FMA = 12;
+#   fp64 Moller-Trumbore test (two cross products, four dot products, one
+#     division): 46;
+#   every ray-bounce: reflection (complex square root, two complex divisions,
+#     perpendicular/parallel bases, reflected direction, 3-vector complex field
+#     update, about 300) plus plane crossing and cell deposit (about 25): 325.
+FLOP_BOX = 12.0
 FLOP_TRI = 46.0
-FLOP_DEPOSIT = 40.0
-FLOP_REFLECT = 160.0
-FLOP_RAYGEN = 70.0
+FLOP_RAY_BOUNCE = 325.0
 # MI355X VALU: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s,
 # FMA = 2 flops -> 78.6 TFLOP/s for fp64 and for non-packed fp32 (the build
 # disables packed fp32).
 PEAK_ALU_TFLOPS = 78.6
-PEAK_LANE_OPS = 39.3e12
-# Lane operations (one per issued lane instruction, an FMA counts once) of the
-# traversal terms, exact for the code: a 4-wide node visit is 4 x (6 FMA + 12
-# min/max + 3) = 84; a Moller-Trumbore test is 32 (two cross products 6 each,
-# four dot products 3 each, 3 subtractions, 5 comparisons).  The other terms
-# (deposit, reflection, ray generation) are left out, so the lane-op fraction
-# below is a lower bound.
-LANE_NODE = 84.0
-LANE_TRI = 32.0
 COPY_PROBE_BYTES = 256 << 20
-# Sources that make up the shoot-and-bounce kernel: HBM traffic measured with
+# Sources that make up the shoot-and-bounce kernels: HBM traffic measured with
 # counters is reported only while they are unchanged.
 KERNEL_SOURCES = ["paper_2303_11103_amd/csrc/" + f for f in
                   ("trace.hip", "traverse.h", "device.h", "kernels.h", "layout.h", "api.hip", "scene.cpp")]
-TRAFFIC_PROFILE = "profiles/sbr_bounce_urban_hbm_traffic.md"
+TRAFFIC_PROFILE = "profiles/sbr_bounce_hbm_traffic.md"
+KERNEL_KIND = {"first": "sbr_bounce<coverage> depth-0 launch (ray generation + first bounce)",
+               "bounce": "sbr_bounce<coverage> depth >= 1 launches (compacted queue)"}
 
 
 def kernel_sources_digest() -> str:
@@ -77,37 +71,44 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_per_launch():
-    """HBM bytes per depth-0 launch from the committed counter profile (FETCH_SIZE
-    + WRITE_SIZE, scaled by the copy probe), or None when the profile is missing
-    or was taken on other kernel sources."""
+def traffic_per_launch(workload: str, kind: str):
+    """HBM bytes per launch of one kernel kind on one workload from the
+    committed counter profile (FETCH_SIZE + WRITE_SIZE, each scaled by the copy
+    probe), or None when the profile is missing or was taken on other kernel
+    sources."""
     path = os.path.join(ROOT, TRAFFIC_PROFILE)
     if not os.path.exists(path):
         return None
-    vals = {}
+    digest = kernel_sources_digest()
     for line in open(path):
-        if line.startswith("traffic:"):
-            for kv in line[len("traffic:"):].split():
-                k, v = kv.split("=")
-                vals[k] = v
-    if vals.get("sources") != kernel_sources_digest() or "bytes_per_launch" not in vals:
-        return None
-    return float(vals["bytes_per_launch"])
+        if not line.startswith("traffic:"):
+            continue
+        vals = dict(kv.split("=", 1) for kv in line[len("traffic:"):].split())
+        if vals.get("sources") == digest and vals.get("workload") == workload and vals.get("kernel") == kind:
+            return float(vals["bytes_per_launch"])
+    return None
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(seconds_budget: float = 20.0):
-    """Time the FP64 oracle on a strided sample of the same workload."""
-    import numpy as np
-    import scenegen as sg
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, name, seconds_budget: float = 20.0):
+    """Time the FP64 oracle on a strided lattice sample of the workload; its
+    rate per ray-bounce extrapolates to the full map."""
     from oracle import native, sbr
-    w = sg.urban_workload()
     threads = native.default_threads()
-    stride = 1000
-    # grow the sample until it takes about seconds_budget (bounded: at most all rays)
+    stride = max(1, w.num_rays // 2000)
     while True:
         p = sbr.TraceParams(num_rays=w.num_rays, max_depth=w.max_depth, ray_begin=0, ray_stride=stride)
         t0 = time.perf_counter()
@@ -117,17 +118,136 @@ def cpu_baseline(seconds_budget: float = 20.0):
         if dt > seconds_budget / 3 or stride == 1:
             break
         stride = max(1, int(stride * dt / seconds_budget))
-    return {"value": segs / dt / 1e6, "unit": "M ray-bounces/s", "cores": threads, "kind": "oracle",
-            "sample": "urban canyon coverage map, lattice rays 0, %d, 2*%d, ... of 1e7 (%d rays, %d ray-bounces, "
-                      "depth 3), %.1f s on %d threads" % (stride, stride, len(r.ray_idx), segs, dt, threads)}
+    rate = segs / dt
+    return {"value": rate / 1e6, "unit": "M ray-bounces/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": "%s coverage map, lattice rays 0, %d, 2*%d, ... of %d (%d rays, %d ray-bounces, depth %d), "
+                      "%.1f s on %d threads; brute-force all-triangle intersection" % (
+                          name, stride, stride, w.num_rays, len(r.ray_idx), segs, w.max_depth, dt, threads)}
+
+
+def coverage_bench(rt, ctx, torch, w, name, steps, warmup):
+    """Times `steps` coverage maps of workload w after `warmup`, with per-launch
+    events; returns (result dict, scene)."""
+    import ctypes
+
+    import numpy as np
+    from paper_2303_11103_amd._lib import check, lib
+    dev = ctx.torch_device
+    t0 = time.perf_counter()
+    scene = rt.Scene.from_scenegen(ctx, w.scene)
+    scene_s = time.perf_counter() - t0
+    info = scene.info()
+    p = rt.TraceParams(w.scene.freq_hz, w.max_depth, w.num_rays)
+    tx = w.tx[0]
+    nd = w.max_depth + 1
+    out = {"gain": torch.empty((w.grid.ny, w.grid.nx), dtype=torch.float32, device=dev),
+           "hits": torch.empty((w.grid.ny, w.grid.nx), dtype=torch.int32, device=dev),
+           "gain_db": torch.empty((w.grid.ny, w.grid.nx), dtype=torch.float32, device=dev),
+           "ray_bounces": torch.empty(nd, dtype=torch.int64, device=dev)}
+    log("bench: %s, %d triangles, %d rays, depth %d, BVH %d nodes (build %.1f ms)" % (
+        name, w.scene.nt, w.num_rays, w.max_depth, info["bvh_nodes"], info["build_ms"]))
+    for _ in range(warmup):
+        rt.coverage_map(ctx, scene, p, tx, w.grid, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    check(lib.rt_profile_enable(ctx.h, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record(stream)
+    for i in range(steps):
+        rt.coverage_map(ctx, scene, p, tx, w.grid, out=out)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    check(lib.rt_profile_enable(ctx.h, 0))
+    launches = (ctypes.c_int64 * nd)()
+    kms = (ctypes.c_double * nd)()
+    check(lib.rt_profile_read(ctx.h, nd, launches, kms))
+    ms_step = (t1 - t0) * 1e3 / steps
+    step_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+    rb_depth = out["ray_bounces"].cpu().numpy().astype(np.int64)
+    ray_bounces = int(rb_depth.sum())
+    value = ray_bounces / (ms_step / 1e3) / 1e6
+    log("bench: %s %.3f ms/step (median event %.3f), %d ray-bounces/step -> %.1f M ray-bounces/s" % (
+        name, ms_step, statistics.median(step_ms), ray_bounces, value))
+
+    # work counters: one extra, untimed map with per-ray counters
+    work = torch.zeros(4 * nd, dtype=torch.int64, device=dev)
+    g2 = torch.empty_like(out["gain"])
+    h2 = torch.empty_like(out["hits"])
+    pc, tc, rc, gc = p.c(), rt.rt.device_struct(tx), rt.rt.device_struct(w.rx_ant), rt.rt.grid_struct(w.grid)
+    ctx._bind_stream()
+    check(lib.rt_coverage_work(ctx.h, scene.h, ctypes.byref(pc), ctypes.byref(tc), ctypes.byref(rc),
+                               ctypes.byref(gc), ctypes.c_void_p(g2.data_ptr()), ctypes.c_void_p(h2.data_ptr()),
+                               ctypes.c_void_p(work.data_ptr())))
+    wk = work.cpu().numpy().reshape(4, nd).astype(np.float64)
+    assert np.array_equal(wk[0].astype(np.int64), rb_depth), (wk[0], rb_depth)
+    rays, nodes, boxes, tris = wk
+    flops_depth = FLOP_BOX * boxes + FLOP_TRI * tris + FLOP_RAY_BOUNCE * rays
+    launches = np.asarray(list(launches), dtype=np.float64) / steps   # per step, per depth
+    kms = np.asarray(list(kms)) / steps                               # ms per step, per depth
+    kinds = {"first": [0], "bounce": list(range(1, nd))}
+    per_kind = {}
+    for kind, ds in kinds.items():
+        if not ds:
+            continue
+        ms = float(kms[ds].sum())
+        nl = float(launches[ds].sum())
+        fl = float(flops_depth[ds].sum())
+        per_kind[kind] = {"ms_per_step": round(ms, 4), "launches_per_step": int(round(nl)),
+                          "avg_launch_ms": round(ms / nl, 5), "flop_per_step": fl,
+                          "flop_per_launch": fl / nl,
+                          "achieved_tflops": round(fl / (ms / 1e3) / 1e12, 3),
+                          "frac": round(fl / (ms / 1e3) / 1e12 / PEAK_ALU_TFLOPS, 4)}
+    dom = max(per_kind, key=lambda k: per_kind[k]["ms_per_step"])
+    d = per_kind[dom]
+    kernel_ms_total = float(kms.sum())
+    achieved_all = float(flops_depth.sum()) / (kernel_ms_total / 1e3) / 1e12
+    roofline = {
+        "bound": "alu",
+        "achieved": d["achieved_tflops"],
+        "peak": PEAK_ALU_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": d["frac"],
+        "traffic": traffic_per_launch(name, dom),
+        "kernel": KERNEL_KIND[dom],
+        "kernel_share_of_step": round(d["ms_per_step"] / kernel_ms_total, 3),
+        "avg_launch_ms": d["avg_launch_ms"],
+        "flop_per_launch": d["flop_per_launch"],
+        "per_unit_flop": {"box_test": FLOP_BOX, "triangle_test": FLOP_TRI, "ray_bounce": FLOP_RAY_BOUNCE},
+        "kernels": per_kind,
+        "all_launches": {"kernel_ms_per_step": round(kernel_ms_total, 4), "achieved": round(achieved_all, 3),
+                         "frac": round(achieved_all / PEAK_ALU_TFLOPS, 4),
+                         "kernel_ms_per_depth": [round(float(x), 4) for x in kms]},
+        "node_visits_per_ray_bounce": round(float(nodes.sum() / rays.sum()), 3),
+        "box_tests_per_ray_bounce": round(float(boxes.sum() / rays.sum()), 3),
+        "tri_tests_per_ray_bounce": round(float(tris.sum() / rays.sum()), 3),
+        "flop_per_ray_bounce": round(float(flops_depth.sum() / rays.sum()), 1),
+        "rays_per_depth": [int(x) for x in rays],
+        "node_visits_per_depth": [int(x) for x in nodes],
+        "box_tests_per_depth": [int(x) for x in boxes],
+        "tri_tests_per_depth": [int(x) for x in tris],
+    }
+    log("bench: %s dominant kernel %s: %.4f ms/launch, %.2f TFLOP/s (%.1f%% of %.1f); all launches %.3f ms/step, "
+        "%.2f TFLOP/s" % (name, dom, d["avg_launch_ms"], d["achieved_tflops"], 100 * d["frac"], PEAK_ALU_TFLOPS,
+                          kernel_ms_total, achieved_all))
+    res = {"value": value, "ms_per_step": ms_step, "coverage_map_ms_median": statistics.median(step_ms),
+           "coverage_map_ms_events": [round(x, 4) for x in step_ms],
+           "ray_bounces_per_step": ray_bounces, "roofline": roofline,
+           "bvh_nodes": info["bvh_nodes"], "bvh_build_ms": round(info["build_ms"], 1),
+           "scene_create_s": round(scene_s, 2)}
+    return res, scene
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-urban", action="store_true", help="skip the urban-canyon secondary measurement")
     ap.add_argument("--no-extras", action="store_true", help="skip the paths/gradient side measurements")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate measurement")
     ap.add_argument("--surrogate-steps", type=int, default=20000)
@@ -142,108 +262,19 @@ def main():
               "MI355X (rays would shard by lattice range, maps reduce with one all-reduce); got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import ctypes
-
-    import numpy as np
     import torch
 
     import paper_2303_11103_amd as rt
-    from paper_2303_11103_amd._lib import check, lib
     import scenegen as sg
 
-    dev = torch.device("cuda", 0)
-    w = sg.urban_workload()
     ctx = rt.Context(0)
-    scene = rt.Scene.from_scenegen(ctx, w.scene)
-    info = scene.info()
-    p = rt.TraceParams(w.scene.freq_hz, w.max_depth, w.num_rays)
-    tx = w.tx[0]
-    out = {"gain": torch.empty((w.grid.ny, w.grid.nx), dtype=torch.float32, device=dev),
-           "hits": torch.empty((w.grid.ny, w.grid.nx), dtype=torch.int32, device=dev),
-           "gain_db": torch.empty((w.grid.ny, w.grid.nx), dtype=torch.float32, device=dev),
-           "ray_bounces": torch.empty(w.max_depth + 1, dtype=torch.int64, device=dev)}
-    log("bench: urban canyon, %d rays, depth %d, BVH %d nodes (build %.1f ms)" % (
-        w.num_rays, w.max_depth, info["bvh_nodes"], info["build_ms"]))
-    for _ in range(args.warmup):
-        rt.coverage_map(ctx, scene, p, tx, w.grid, out=out)
-    torch.cuda.synchronize()
-    log("bench: warmup done")
-
-    nd = w.max_depth + 1
-    check(lib.rt_profile_enable(ctx.h, 1))
-    stream = torch.cuda.current_stream(dev)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        rt.coverage_map(ctx, scene, p, tx, w.grid, out=out)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    check(lib.rt_profile_enable(ctx.h, 0))
-    launches = (ctypes.c_int64 * nd)()
-    kms = (ctypes.c_double * nd)()
-    check(lib.rt_profile_read(ctx.h, nd, launches, kms))
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    ms_step_ev = ev0.elapsed_time(ev1) / args.steps
-    rb_depth = out["ray_bounces"].cpu().numpy().astype(np.int64)
-    ray_bounces = int(rb_depth.sum())
-    value = ray_bounces / (ms_step / 1e3) / 1e6
-    log("bench: %.3f ms/step (events %.3f), %d ray-bounces/step -> %.1f M ray-bounces/s" % (
-        ms_step, ms_step_ev, ray_bounces, value))
-
-    # work counters (one extra, untimed run with per-ray counters)
-    work = torch.zeros(3 * nd, dtype=torch.int64, device=dev)
-    g2 = torch.empty_like(out["gain"])
-    h2 = torch.empty_like(out["hits"])
-    pc, tc, rc, gc = p.c(), rt.rt.device_struct(tx), rt.rt.device_struct(w.rx_ant), rt.rt.grid_struct(w.grid)
-    ctx._bind_stream()
-    check(lib.rt_coverage_work(ctx.h, scene.h, ctypes.byref(pc), ctypes.byref(tc), ctypes.byref(rc),
-                               ctypes.byref(gc), ctypes.c_void_p(g2.data_ptr()), ctypes.c_void_p(h2.data_ptr()),
-                               ctypes.c_void_p(work.data_ptr())))
-    wk = work.cpu().numpy().reshape(3, nd)
-    assert np.array_equal(wk[0], rb_depth), (wk[0], rb_depth)
-    survivors = np.append(wk[0][1:], 0)
-    flops_depth = FLOP_NODE * wk[1] + FLOP_TRI * wk[2] + FLOP_DEPOSIT * wk[0] + FLOP_REFLECT * survivors
-    flops_depth[0] += FLOP_RAYGEN * wk[0][0]
-    k_ms = np.asarray(list(kms)) / np.maximum(1, np.asarray(list(launches)))  # per launch, per depth
-    per_step_kernel_ms = float(k_ms.sum())
-    achieved_all = flops_depth.sum() / (per_step_kernel_ms / 1e3) / 1e12
-    # dominant kernel: the depth-0 launch (sbr_bounce<1, true>: ray generation,
-    # first closest hit, deposit, reflection), the longest single launch of a step
-    dom = int(np.argmax(k_ms))
-    achieved = flops_depth[0] / (k_ms[0] / 1e3) / 1e12
-    roofline = {
-        "bound": "alu",
-        "achieved": round(float(achieved), 3),
-        "peak": PEAK_ALU_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(float(achieved / PEAK_ALU_TFLOPS), 4),
-        "traffic": traffic_per_launch(),
-        "kernel": "sbr_bounce<coverage, first bounce> (depth-0 launch: %d rays)" % int(wk[0][0]),
-        "kernel_ms": round(float(k_ms[0]), 4),
-        "flop_per_launch": float(flops_depth[0]),
-        "traversal_lane_op_frac": round(float((LANE_NODE * wk[1][0] + LANE_TRI * wk[2][0]) / (k_ms[0] / 1e3)
-                                              / PEAK_LANE_OPS), 4),
-        "longest_launch": "depth %d, %.3f ms" % (dom, float(k_ms[dom])),
-        "all_launches": {"kernel_ms_per_depth": [round(float(x), 4) for x in k_ms],
-                         "achieved": round(float(achieved_all), 3),
-                         "frac": round(float(achieved_all / PEAK_ALU_TFLOPS), 4)},
-        "node_visits_per_ray_bounce": round(float(wk[1].sum() / wk[0].sum()), 2),
-        "tri_tests_per_ray_bounce": round(float(wk[2].sum() / wk[0].sum()), 2),
-        "flop_per_ray_bounce": round(float(flops_depth.sum() / wk[0].sum()), 1),
-        "rays_per_depth": [int(x) for x in wk[0]],
-        "node_visits_per_depth": [int(x) for x in wk[1]],
-        "tri_tests_per_depth": [int(x) for x in wk[2]],
-    }
-    log("bench: depth-0 launch %.4f ms, %.2f TFLOP/s algorithmic (%.1f%% of %.1f); all launches %.3f ms/step, "
-        "%.2f TFLOP/s" % (k_ms[0], achieved, 100 * achieved / PEAK_ALU_TFLOPS, PEAK_ALU_TFLOPS,
-                          per_step_kernel_ms, achieved_all))
+    c = sg.city_workload()
+    city, city_scene = coverage_bench(rt, ctx, torch, c, "city", args.steps, args.warmup)
+    city_scene.close()
     if args.copy_probe:
         # a plain device copy of known size: the HBM counters of the profile runs
         # are scaled by what they read for it
-        src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev)
+        src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=ctx.torch_device)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
@@ -252,25 +283,42 @@ def main():
 
     result = {
         "metric": BJ_METRIC,
-        "value": round(value, 2),
+        "value": round(city["value"], 2),
         "unit": "M ray-bounces/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(city["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64 geometry + f32 field",
         "data": "synthetic",
-        "config": {"workload": "urban canyon coverage map: 8x8 boxes (770 tris), 1e7 rays, depth 3, "
-                               "400x400 cells of 1 m, 3.5 GHz",
-                   "num_rays": w.num_rays, "max_depth": w.max_depth, "grid": [w.grid.ny, w.grid.nx],
-                   "triangles": int(w.scene.nt)},
-        "coverage_map_ms": round(ms_step, 4),
-        "ray_bounces_per_step": ray_bounces,
-        "roofline": roofline,
+        "config": {"workload": "large procedural city coverage map: 50x50 blocks of extruded convex polygons "
+                               "(%d tris, 3 materials), TR 38.901 tx, 1e8 rays, depth 5, 2000x2000 cells of 1 m, "
+                               "28 GHz" % c.scene.nt,
+                   "num_rays": c.num_rays, "max_depth": c.max_depth, "grid": [c.grid.ny, c.grid.nx],
+                   "triangles": int(c.scene.nt)},
+        "coverage_map_ms": round(city["coverage_map_ms_median"], 4),
+        "coverage_map_ms_events": city["coverage_map_ms_events"],
+        "ray_bounces_per_step": city["ray_bounces_per_step"],
+        "bvh": {"nodes": city["bvh_nodes"], "build_ms": city["bvh_build_ms"],
+                "scene_create_s": city["scene_create_s"]},
+        "roofline": city["roofline"],
     }
+
+    w = sg.urban_workload()
+    if not args.no_urban:
+        urban, scene = coverage_bench(rt, ctx, torch, w, "urban", 2 * args.steps, args.warmup)
+        result["urban"] = {"workload": "urban canyon coverage map: 8x8 boxes (770 tris), 1e7 rays, depth 3, "
+                                       "400x400 cells of 1 m, 3.5 GHz",
+                           "M_ray_bounces_per_s": round(urban["value"], 2),
+                           "coverage_map_ms": round(urban["coverage_map_ms_median"], 4),
+                           "ms_per_step": round(urban["ms_per_step"], 4),
+                           "ray_bounces_per_step": urban["ray_bounces_per_step"],
+                           "roofline": urban["roofline"]}
+    else:
+        scene = rt.Scene.from_scenegen(ctx, w.scene)
 
     if not args.no_extras:
         try:
@@ -288,9 +336,10 @@ def main():
             result["surrogate_error"] = repr(e)
 
     if not args.no_cpu_baseline:
-        log("bench: timing the FP64 oracle on a ray sample ...")
-        cb = cpu_baseline()
-        cb["vs_gpu"] = round(value / cb["value"], 1)
+        log("bench: timing the FP64 oracle on a lattice sample of the city ...")
+        cb = cpu_baseline(c, "large city")
+        cb["full_map_s_extrapolated"] = round(city["ray_bounces_per_step"] / (cb["value"] * 1e6), 1)
+        cb["vs_gpu"] = round(city["value"] / cb["value"], 1)
         result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)
 
@@ -385,32 +434,11 @@ def extras(rt, ctx, scene, w, torch):
                          "M_ray_bounces_per_s": round(rbs / (ms / 1e3) / 1e6, 1)}
     log("bench: scattering %s" % res["scattering"])
     ss.close()
-    # large procedural city: coverage map at full size
+    # large procedural city: paths to the 4096 street receivers
     c = sg.city_workload()
-    t0 = time.perf_counter()
     sc = rt.Scene.from_scenegen(ctx, c.scene)
-    scene_s = time.perf_counter() - t0
-    pc = rt.TraceParams(c.scene.freq_hz, c.max_depth, c.num_rays)
-    dev = ctx.torch_device
-    outc = {"gain": torch.empty((c.grid.ny, c.grid.nx), dtype=torch.float32, device=dev),
-            "hits": torch.empty((c.grid.ny, c.grid.nx), dtype=torch.int32, device=dev),
-            "gain_db": torch.empty((c.grid.ny, c.grid.nx), dtype=torch.float32, device=dev),
-            "ray_bounces": torch.empty(c.max_depth + 1, dtype=torch.int64, device=dev)}
-    rt.coverage_map(ctx, sc, pc, c.tx[0], c.grid, out=outc)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(2):
-        rt.coverage_map(ctx, sc, pc, c.tx[0], c.grid, out=outc)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / 2
-    rbc = int(outc["ray_bounces"].sum())
-    info = sc.info()
-    res["city"] = {"workload": "large city coverage map: 50x50 blocks (%d tris), 1e8 rays, depth 5, 2000x2000 "
-                               "cells of 1 m, 28 GHz, TR 38.901 tx" % info["num_triangles"],
-                   "coverage_map_ms": round(ms, 3), "ray_bounces": rbc,
-                   "M_ray_bounces_per_s": round(rbc / (ms / 1e3) / 1e6, 1),
-                   "bvh_nodes": info["bvh_nodes"], "bvh_build_ms": round(info["build_ms"], 1),
-                   "scene_create_s": round(scene_s, 2)}
+    res["city"] = {"workload": "large city paths: %d street receivers, 1e8 rays, depth 5, reception spheres "
+                               "(kappa 2)" % len(c.rx)}
     # paths to the 4096 street receivers with reception-sphere candidates
     pp = rt.TraceParams(c.scene.freq_hz, c.max_depth, c.num_rays, max_paths_per_rx=256, cand_mode=1,
                         sphere_kappa=2.0)

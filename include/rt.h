@@ -214,8 +214,10 @@ rt_status rt_coverage_maps(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* 
                            const rt_device* rx_ant, const rt_grid* grid, float* gain, uint32_t* hits, float* gain_db);
 
 /* rt_coverage_map that also counts, per depth k, the traced rays, the BVH
- * inner nodes visited and the triangles tested:
- *   work [3][max_depth+1] (dev) uint64 (rays, node visits, triangle tests).
+ * inner nodes visited, the child boxes tested at those nodes (the node's
+ * non-empty slots) and the triangles tested:
+ *   work [4][max_depth+1] (dev) uint64 (rays, node visits, box tests,
+ *   triangle tests).
  * The counters add atomics per ray; meant for measuring the work per
  * ray-bounce, not for production runs. */
 rt_status rt_coverage_work(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p, const rt_device* tx,

@@ -7,6 +7,11 @@ recomputed, not stored).
 Parameters theta (float64, 2*nm + 5): (eps_r, sigma) of every material, then
 the transmitter's x, y, z, yaw, pitch.  The paper learns materials (Sec.
 III-A) and transmitter orientation (Sec. III-B) from gradients of this kind.
+
+Every Function sets the materials of its theta only for the duration of its
+own launches: the forward leaves the scene's table as it found it, and the
+backward sets the table its forward used, so several forwards before one
+backward each differentiate at their own theta.
 """
 from __future__ import annotations
 
@@ -24,22 +29,24 @@ class ReceivedPower(torch.autograd.Function):
     def forward(fctx, theta, ctx, scene, params, tx, rxs):
         th = theta.detach().to("cpu", torch.float64).numpy()
         nm = scene.nm
-        scene.set_materials(th[:2 * nm].reshape(nm, 2))
+        mats = th[:2 * nm].reshape(nm, 2).copy()
         dev = SimpleNamespace(pos=tuple(float(x) for x in th[2 * nm:2 * nm + 3]), yaw=float(th[2 * nm + 3]),
                               pitch=float(th[2 * nm + 4]), roll=float(tx.roll), pattern=int(tx.pattern),
                               pol=int(getattr(tx, "pol", 0)))
-        paths = rt.compute_paths(ctx, scene, params, [dev], rxs)
-        power = rt.paths_power(ctx, paths)[0]
+        with scene.materials_set_to(mats):
+            paths = rt.compute_paths(ctx, scene, params, [dev], rxs)
+            power = rt.paths_power(ctx, paths)[0]
         fctx.save_for_backward(paths["depth"][0].clone(), paths["faces"][0].clone())
-        fctx.rt = (ctx, scene, params, dev, rxs)
+        fctx.rt = (ctx, scene, params, dev, rxs, mats)
         return power
 
     @staticmethod
     def backward(fctx, grad_power):
         depth, faces = fctx.saved_tensors
-        ctx, scene, params, dev, rxs = fctx.rt
-        g = rt.paths_power_grad(ctx, scene, params, dev, rxs, depth, faces,
-                                grad_power.contiguous().to(torch.float64))
+        ctx, scene, params, dev, rxs, mats = fctx.rt
+        with scene.materials_set_to(mats):
+            g = rt.paths_power_grad(ctx, scene, params, dev, rxs, depth, faces,
+                                    grad_power.contiguous().to(torch.float64))
         return g, None, None, None, None, None
 
 
@@ -59,12 +66,12 @@ class CoverageRegionGain(torch.autograd.Function):
     def forward(fctx, theta, ctx, scene, params, tx, grid, region, rx_ant):
         th = theta.detach().to("cpu", torch.float64).numpy()
         nm = scene.nm
-        scene.set_materials(th[:2 * nm].reshape(nm, 2))
         dev = SimpleNamespace(pos=tuple(float(x) for x in tx.pos), yaw=float(th[2 * nm]), pitch=float(th[2 * nm + 1]),
                               roll=float(tx.roll), pattern=int(tx.pattern),
                               pol=int(getattr(tx, "pol", 0)))
-        hit_tri, hit_t = rt.trace_record(ctx, scene, params, dev)
-        out = rt.coverage_grad(ctx, scene, params, dev, grid, hit_tri, hit_t, region=region, rx_ant=rx_ant)
+        with scene.materials_set_to(th[:2 * nm].reshape(nm, 2)):
+            hit_tri, hit_t = rt.trace_record(ctx, scene, params, dev)
+            out = rt.coverage_grad(ctx, scene, params, dev, grid, hit_tri, hit_t, region=region, rx_ant=rx_ant)
         fctx.save_for_backward(out[1:].clone())
         return out[0].clone()
 
@@ -92,17 +99,19 @@ class ChannelFrequencyResponse(torch.autograd.Function):
     @staticmethod
     def forward(fctx, theta, ctx, scene, params, tx, rxs, cfr_kw):
         nm = scene.nm
-        scene.set_materials(theta.detach().to("cpu", torch.float64).numpy().reshape(nm, 2))
-        paths = rt.compute_paths(ctx, scene, params, [tx], rxs)
-        H = rt.paths_cfr(ctx, paths, params.freq_hz, **cfr_kw)
-        fctx.rt = (ctx, scene, params, tx, rxs, cfr_kw, paths)
+        mats = theta.detach().to("cpu", torch.float64).numpy().reshape(nm, 2).copy()
+        with scene.materials_set_to(mats):
+            paths = rt.compute_paths(ctx, scene, params, [tx], rxs)
+            H = rt.paths_cfr(ctx, paths, params.freq_hz, **cfr_kw)
+        fctx.rt = (ctx, scene, params, tx, rxs, cfr_kw, paths, mats)
         return H[0]
 
     @staticmethod
     def backward(fctx, G):
-        ctx, scene, params, tx, rxs, cfr_kw, paths = fctx.rt
+        ctx, scene, params, tx, rxs, cfr_kw, paths, mats = fctx.rt
         g = rt.paths_cfr_adjoint(ctx, paths, G[None], params.freq_hz, **cfr_kw)
-        grad = rt.paths_coef_grad(ctx, scene, params, tx, rxs, paths["depth"][0], paths["faces"][0], g[0])
+        with scene.materials_set_to(mats):
+            grad = rt.paths_coef_grad(ctx, scene, params, tx, rxs, paths["depth"][0], paths["faces"][0], g[0])
         return grad[:2 * scene.nm], None, None, None, None, None, None
 
 

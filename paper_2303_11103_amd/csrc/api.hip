@@ -323,7 +323,7 @@ rt_status rt_destroy(rt_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (DevBuf* b : {&c->queue[0], &c->queue[1], &c->counters, &c->table, &c->cands, &c->rx, &c->rx_ant, &c->paths,
-                      &c->pairs, &c->pair_rx, &c->rgrid})
+                      &c->pairs, &c->pair_rx, &c->rgrid, &c->chan})
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
@@ -430,7 +430,7 @@ rt_status rt_scene_face_ids(const rt_scene* s, int32_t* ids) {
 rt_status rt_scene_destroy(rt_scene* s) {
     if (!s) return RT_OK;
     if (s->ctx) (void)hipSetDevice(s->ctx->device);
-    for (DevBuf* b : {&s->nodes, &s->tris, &s->shades, &s->faces, &s->face_tris})
+    for (DevBuf* b : {&s->nodes, &s->tris, &s->shades, &s->faces, &s->face_tris, &s->leaf_of_input})
         if (b->p) (void)hipFree(b->p);
     delete s;
     return RT_OK;
@@ -478,7 +478,7 @@ rt_status coverage_impl(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const 
     RT_HIP(hipMemsetAsync(gain, 0, (size_t)cells * sizeof(float), c->stream));
     RT_HIP(hipMemsetAsync(hits, 0, (size_t)cells * sizeof(uint32_t), c->stream));
     if (ray_bounces) RT_HIP(hipMemsetAsync(ray_bounces, 0, (size_t)(p->max_depth + 1) * sizeof(uint64_t), c->stream));
-    if (work) RT_HIP(hipMemsetAsync(work, 0, (size_t)3 * (p->max_depth + 1) * sizeof(uint64_t), c->stream));
+    if (work) RT_HIP(hipMemsetAsync(work, 0, (size_t)4 * (p->max_depth + 1) * sizeof(uint64_t), c->stream));
     st = run_sbr(c, s, p, tx, rx_ant, g, work ? (rt::kModeCoverage | rt::kModeStats) : rt::kModeCoverage, gain, hits,
                  ray_bounces, nullptr, nullptr, nullptr, 0, nullptr, work);
     if (st != RT_OK) return st;
@@ -588,8 +588,12 @@ rt_status rt_compute_paths(rt_ctx* c, rt_scene* s, const rt_trace_params* p, con
         for (int k = 0; k < 3; ++k) rxp[3 * i + k] = rx[i].pos[k];
         rxa[i] = make_antenna(rx + i);
     }
-    RT_HIP(hipMemcpy(c->rx.p, rxp.data(), rxp.size() * sizeof(double), hipMemcpyHostToDevice));
-    RT_HIP(hipMemcpy(c->rx_ant.p, rxa.data(), rxa.size() * sizeof(rt::Antenna), hipMemcpyHostToDevice));
+    // staged on the context's stream: kernels still queued there (a gradient of
+    // the previous call) read these buffers
+    RT_HIP(hipMemcpyAsync(c->rx.p, rxp.data(), rxp.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    RT_HIP(hipMemcpyAsync(c->rx_ant.p, rxa.data(), rxa.size() * sizeof(rt::Antenna), hipMemcpyHostToDevice,
+                          c->stream));
+    RT_HIP(hipStreamSynchronize(c->stream));  // host staging vectors go out of scope
     rt::SbrArgs sph{};
     if (sphere) {
         // every accepted pair has a path length below (max_depth + 1) times the
@@ -656,10 +660,12 @@ rt_status rt_compute_paths(rt_ctx* c, rt_scene* s, const rt_trace_params* p, con
             }
         }
         RT_HIP(ensure(c->rgrid, (start.size() + items.size()) * sizeof(int32_t)));
-        RT_HIP(hipMemcpy(c->rgrid.p, start.data(), start.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        RT_HIP(hipMemcpyAsync(c->rgrid.p, start.data(), start.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                              c->stream));
         if (!items.empty())
-            RT_HIP(hipMemcpy((int32_t*)c->rgrid.p + start.size(), items.data(), items.size() * sizeof(int32_t),
-                             hipMemcpyHostToDevice));
+            RT_HIP(hipMemcpyAsync((int32_t*)c->rgrid.p + start.size(), items.data(), items.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, c->stream));
+        RT_HIP(hipStreamSynchronize(c->stream));
         sph.rx = (const double*)c->rx.p;
         sph.cell_start = (const int32_t*)c->rgrid.p;
         sph.cell_rx = (const int32_t*)c->rgrid.p + start.size();

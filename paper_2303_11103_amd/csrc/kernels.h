@@ -67,7 +67,7 @@ struct SbrArgs {
     uint32_t* out_count;        // [kQueueRegions]
     int64_t region_cap;
     uint64_t* stats;    // [max_depth + 1] traced rays per depth (nullable)
-    uint64_t* work;     // stats mode: [3][max_depth + 1] rays, inner-node visits, triangle tests
+    uint64_t* work;     // stats mode: [4][max_depth + 1] rays, inner-node visits, child-box tests, triangle tests
     // record mode
     int32_t* rec_tri;
     double* rec_t;

@@ -7,7 +7,7 @@
 //   bounce 0 generates rays in coherence order and traces them;
 //   bounce k > 0 reads the compacted queue of rays that survived bounce k-1.
 // Each launch runs a persistent, wave-strided loop.  Per ray: closest hit
-// (fp32 conservative slab tests on a binary BVH with a per-lane LDS stack,
+// (fp32 conservative slab tests on a 4-wide BVH with a per-lane LDS stack,
 // fp64 Moller-Trumbore on triangles), coverage deposit of the segment, then
 // Fresnel reflection of the field and a wave-ballot compaction into the next
 // queue (one atomic per wave).
@@ -302,7 +302,8 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
                 const int nd = a.max_depth + 1;
                 atomicAdd((unsigned long long*)&a.work[a.depth], 1ull);
                 atomicAdd((unsigned long long*)&a.work[nd + a.depth], (unsigned long long)ts.nodes);
-                atomicAdd((unsigned long long*)&a.work[2 * nd + a.depth], (unsigned long long)ts.tris);
+                atomicAdd((unsigned long long*)&a.work[2 * nd + a.depth], (unsigned long long)ts.boxes);
+                atomicAdd((unsigned long long*)&a.work[3 * nd + a.depth], (unsigned long long)ts.tris);
             }
             if ((MODE & kModeSphere) && a.depth >= 1) sphere_pairs(a, st, o, d, tbest);
             if (MODE & kModeRecord) {

@@ -70,8 +70,14 @@ __device__ __forceinline__ bool tri_test(const Tri* __restrict__ tris, int k, d3
 // Work counters of one traversal (inner nodes visited, triangles tested).
 struct TravStats {
     uint32_t nodes = 0;
+    uint32_t boxes = 0;  // child boxes of the visited nodes (empty slots not counted)
     uint32_t tris = 0;
 };
+
+__device__ __forceinline__ uint32_t live_children(int4 ch) {
+    return (uint32_t)(ch.x != kEmptyChild) + (uint32_t)(ch.y != kEmptyChild) + (uint32_t)(ch.z != kEmptyChild) +
+           (uint32_t)(ch.w != kEmptyChild);
+}
 
 // Copies the first min(num_nodes, kLdsNodes) nodes into LDS (whole block).
 __device__ __forceinline__ int stage_nodes(const DevScene& sc, Node* lds) {
@@ -145,6 +151,7 @@ __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_node
                     X0 = np[0]; X1 = np[1]; Y0 = np[2]; Y1 = np[3]; Z0 = np[4]; Z1 = np[5];
                     ch = reinterpret_cast<const int4*>(np)[6];
                 }
+                if (STATS) ts->boxes += live_children(ch);
                 const float k0 = slab(X0.x, X1.x, Y0.x, Y1.x, Z0.x, Z1.x, ix, iy, iz, oix, oiy, oiz, tfar);
                 const float k1 = slab(X0.y, X1.y, Y0.y, Y1.y, Z0.y, Z1.y, ix, iy, iz, oix, oiy, oiz, tfar);
                 const float k2 = slab(X0.z, X1.z, Y0.z, Y1.z, Z0.z, Z1.z, ix, iy, iz, oix, oiy, oiz, tfar);
@@ -235,6 +242,7 @@ __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_node
                 X0 = np[0]; X1 = np[1]; Y0 = np[2]; Y1 = np[3]; Z0 = np[4]; Z1 = np[5];
                 ch = reinterpret_cast<const int4*>(np)[6];
             }
+            if (STATS) ts->boxes += live_children(ch);
             float k0 = slab(X0.x, X1.x, Y0.x, Y1.x, Z0.x, Z1.x, ix, iy, iz, oix, oiy, oiz, tfar);
             float k1 = slab(X0.y, X1.y, Y0.y, Y1.y, Z0.y, Z1.y, ix, iy, iz, oix, oiy, oiz, tfar);
             float k2 = slab(X0.z, X1.z, Y0.z, Y1.z, Z0.z, Z1.z, ix, iy, iz, oix, oiy, oiz, tfar);

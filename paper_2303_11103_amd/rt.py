@@ -6,6 +6,7 @@ torch's current stream for that device.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 from dataclasses import dataclass
 
@@ -100,6 +101,7 @@ class Scene:
         self.h = h
         self.nt = int(F.shape[0])
         self.nm = len(mats)
+        self.materials = mats.copy()   # the table the library holds (float32 [nm][2])
 
     @classmethod
     def from_scenegen(cls, ctx, s):
@@ -115,6 +117,19 @@ class Scene:
         mats = np.ascontiguousarray(materials, dtype=np.float32).reshape(-1, 2)
         marr = (L.rt_material * len(mats))(*[L.rt_material(float(e), float(s)) for e, s in mats])
         check(lib.rt_scene_set_materials(self.h, marr, len(mats)))
+        self.materials = mats.copy()
+
+    @contextlib.contextmanager
+    def materials_set_to(self, materials):
+        """Within the block the scene holds ``materials``; the previous table
+        is restored on exit.  Launches take the table by value, so kernels
+        enqueued inside the block keep it."""
+        prev = self.materials.copy()
+        self.set_materials(materials)
+        try:
+            yield self
+        finally:
+            self.set_materials(prev)
 
     def info(self) -> dict:
         inf = L.rt_scene_info_t()

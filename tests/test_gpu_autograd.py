@@ -21,6 +21,29 @@ def _theta(w, mats):
                         dtype=torch.float64, device="cuda", requires_grad=True)
 
 
+def _oracle_fd(w, sc, p, mats, used):
+    """Oracle central differences of the mean dB loss at materials ``mats``,
+    over the face sequences the GPU finds for each receiver."""
+    m = lib()
+    with sc.materials_set_to(mats):
+        o = m.compute_paths(ctx(), sc, p, w.tx, w.rx)
+    depth = o["depth"][0].cpu().numpy()
+    faces = o["faces"][0].cpu().numpy()
+    seqs = [[tuple(int(f) for f in faces[r, j, :depth[r, j]]) for j in range(depth.shape[1]) if depth[r, j] >= 0]
+            for r in range(len(w.rx))]
+    g = geom.Geometry(w.scene)
+    g.materials = np.asarray(mats, dtype=np.float32).astype(np.float64)
+    fd, used_o, unstable = ograd.fd_gradient(g, w.tx[0], w.rx, seqs, mask=used)
+    assert not unstable.any()
+    return fd
+
+
+def _assert_close(g_gpu, fd):
+    scale = np.abs(fd)
+    big = scale > 1e-6 * scale.max()
+    assert np.max(np.abs(g_gpu - fd)[big] / scale[big]) < 1e-3, (g_gpu, fd)
+
+
 def test_autograd_loss_gradient_matches_finite_differences():
     lib()
     from paper_2303_11103_amd.autograd import received_power
@@ -33,20 +56,68 @@ def test_autograd_loss_gradient_matches_finite_differences():
     used = P > 0
     L = torch.mean(10 * torch.log10(P[used]))
     L.backward()
-    g_gpu = theta.grad.cpu().numpy()
     # frozen path sets from the GPU forward pass, FD by the oracle over the same receivers
+    _assert_close(theta.grad.cpu().numpy(), _oracle_fd(w, sc, p, w.scene.materials, used.cpu().numpy()))
+
+
+def test_autograd_backward_uses_its_own_forward_materials():
+    """Two forwards at different materials, then the first one's backward: it
+    must differentiate at the first forward's materials, and neither forward
+    may leave the scene's table changed."""
+    lib()
+    from paper_2303_11103_amd.autograd import received_power
+    w = sg.diff_workload(num_rays=100_000)
+    w.rx = w.rx[:40]
+    p = params(w, max_paths_per_rx=64)
+    sc = scene(w.scene)
+    before = sc.materials.copy()
+    m1 = np.asarray(w.scene.materials, dtype=np.float64)
+    m2 = m1 * np.array([[1.7, 3.0], [0.6, 5.0]])
+    th1, th2 = _theta(w, m1), _theta(w, m2)
+    P1 = received_power(th1, ctx(), sc, p, w.tx[0], w.rx)
+    P2 = received_power(th2, ctx(), sc, p, w.tx[0], w.rx)
+    assert np.array_equal(sc.materials, before)
+    used = P1 > 0
+    torch.mean(10 * torch.log10(P1[used])).backward()
+    _assert_close(th1.grad.cpu().numpy(), _oracle_fd(w, sc, p, m1, used.cpu().numpy()))
+    torch.mean(10 * torch.log10(P2[used & (P2 > 0)])).backward()
+    _assert_close(th2.grad.cpu().numpy(), _oracle_fd(w, sc, p, m2, (used & (P2 > 0)).cpu().numpy()))
+    assert np.array_equal(sc.materials, before)
+
+
+def test_paths_and_gradient_on_a_non_default_stream():
+    """Paths, the power gradient and paths to other receivers, enqueued on a
+    second torch stream without waits in between, give the default stream's
+    results (the receivers of the second call are staged on the library's
+    stream, behind the gradient kernel that reads the first ones)."""
     m = lib()
-    o = m.compute_paths(ctx(), sc, p, w.tx, w.rx)
-    depth = o["depth"][0].cpu().numpy()
-    faces = o["faces"][0].cpu().numpy()
-    seqs = [[tuple(int(f) for f in faces[r, j, :depth[r, j]]) for j in range(depth.shape[1]) if depth[r, j] >= 0]
-            for r in range(len(w.rx))]
-    g = geom.Geometry(w.scene)
-    fd, used_o, unstable = ograd.fd_gradient(g, w.tx[0], w.rx, seqs, mask=used.cpu().numpy())
-    assert not unstable.any()
-    scale = np.abs(fd)
-    big = scale > 1e-6 * scale.max()
-    assert np.max(np.abs(g_gpu - fd)[big] / scale[big]) < 1e-3, (g_gpu, fd)
+    w = sg.diff_workload(num_rays=100_000)
+    p = params(w, max_paths_per_rx=64)
+    sc = scene(w.scene)
+    rx_a, rx_b = w.rx[:64], w.rx[64:200]
+
+    def run():
+        o = m.compute_paths(ctx(), sc, p, w.tx, rx_a)
+        dL = torch.ones(len(rx_a), dtype=torch.float64, device="cuda")
+        g = m.paths_power_grad(ctx(), sc, p, w.tx[0], rx_a, o["depth"][0], o["faces"][0], dL)
+        o2 = m.compute_paths(ctx(), sc, p, w.tx, rx_b)
+        g2 = m.paths_power_grad(ctx(), sc, p, w.tx[0], rx_b, o2["depth"][0], o2["faces"][0],
+                                torch.ones(len(rx_b), dtype=torch.float64, device="cuda"))
+        return [t.clone() for t in (o["num_paths"], m.paths_power(ctx(), o), g,
+                                    o2["num_paths"], m.paths_power(ctx(), o2), g2)]
+
+    ref = run()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        got = run()
+    s.synchronize()
+    for k, (r, gt) in enumerate(zip(ref, got)):
+        r, gt = r.cpu().double(), gt.cpu().double()
+        if k % 3 == 0:
+            assert torch.equal(r, gt)       # path counts
+        else:                               # powers and gradients (atomic sums: order may differ)
+            assert torch.allclose(gt, r, rtol=1e-9, atol=1e-12 * float(r.abs().max())), (k, r, gt)
 
 
 def _fit(w, sc, p, start, used, target, train_mask, outer=3):
