@@ -69,6 +69,30 @@ def gelu_grad(x):
     return 0.5 * (1.0 + t) + 0.5 * x * (1.0 - t * t) * du
 
 
+# Map inference (reading R21 of the design notes): GELU is evaluated there as
+# x clamp(1/2 + u Q(u^2), 0, 1) with u = clamp(x / 4, -1, 1) and Q the degree-6
+# least-squares fit below (coefficients of u^0 .. u^12 in powers of u^2).
+GELU_POLY = (1.59098072, -4.1370718, 9.05178404, -13.5802262, 12.9487521, -6.98037448, 1.60618985)
+
+
+def gelu_poly(x):
+    u = np.clip(np.asarray(x, dtype=np.float64) / 4.0, -1.0, 1.0)
+    return x * np.clip(0.5 + u * np.polyval(GELU_POLY[::-1], u * u), 0.0, 1.0)
+
+
+def round_weights_f16(theta):
+    """theta with W1..W4 and w5 rounded to IEEE half precision (round to
+    nearest), the weight format of map inference: layer 1 is stored as W1 / 4
+    and the head as 4 w5 (powers of two, so only the subnormal range differs
+    from rounding W itself); biases stay as they are."""
+    layers = unpack(theta)
+    out = []
+    for li, (W, b) in enumerate(layers):
+        sc = 0.25 if li == 0 else (4.0 if li == len(layers) - 1 else 1.0)
+        out.append((np.asarray(np.float16(sc * W), dtype=np.float64) / sc, b))
+    return np.concatenate([np.concatenate([W.reshape(-1), b.reshape(-1)]) for W, b in out])
+
+
 def features(v, Bf):
     proj = 2.0 * np.pi * (np.asarray(v, dtype=np.float64) @ np.asarray(Bf, dtype=np.float64).T)
     return np.concatenate([np.sin(proj), np.cos(proj)], axis=1)
@@ -82,15 +106,17 @@ def free_space_db(points, freq_hz, rx_z):
     return 20.0 * np.log10(C0 / freq_hz / (4.0 * np.pi * d))
 
 
-def forward(theta, v, Bf, feats=None, prior_db=None):
+def forward(theta, v, Bf, feats=None, prior_db=None, act=gelu):
     """Prediction and the cache for ``backward``; prior_db (per row, e.g. from
-    ``free_space_db``) is added to the head's output."""
+    ``free_space_db``) is added to the head's output; act is the activation
+    (``gelu``, or ``gelu_poly`` for the map-inference reading; ``backward``
+    assumes ``gelu``)."""
     layers = unpack(theta)
     h = features(v, Bf) if feats is None else np.asarray(feats, dtype=np.float64)
     cache = [h]
     for W, b in layers[:-1]:
         z = h @ W.T + b
-        h = gelu(z)
+        h = act(z)
         cache.append((z, h))
     w5, b5 = layers[-1]
     y = h @ w5[0] + b5[0]

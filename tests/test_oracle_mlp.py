@@ -78,9 +78,24 @@ def test_polynomial_gelu_of_map_inference_is_close_to_the_tanh_form():
     """The map-inference kernel evaluates GELU as x clamp(1/2 + u Q(u^2), 0, 1),
     u = clamp(x / 4, -1, 1); in exact arithmetic it stays within 2.5e-4 of the
     tanh form everywhere (coefficients as in the kernel)."""
-    q = [1.59098072, -4.1370718, 9.05178404, -13.5802262, 12.9487521, -6.98037448, 1.60618985]
     x = np.linspace(-12, 12, 48001)
-    u = np.clip(x / 4, -1, 1)
-    phi = np.clip(0.5 + u * np.polyval(q[::-1], u * u), 0, 1)
-    assert np.max(np.abs(x * phi - mlp.gelu(x))) < 2.5e-4 * np.maximum(1.0, np.abs(x)).max()
-    assert np.max(np.abs(x * phi - mlp.gelu(x))[np.abs(x) <= 4]) < 2.5e-4
+    g = mlp.gelu_poly(x)
+    assert np.max(np.abs(g - mlp.gelu(x))) < 2.5e-4 * np.maximum(1.0, np.abs(x)).max()
+    assert np.max(np.abs(g - mlp.gelu(x))[np.abs(x) <= 4]) < 2.5e-4
+    # outside |x| <= 4 it is exactly max(x, 0) (the clamp), as the tanh form is to 1e-3
+    far = np.abs(x) >= 4
+    assert np.array_equal(g[far], np.maximum(x[far], 0.0))
+
+
+def test_half_precision_weights_round_to_nearest_and_keep_biases():
+    theta, *_ = _problem(seed=4)
+    r = mlp.round_weights_f16(theta)
+    L0, L1 = mlp.unpack(theta), mlp.unpack(r)
+    for li, ((W, b), (Wr, br)) in enumerate(zip(L0, L1)):
+        assert np.array_equal(b, br)
+        # each weight moves by at most half a unit in the last place of a half
+        # (10 fraction bits; subnormals below 2^-14 have absolute spacing 2^-24)
+        ulp = np.maximum(2.0 ** (np.floor(np.log2(np.maximum(np.abs(W), 2.0 ** -14))) - 10), 2.0 ** -24)
+        sc = 0.25 if li == 0 else (4.0 if li == 4 else 1.0)
+        assert np.all(np.abs(Wr - W) <= 0.5 * ulp / min(sc, 1.0) + 1e-18)
+        assert np.all(np.float16(sc * Wr) == sc * Wr)
