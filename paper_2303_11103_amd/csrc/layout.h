@@ -10,7 +10,8 @@ namespace rt {
 // coordinates interleaved so that one 16-byte load fetches one bound of all
 // four children (two 64-byte lines):
 //   bx[0] = lo.x, bx[1] = hi.x, bx[2] = lo.y, bx[3] = hi.y, bz[0] = lo.z, bz[1] = hi.z
-// child >= 0: index of an inner node; kEmptyChild: unused slot; other
+// child >= 0: index of an inner node; kEmptyChild: unused slot (its box has
+// lo = +inf and hi = -inf on every axis, so every ray misses it); other
 // negative values: leaf ~((first << 5) | (count - 1)) over the reordered
 // triangle array, count <= 32.
 struct alignas(128) Node {

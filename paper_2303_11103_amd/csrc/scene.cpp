@@ -54,7 +54,9 @@ struct BuildNode {
 
 class Builder {
 public:
-    Builder(std::vector<Prim>& prims) : prims_(prims) {}
+    // depth_bound: the binary tree gets no deeper than this; subtrees that
+    // would exceed it are split at object medians
+    Builder(std::vector<Prim>& prims, int depth_bound) : prims_(prims), bound_(depth_bound) {}
 
     int32_t build(int32_t first, int32_t count, int depth) {
         int32_t id = (int32_t)nodes_.size();
@@ -67,7 +69,7 @@ public:
         nodes_[id].box = b;
         max_depth_ = std::max(max_depth_, depth);
         if (count <= 2) return leaf(id, first, count);
-        int force_median = (depth + (int)std::ceil(std::log2((double)count)) >= kMaxDepth - 1);
+        int force_median = (depth + (int)std::ceil(std::log2((double)count)) >= bound_ - 1);
         int axis = 0;
         double ext[3];
         for (int i = 0; i < 3; ++i) ext[i] = cb.hi[i] - cb.lo[i];
@@ -161,6 +163,7 @@ private:
     }
 
     std::vector<Prim>& prims_;
+    int bound_;
     std::vector<BuildNode> nodes_;
     int max_depth_ = 0;
 };
@@ -280,116 +283,140 @@ int build_scene(const float* V, int64_t nv, const int32_t* F, int64_t nt, const 
     }
     out.num_faces = (int32_t)face_first.size();
 
-    // ---- BVH
-    Builder builder(prims);
-    builder.build(0, (int32_t)nt, 0);
-    auto& bn = builder.nodes();
-    out.depth = builder.max_depth();
-    if (out.depth > kMaxDepth + 1) {
-        err = "BVH build tree deeper than expected";
-        return -1;
-    }
-
-    // reorder triangles by leaf order
-    out.tris.resize(nt);
-    out.shades.resize(nt);
-    std::vector<int32_t> new_of_old(nt);
-    for (int64_t i = 0; i < nt; ++i) {
-        out.tris[i] = tri[prims[i].tri];
-        out.shades[i] = shade[prims[i].tri];
-        new_of_old[prims[i].tri] = (int32_t)i;
-    }
-
-    // Collapse the binary build tree into a 4-wide tree: a node adopts up to
-    // four descendants by repeatedly opening the inner child with the largest
-    // surface area.  Nodes are numbered breadth first, so the first ones are
-    // the top levels, which the kernels stage in LDS.
-    const double p = out.pad;
-    auto set_box = [&](Node& g, int slot, const Box& B) {
-        g.bx[0][slot] = round_down(B.lo[0] - p);
-        g.bx[1][slot] = round_up(B.hi[0] + p);
-        g.bx[2][slot] = round_down(B.lo[1] - p);
-        g.bx[3][slot] = round_up(B.hi[1] + p);
-        g.bz[0][slot] = round_down(B.lo[2] - p);
-        g.bz[1][slot] = round_up(B.hi[2] + p);
-    };
-    auto empty_slot = [&](Node& g, int slot) {
-        g.bx[0][slot] = g.bx[2][slot] = g.bz[0][slot] = INFINITY;
-        g.bx[1][slot] = g.bx[3][slot] = g.bz[1][slot] = -INFINITY;
-        g.child[slot] = kEmptyChild;
-    };
-    auto gather = [&](int32_t b) {
-        std::vector<int32_t> kids;
-        if (bn[b].left < 0) {
-            kids.push_back(b);  // a root leaf becomes the only child of the root
-            return kids;
-        }
-        kids = {bn[b].left, bn[b].right};
-        while (kids.size() < 4) {
-            int best = -1;
-            double area = -1.0;
-            for (int i = 0; i < (int)kids.size(); ++i) {
-                const BuildNode& c = bn[kids[i]];
-                if (c.left >= 0 && c.box.area() > area) {
-                    area = c.box.area();
-                    best = i;
-                }
-            }
-            if (best < 0) break;
-            int32_t open = kids[best];
-            kids.erase(kids.begin() + best);
-            kids.insert(kids.begin() + best, bn[open].right);
-            kids.insert(kids.begin() + best, bn[open].left);
-        }
-        return kids;
-    };
-    {
-        std::vector<int32_t> order = {0};            // build nodes that become GPU nodes, BFS order
-        std::vector<std::vector<int32_t>> kids_of;
-        std::vector<int32_t> gpu_of(bn.size(), -1);
-        gpu_of[0] = 0;
-        for (size_t h = 0; h < order.size(); ++h) {
-            std::vector<int32_t> kids = gather(order[h]);
-            for (int32_t c : kids) {
-                if (bn[c].left >= 0 && c != order[h]) {
-                    gpu_of[c] = (int32_t)order.size();
-                    order.push_back(c);
-                }
-            }
-            kids_of.push_back(kids);
-        }
-        out.nodes.resize(order.size());
-        std::vector<int> need(order.size(), 0);
-        for (size_t h = 0; h < order.size(); ++h) {
-            Node& g = out.nodes[h];
-            std::memset(&g, 0, sizeof(Node));
-            const auto& kids = kids_of[h];
-            for (int slot = 0; slot < 4; ++slot) {
-                if (slot >= (int)kids.size()) {
-                    empty_slot(g, slot);
-                    continue;
-                }
-                const BuildNode& c = bn[kids[slot]];
-                set_box(g, slot, c.box);
-                g.child[slot] = (c.left < 0 || kids[slot] == order[h]) ? make_leaf(c.first, c.count) : gpu_of[kids[slot]];
-            }
-        }
-        // worst-case stack: along any root-to-leaf path, a visit pushes all but one child
-        for (size_t h = order.size(); h-- > 0;) {
-            int deepest = 0, n = 0;
-            for (int slot = 0; slot < 4; ++slot) {
-                int32_t c = out.nodes[h].child[slot];
-                if (c == kEmptyChild) continue;
-                ++n;
-                if (c >= 0) deepest = std::max(deepest, need[c]);
-            }
-            need[h] = (n - 1) + deepest;
-        }
-        out.stack_need = need[0] + 1;
-        if (out.stack_need > kStackEntries + kStackOverflow) {  // 64 entries in all
-            err = "BVH needs a deeper traversal stack than " + std::to_string(kStackEntries + kStackOverflow);
+    // ---- BVH.  The traversal kernels keep kStackEntries stack entries per
+    // lane in LDS and need a slower variant with a private-memory overflow for
+    // deeper trees, so a tree whose worst-case stack need exceeds that is
+    // rebuilt with a tighter depth bound (deep, thin SAH branches become
+    // balanced median splits) while the bound stays above log2(nt) + 2.
+    const std::vector<Prim> prims_in = prims;
+    std::vector<int32_t> new_of_old;
+    const int min_bound = (int)std::ceil(std::log2((double)nt)) + 2;
+    // Attempts: the SAH tree collapsed by opening the child of largest area;
+    // then collapsed by opening the tallest child, which spends the four slots
+    // on the deepest paths; then that with tighter depth bounds.
+    for (int attempt = 0, bound = kMaxDepth;; ++attempt, bound -= attempt >= 2 ? 2 : 0) {
+        const bool by_height = attempt >= 1;
+        prims = prims_in;
+        Builder builder(prims, bound);
+        builder.build(0, (int32_t)nt, 0);
+        auto& bn = builder.nodes();
+        // subtree heights (children follow their parent in build order)
+        std::vector<int> height(bn.size(), 0);
+        for (size_t i = bn.size(); i-- > 0;)
+            if (bn[i].left >= 0) height[i] = 1 + std::max(height[bn[i].left], height[bn[i].right]);
+        out.depth = builder.max_depth();
+        if (out.depth > kMaxDepth + 1) {
+            err = "BVH build tree deeper than expected";
             return -1;
         }
+
+        // reorder triangles by leaf order
+        out.tris.resize(nt);
+        out.shades.resize(nt);
+        new_of_old.assign(nt, 0);
+        for (int64_t i = 0; i < nt; ++i) {
+            out.tris[i] = tri[prims[i].tri];
+            out.shades[i] = shade[prims[i].tri];
+            new_of_old[prims[i].tri] = (int32_t)i;
+        }
+
+        // Collapse the binary build tree into a 4-wide tree: a node adopts up to
+        // four descendants by repeatedly opening the inner child with the largest
+        // surface area.  Nodes are numbered breadth first, so the first ones are
+        // the top levels, which the kernels stage in LDS.
+        const double p = out.pad;
+        auto set_box = [&](Node& g, int slot, const Box& B) {
+            g.bx[0][slot] = round_down(B.lo[0] - p);
+            g.bx[1][slot] = round_up(B.hi[0] + p);
+            g.bx[2][slot] = round_down(B.lo[1] - p);
+            g.bx[3][slot] = round_up(B.hi[1] + p);
+            g.bz[0][slot] = round_down(B.lo[2] - p);
+            g.bz[1][slot] = round_up(B.hi[2] + p);
+        };
+        auto empty_slot = [&](Node& g, int slot) {
+            g.bx[0][slot] = g.bx[2][slot] = g.bz[0][slot] = INFINITY;
+            g.bx[1][slot] = g.bx[3][slot] = g.bz[1][slot] = -INFINITY;
+            g.child[slot] = kEmptyChild;
+        };
+        auto gather = [&](int32_t b) {
+            std::vector<int32_t> kids;
+            if (bn[b].left < 0) {
+                kids.push_back(b);  // a root leaf becomes the only child of the root
+                return kids;
+            }
+            kids = {bn[b].left, bn[b].right};
+            while (kids.size() < 4) {
+                int best = -1;
+                double score = -1.0;
+                for (int i = 0; i < (int)kids.size(); ++i) {
+                    const BuildNode& c = bn[kids[i]];
+                    // by height: the tallest subtree (ties: the largest area)
+                    const double sc = by_height ? height[kids[i]] + c.box.area() / (1.0 + bn[0].box.area())
+                                                : c.box.area();
+                    if (c.left >= 0 && sc > score) {
+                        score = sc;
+                        best = i;
+                    }
+                }
+                if (best < 0) break;
+                int32_t open = kids[best];
+                kids.erase(kids.begin() + best);
+                kids.insert(kids.begin() + best, bn[open].right);
+                kids.insert(kids.begin() + best, bn[open].left);
+            }
+            return kids;
+        };
+        {
+            std::vector<int32_t> order = {0};            // build nodes that become GPU nodes, BFS order
+            std::vector<std::vector<int32_t>> kids_of;
+            std::vector<int32_t> gpu_of(bn.size(), -1);
+            gpu_of[0] = 0;
+            for (size_t h = 0; h < order.size(); ++h) {
+                std::vector<int32_t> kids = gather(order[h]);
+                for (int32_t c : kids) {
+                    if (bn[c].left >= 0 && c != order[h]) {
+                        gpu_of[c] = (int32_t)order.size();
+                        order.push_back(c);
+                    }
+                }
+                kids_of.push_back(kids);
+            }
+            out.nodes.resize(order.size());
+            std::vector<int> need(order.size(), 0);
+            for (size_t h = 0; h < order.size(); ++h) {
+                Node& g = out.nodes[h];
+                std::memset(&g, 0, sizeof(Node));
+                const auto& kids = kids_of[h];
+                for (int slot = 0; slot < 4; ++slot) {
+                    if (slot >= (int)kids.size()) {
+                        empty_slot(g, slot);
+                        continue;
+                    }
+                    const BuildNode& c = bn[kids[slot]];
+                    set_box(g, slot, c.box);
+                    g.child[slot] = (c.left < 0 || kids[slot] == order[h]) ? make_leaf(c.first, c.count) : gpu_of[kids[slot]];
+                }
+            }
+            // worst-case stack: along any root-to-leaf path, a visit pushes all but one child
+            for (size_t h = order.size(); h-- > 0;) {
+                int deepest = 0, n = 0;
+                for (int slot = 0; slot < 4; ++slot) {
+                    int32_t c = out.nodes[h].child[slot];
+                    if (c == kEmptyChild) continue;
+                    ++n;
+                    if (c >= 0) deepest = std::max(deepest, need[c]);
+                }
+                need[h] = (n - 1) + deepest;
+            }
+            out.stack_need = need[0] + 1;
+        }
+        out.depth_bound = bound;
+        out.collapse_by_height = by_height;
+        if (out.stack_need <= kStackEntries || (attempt >= 1 && bound - 2 < min_bound)) break;
+    }
+    if (out.stack_need > kStackEntries + kStackOverflow) {  // 64 entries in all
+        err = "BVH needs a deeper traversal stack than " + std::to_string(kStackEntries + kStackOverflow);
+        return -1;
     }
 
     // ---- faces with their triangles (reordered indices)

@@ -17,6 +17,8 @@ struct HostScene {
     int32_t num_faces = 0;
     int depth = 0;                    // depth of the binary build tree
     int stack_need = 0;               // worst-case traversal stack entries of the 4-wide tree
+    int depth_bound = 0;              // depth bound the accepted binary tree was built with
+    bool collapse_by_height = false;  // 4-wide nodes formed by opening the tallest child (else the largest)
     double max_abs = 0.0;             // largest |coordinate| (at least 64 m)
     double pad = 0.0;                 // bounding-box inflation [m]
     double build_ms = 0.0;

@@ -80,6 +80,10 @@ __device__ __forceinline__ uint32_t live_children(int4 ch) {
 }
 
 // Copies the first min(num_nodes, kLdsNodes) nodes into LDS (whole block).
+// The LDS copy is swizzled: 16-byte slot s of node n is stored at slot
+// s ^ (n & 7).  Lanes of a wave that read the same plane of different nodes
+// then spread over eight groups of LDS banks instead of one (a node is 128
+// bytes, so without the swizzle slot s of every node falls on the same banks).
 __device__ __forceinline__ int stage_nodes(const DevScene& sc, Node* lds) {
     const int n = sc.num_nodes < kLdsNodes ? sc.num_nodes : kLdsNodes;
     const float4* src = reinterpret_cast<const float4*>(sc.nodes);
@@ -89,26 +93,57 @@ __device__ __forceinline__ int stage_nodes(const DevScene& sc, Node* lds) {
     return n;
 }
 
-// Slab test of one child box: entry distance (or +inf when missed).
-__device__ __forceinline__ float slab(float lx, float hx, float ly, float hy, float lz, float hz, float ix, float iy,
-                                      float iz, float oix, float oiy, float oiz, float tfar) {
-    const float a0 = fmaf(lx, ix, -oix), a1 = fmaf(hx, ix, -oix);
-    const float b0 = fmaf(ly, iy, -oiy), b1 = fmaf(hy, iy, -oiy);
-    const float c0 = fmaf(lz, iz, -oiz), c1 = fmaf(hz, iz, -oiz);
-    const float n = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), 0.0f));
-    const float f = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), tfar));
-    return n <= f * kWiden ? n : __builtin_inff();
+// Per-ray byte offsets of the near and far planes of each axis inside a node
+// (lo at +0 and hi at +16 of the axis's 32-byte pair): a ray with a negative
+// direction component enters a box through its hi plane.
+struct Octant {
+    uint32_t nx, ny, nz, fx, fy, fz;
+};
+
+__device__ __forceinline__ Octant ray_octant(float ix, float iy, float iz) {
+    Octant q;
+    q.nx = ix < 0.0f ? 16u : 0u;
+    q.ny = iy < 0.0f ? 48u : 32u;
+    q.nz = iz < 0.0f ? 80u : 64u;
+    q.fx = q.nx ^ 16u;
+    q.fy = q.ny ^ 16u;
+    q.fz = q.nz ^ 16u;
+    return q;
 }
 
-__device__ __forceinline__ void cswap(float& ka, int& va, float& kb, int& vb) {
-    if (kb < ka) {
-        const float tk = ka;
-        ka = kb;
-        kb = tk;
-        const int tv = va;
-        va = vb;
-        vb = tv;
-    }
+// Near and far planes of the four children (one float4 per plane, one lane
+// per child) and the child references of the node at byte address p.
+struct NodePlanes {
+    float4 NX, NY, NZ, FX, FY, FZ;
+    int4 ch;
+};
+
+// base: the node array (LDS or global); off: byte offset of the node (a
+// multiple of 128, so the plane offsets can be or-ed in as 32-bit values);
+// sw: the slot swizzle of the copy, (n & 7) * 16 in LDS, 0 in global memory.
+__device__ __forceinline__ NodePlanes load_planes(const char* base, uint32_t off, uint32_t sw, const Octant& q) {
+    NodePlanes n;
+    n.NX = *reinterpret_cast<const float4*>(base + (off | (q.nx ^ sw)));
+    n.FX = *reinterpret_cast<const float4*>(base + (off | (q.fx ^ sw)));
+    n.NY = *reinterpret_cast<const float4*>(base + (off | (q.ny ^ sw)));
+    n.FY = *reinterpret_cast<const float4*>(base + (off | (q.fy ^ sw)));
+    n.NZ = *reinterpret_cast<const float4*>(base + (off | (q.nz ^ sw)));
+    n.FZ = *reinterpret_cast<const float4*>(base + (off | (q.fz ^ sw)));
+    n.ch = *reinterpret_cast<const int4*>(base + (off | (96u ^ sw)));
+    return n;
+}
+
+// Sort key of one child box: its entry distance (>= 0, sign bit cleared so
+// that -0 orders as 0; the float bits then order as unsigned) with the slot
+// in the two low bits, or ~0 when the ray misses the box.  The planes come in
+// ray order, so no per-axis min/max is needed; an empty slot (lo = +inf,
+// hi = -inf on every axis) always misses.
+__device__ __forceinline__ uint32_t box_key(float nx, float ny, float nz, float fx, float fy, float fz, float ix,
+                                            float iy, float iz, float oix, float oiy, float oiz, float tfar,
+                                            uint32_t slot) {
+    const float tn = fmaxf(fmaxf(fmaf(nx, ix, -oix), fmaf(ny, iy, -oiy)), fmaxf(fmaf(nz, iz, -oiz), 0.0f));
+    const float tf = fminf(fminf(fmaf(fx, ix, -oix), fmaf(fy, iy, -oiy)), fminf(fmaf(fz, iz, -oiz), tfar));
+    return tn <= tf * kWiden ? ((__float_as_uint(tn) & 0x7ffffffcu) | slot) : ~0u;
 }
 
 // Closest hit (ANY = false) or any hit on an open segment (ANY = true)
@@ -125,146 +160,78 @@ __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_node
     const float ox = (float)o.x, oy = (float)o.y, oz = (float)o.z;
     const float ix = safe_inv(d.x), iy = safe_inv(d.y), iz = safe_inv(d.z);
     const float oix = ox * ix, oiy = oy * iy, oiz = oz * iz;
+    const Octant oct = ray_octant(ix, iy, iz);
     float tfar = ANY ? kAnyFar : f_up(tbest);
     int best = -1;
     int node = 0, sp = 0;
-    if constexpr (!OVF) {
-        // Branch-free ordering: a hit child's key is its entry distance (>= 0,
-        // so the float bits order as unsigned) with the slot in the two low
-        // bits, a missed or empty child's key is ~0; four keys sort with
-        // unsigned min/max.  Pushes write unconditionally and advance sp only
-        // for hits (sp stays below the tree's stack need <= kStack), and the
-        // top of the stack is read ahead at every step for the pop.
-        while (true) {
-            const int top = stack[sp > 0 ? sp - 1 : 0][tid];
-            if (node >= 0) {
-                if (STATS) ts->nodes++;
-                float4 X0, X1, Y0, Y1, Z0, Z1;
-                int4 ch;
-                if (node < n_lds) {
-                    const float4* np = reinterpret_cast<const float4*>(lds_nodes + node);
-                    X0 = np[0]; X1 = np[1]; Y0 = np[2]; Y1 = np[3]; Z0 = np[4]; Z1 = np[5];
-                    ch = reinterpret_cast<const int4*>(np)[6];
-                    asm volatile("" ::: "memory");  // keeps these LDS reads apart from the global ones
-                } else {
-                    const float4* np = reinterpret_cast<const float4*>(sc.nodes + node);
-                    X0 = np[0]; X1 = np[1]; Y0 = np[2]; Y1 = np[3]; Z0 = np[4]; Z1 = np[5];
-                    ch = reinterpret_cast<const int4*>(np)[6];
-                }
-                if (STATS) ts->boxes += live_children(ch);
-                const float k0 = slab(X0.x, X1.x, Y0.x, Y1.x, Z0.x, Z1.x, ix, iy, iz, oix, oiy, oiz, tfar);
-                const float k1 = slab(X0.y, X1.y, Y0.y, Y1.y, Z0.y, Z1.y, ix, iy, iz, oix, oiy, oiz, tfar);
-                const float k2 = slab(X0.z, X1.z, Y0.z, Y1.z, Z0.z, Z1.z, ix, iy, iz, oix, oiy, oiz, tfar);
-                const float k3 = slab(X0.w, X1.w, Y0.w, Y1.w, Z0.w, Z1.w, ix, iy, iz, oix, oiy, oiz, tfar);
-                auto key = [](float k, int c, uint32_t slot) {
-                    return (k < __builtin_inff() && c != kEmptyChild) ? ((__float_as_uint(k) & ~3u) | slot) : ~0u;
-                };
-                uint32_t q0 = key(k0, ch.x, 0u), q1 = key(k1, ch.y, 1u), q2 = key(k2, ch.z, 2u),
-                         q3 = key(k3, ch.w, 3u);
-                int c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
-                // compare-exchange of (key, child) pairs as selects (no branches)
-                auto cx = [](uint32_t& a, int& ca, uint32_t& b, int& cb) {
-                    const bool sw = b < a;
-                    const uint32_t lo = sw ? b : a, hi = sw ? a : b;
-                    const int clo = sw ? cb : ca, chi = sw ? ca : cb;
-                    a = lo;
-                    b = hi;
-                    ca = clo;
-                    cb = chi;
-                };
-                cx(q0, c0, q1, c1);
-                cx(q2, c2, q3, c3);
-                cx(q0, c0, q2, c2);
-                cx(q1, c1, q3, c3);
-                cx(q1, c1, q2, c2);
-                stack[sp][tid] = c3;
-                sp += q3 != ~0u;
-                stack[sp][tid] = c2;
-                sp += q2 != ~0u;
-                stack[sp][tid] = c1;
-                sp += q1 != ~0u;
-                if (q0 != ~0u) {
-                    node = c0;
-                } else {  // no child hit, so nothing was pushed: top is still the top
-                    if (sp == 0) break;
-                    node = top;
-                    --sp;
-                }
-            } else {
-                const int code = ~node;
-                const int first = code >> kLeafShift, cnt = (code & (kMaxLeaf - 1)) + 1;
-                if (STATS) ts->tris += cnt;
-                for (int k = first; k < first + cnt; ++k) {
-                    if (tri_test(sc.tris, k, o, d, excl0, excl1, tmin, tbest, ANY)) {
-                        best = k;
-                        if (ANY) return best;
-                        tfar = f_up(tbest);
-                    }
-                }
-                if (sp == 0) break;
-                node = top;
-                --sp;
-            }
-        }
-        return best;
-    }
     int32_t ovf[OVF ? kStackOverflow : 1];  // entries beyond the LDS stack (deep trees only)
-    auto push = [&](int v) {
-        if (!OVF || sp < kStack) stack[sp][tid] = v;
-        else ovf[sp - kStack] = v;
-        ++sp;
+    // Pushes write unconditionally and advance sp only for hit children; the
+    // top of the stack is read ahead at every step for the pop.
+    auto put = [&](int at, int v) {
+        if (!OVF || at < kStack) stack[at][tid] = v;
+        else ovf[at - kStack] = v;
     };
-    auto pop = [&]() {
-        --sp;
+    auto get = [&](int at) {
         int v;
-        if (!OVF || sp < kStack) {
-            v = stack[sp][tid];
+        if (!OVF || at < kStack) {
+            v = stack[at][tid];
             asm volatile("" ::: "memory");  // an LDS read, not a flat one shared with ovf
         } else {
-            v = ovf[sp - kStack];
+            v = ovf[at - kStack];
         }
         return v;
     };
     while (true) {
+        const int top = get(sp > 0 ? sp - 1 : 0);
         if (node >= 0) {
             if (STATS) ts->nodes++;
-            float4 X0, X1, Y0, Y1, Z0, Z1;
-            int4 ch;
+            NodePlanes np;
+            const uint32_t off = (uint32_t)node * (uint32_t)sizeof(Node);
             if (node < n_lds) {
-                const float4* np = reinterpret_cast<const float4*>(lds_nodes + node);
-                X0 = np[0]; X1 = np[1]; Y0 = np[2]; Y1 = np[3]; Z0 = np[4]; Z1 = np[5];
-                ch = reinterpret_cast<const int4*>(np)[6];
+                np = load_planes(reinterpret_cast<const char*>(lds_nodes), off, 0u, oct);
                 // keeps the two branches distinct, so that the LDS reads are not
                 // merged with the global ones into generic (flat) loads
                 asm volatile("" ::: "memory");
             } else {
-                const float4* np = reinterpret_cast<const float4*>(sc.nodes + node);
-                X0 = np[0]; X1 = np[1]; Y0 = np[2]; Y1 = np[3]; Z0 = np[4]; Z1 = np[5];
-                ch = reinterpret_cast<const int4*>(np)[6];
+                np = load_planes(reinterpret_cast<const char*>(sc.nodes), off, 0u, oct);
             }
-            if (STATS) ts->boxes += live_children(ch);
-            float k0 = slab(X0.x, X1.x, Y0.x, Y1.x, Z0.x, Z1.x, ix, iy, iz, oix, oiy, oiz, tfar);
-            float k1 = slab(X0.y, X1.y, Y0.y, Y1.y, Z0.y, Z1.y, ix, iy, iz, oix, oiy, oiz, tfar);
-            float k2 = slab(X0.z, X1.z, Y0.z, Y1.z, Z0.z, Z1.z, ix, iy, iz, oix, oiy, oiz, tfar);
-            float k3 = slab(X0.w, X1.w, Y0.w, Y1.w, Z0.w, Z1.w, ix, iy, iz, oix, oiy, oiz, tfar);
-            int c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
-            if (c1 == kEmptyChild) k1 = __builtin_inff();
-            if (c2 == kEmptyChild) k2 = __builtin_inff();
-            if (c3 == kEmptyChild) k3 = __builtin_inff();
-            // sorting network on (entry distance, child)
-            cswap(k0, c0, k1, c1);
-            cswap(k2, c2, k3, c3);
-            cswap(k0, c0, k2, c2);
-            cswap(k1, c1, k3, c3);
-            cswap(k1, c1, k2, c2);
-            if (k3 < __builtin_inff()) push(c3);
-            if (k2 < __builtin_inff()) push(c2);
-            if (k1 < __builtin_inff()) push(c1);
-            if (k0 < __builtin_inff()) {
+            if (STATS) ts->boxes += live_children(np.ch);
+            uint32_t q0 = box_key(np.NX.x, np.NY.x, np.NZ.x, np.FX.x, np.FY.x, np.FZ.x, ix, iy, iz, oix, oiy, oiz,
+                                  tfar, 0u);
+            uint32_t q1 = box_key(np.NX.y, np.NY.y, np.NZ.y, np.FX.y, np.FY.y, np.FZ.y, ix, iy, iz, oix, oiy, oiz,
+                                  tfar, 1u);
+            uint32_t q2 = box_key(np.NX.z, np.NY.z, np.NZ.z, np.FX.z, np.FY.z, np.FZ.z, ix, iy, iz, oix, oiy, oiz,
+                                  tfar, 2u);
+            uint32_t q3 = box_key(np.NX.w, np.NY.w, np.NZ.w, np.FX.w, np.FY.w, np.FZ.w, ix, iy, iz, oix, oiy, oiz,
+                                  tfar, 3u);
+            int c0 = np.ch.x, c1 = np.ch.y, c2 = np.ch.z, c3 = np.ch.w;
+            // sorting network of compare-exchanges on (key, child) as selects
+            auto cx = [](uint32_t& a, int& ca, uint32_t& b, int& cb) {
+                const bool sw = b < a;
+                const uint32_t lo = sw ? b : a, hi = sw ? a : b;
+                const int clo = sw ? cb : ca, chi = sw ? ca : cb;
+                a = lo;
+                b = hi;
+                ca = clo;
+                cb = chi;
+            };
+            cx(q0, c0, q1, c1);
+            cx(q2, c2, q3, c3);
+            cx(q0, c0, q2, c2);
+            cx(q1, c1, q3, c3);
+            cx(q1, c1, q2, c2);
+            put(sp, c3);
+            sp += q3 != ~0u;
+            put(sp, c2);
+            sp += q2 != ~0u;
+            put(sp, c1);
+            sp += q1 != ~0u;
+            if (q0 != ~0u) {
                 node = c0;
-            } else {
+            } else {  // no child hit, so nothing was pushed: top is still the top
                 if (sp == 0) break;
-                node = pop();
+                node = top;
+                --sp;
             }
         } else {
             const int code = ~node;
@@ -278,7 +245,8 @@ __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_node
                 }
             }
             if (sp == 0) break;
-            node = pop();
+            node = top;
+            --sp;
         }
     }
     return best;
