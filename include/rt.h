@@ -213,6 +213,22 @@ rt_status rt_coverage_map(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p
 rt_status rt_coverage_maps(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p, const rt_device* tx, int32_t ntx,
                            const rt_device* rx_ant, const rt_grid* grid, float* gain, uint32_t* hits, float* gain_db);
 
+/* rt_coverage_map for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, outputs and errors as rt_coverage_map; the caller still
+ * passes (and owns) every output.  The ray queues and queue counters live in
+ * a fixed device array of the library (112 MiB + 64 KiB, one copy per GPU,
+ * held until the process ends), so the lattice is traced in chunks of at most
+ * 2^19 rays instead of 2^24; clears use fill kernels, not memsets.  Nothing is
+ * allocated and no HIP events are created (rt_profile_enable does not apply).
+ * Returns RT_ERR_CAPACITY if the queues for this device's launch width do not
+ * fit the array.  Every call on one GPU shares that array: calls that overlap
+ * on one GPU (other streams, other contexts or threads) race and must be
+ * serialised by the caller. */
+rt_status rt_coverage_map_noalloc(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p, const rt_device* tx,
+                                  const rt_device* rx_ant, const rt_grid* grid, float* gain, uint32_t* hits,
+                                  float* gain_db, uint64_t* ray_bounces);
+
 /* rt_coverage_map that also counts, per depth k, the traced rays, the BVH
  * inner nodes visited, the child boxes tested at those nodes (the node's
  * non-empty slots) and the triangles tested:

@@ -81,6 +81,8 @@ SIGNATURES = {
                         ctypes.POINTER(rt_grid), P, P, P, P],
     "rt_coverage_work": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), ctypes.POINTER(rt_device),
                          ctypes.POINTER(rt_grid), P, P, P],
+    "rt_coverage_map_noalloc": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device),
+                                ctypes.POINTER(rt_device), ctypes.POINTER(rt_grid), P, P, P, P],
     "rt_profile_enable": [P, I32],
     "rt_profile_read": [P, I32, P, P],
     "rt_compute_paths": [P, P, ctypes.POINTER(rt_trace_params), P, I32, P, I32, P, P, P, P, P, P, P, P],

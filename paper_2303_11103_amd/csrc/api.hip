@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -53,6 +54,41 @@ hipError_t ensure(DevBuf& b, size_t bytes) {
     return e;
 }
 
+// Scratch of rt_coverage_map_noalloc: the two ray queues and the queue-region
+// counters of the shoot-and-bounce launches, in a file-scope device array (one
+// copy per GPU, alive until the process ends).  Host code uses only the
+// addresses hipGetSymbolAddress returns for it, never the array's name.
+constexpr size_t kNoAllocCounterBytes = 64 << 10;
+constexpr size_t kNoAllocScratchBytes = (size_t(112) << 20) + kNoAllocCounterBytes;
+constexpr int64_t kNoAllocMaxChunk = int64_t(1) << 19;  // rays per launch sequence
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `device` (looked up once
+// per device).
+rt_status scratch_address(int device, void** out) {
+    if (device < 0 || device >= kMaxDevices) return fail(RT_ERR_ARG, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(RT_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return RT_OK;
+}
+
+// Fixed queue memory handed to run_sbr instead of the context's buffers.
+struct FixedQueues {
+    rt::RayState* q[2];
+    uint32_t* counters;
+    int64_t max_chunk;
+};
+
 }  // namespace
 
 struct rt_ctx {
@@ -70,6 +106,7 @@ struct rt_ctx {
     DevBuf rx_ant;     // Antenna [nrx]
     DevBuf paths;      // unsorted path records
     DevBuf chan;       // channel responses: element offsets and velocities
+    void* scratch = nullptr;  // this device's copy of the fixed scratch array
     int64_t last_candidates = 0;
     // launch timing of the shoot-and-bounce kernels
     bool profiling = false;
@@ -200,14 +237,25 @@ int grid_for(const rt_ctx* c) { return c->num_cu * 4; }
 rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx, const rt_device* rx_ant,
                   const rt_grid* g, int mode, float* gain, uint32_t* hits, uint64_t* stats, int32_t* rec_tri,
                   double* rec_t, uint64_t* table, uint64_t table_mask, uint32_t* overflow,
-                  uint64_t* work = nullptr, const rt::SbrArgs* sphere = nullptr) {
+                  uint64_t* work = nullptr, const rt::SbrArgs* sphere = nullptr, const FixedQueues* fixed = nullptr) {
     const int64_t count = traced_count(p);
-    const int64_t chunk = std::min(count, kChunk);
+    const int64_t chunk = std::min(count, fixed ? fixed->max_chunk : kChunk);
     const int64_t region_cap = rt::sbr_region_capacity(chunk, grid_for(c));
-    const size_t qbytes = (size_t)rt::kQueueRegions * region_cap * sizeof(rt::RayState);
-    RT_HIP(ensure(c->queue[0], qbytes));
-    RT_HIP(ensure(c->queue[1], qbytes));
-    RT_HIP(ensure(c->counters, (size_t)(p->max_depth + 1) * rt::kQueueRegions * sizeof(uint32_t)));
+    rt::RayState* queue[2];
+    uint32_t* cnt;
+    if (fixed) {
+        queue[0] = fixed->q[0];
+        queue[1] = fixed->q[1];
+        cnt = fixed->counters;
+    } else {
+        const size_t qbytes = (size_t)rt::kQueueRegions * region_cap * sizeof(rt::RayState);
+        RT_HIP(ensure(c->queue[0], qbytes));
+        RT_HIP(ensure(c->queue[1], qbytes));
+        RT_HIP(ensure(c->counters, (size_t)(p->max_depth + 1) * rt::kQueueRegions * sizeof(uint32_t)));
+        queue[0] = (rt::RayState*)c->queue[0].p;
+        queue[1] = (rt::RayState*)c->queue[1].p;
+        cnt = (uint32_t*)c->counters.p;
+    }
     rt::MatTable mats = make_mats(s, p->freq_hz);
     rt::SbrArgs a{};
     a.sc = s->dev;
@@ -260,20 +308,22 @@ rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_dev
         a.pairs_mask = sphere->pairs_mask;
         a.pairs_overflow = sphere->pairs_overflow;
     }
-    uint32_t* cnt = (uint32_t*)c->counters.p;
+    const bool profiling = c->profiling && !fixed;  // the fixed-memory path creates no events
     for (int64_t pos0 = 0; pos0 < count; pos0 += chunk) {
         a.pos0 = pos0;
         a.chunk = std::min(chunk, count - pos0);
-        RT_HIP(hipMemsetAsync(cnt, 0, (size_t)(p->max_depth + 1) * rt::kQueueRegions * sizeof(uint32_t), c->stream));
+        const size_t nwords = (size_t)(p->max_depth + 1) * rt::kQueueRegions;
+        if (fixed) RT_HIP(rt::launch_fill_u32(cnt, 0u, nwords, c->stream));
+        else RT_HIP(hipMemsetAsync(cnt, 0, nwords * sizeof(uint32_t), c->stream));
         for (int k = 0; k <= p->max_depth; ++k) {
             a.depth = k;
-            a.in = k ? (const rt::RayState*)c->queue[(k - 1) & 1].p : nullptr;
+            a.in = k ? queue[(k - 1) & 1] : nullptr;
             a.in_count = k ? cnt + (size_t)(k - 1) * rt::kQueueRegions : nullptr;
-            a.out = (rt::RayState*)c->queue[k & 1].p;
+            a.out = queue[k & 1];
             a.out_count = cnt + (size_t)k * rt::kQueueRegions;
             a.region_cap = region_cap;
             hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (c->profiling) {
+            if (profiling) {
                 while (c->ev_pool.size() < c->ev_used + 2) {
                     hipEvent_t e;
                     RT_HIP(hipEventCreate(&e));
@@ -284,7 +334,7 @@ rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_dev
                 RT_HIP(hipEventRecord(e0, c->stream));
             }
             RT_HIP(rt::launch_sbr_bounce(a, mats, mode, grid_for(c), c->stream));
-            if (c->profiling) {
+            if (profiling) {
                 RT_HIP(hipEventRecord(e1, c->stream));
                 c->recs.push_back({k, e0, e1});
             }
@@ -310,8 +360,12 @@ rt_status rt_create(rt_ctx** out, int32_t device) {
     RT_HIP(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(RT_ERR_ARG, "no such HIP device");
     RT_HIP(hipSetDevice(device));
+    void* scr = nullptr;
+    const rt_status st = scratch_address(device, &scr);
+    if (st != RT_OK) return st;
     rt_ctx* c = new rt_ctx();
     c->device = device;
+    c->scratch = scr;
     int cu = 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0) c->num_cu = cu;
     *out = c;
@@ -462,7 +516,7 @@ rt_status rt_trace_record(rt_ctx* c, rt_scene* s, const rt_trace_params* p, cons
 namespace {
 rt_status coverage_impl(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx,
                         const rt_device* rx_ant, const rt_grid* g, float* gain, uint32_t* hits, float* gain_db,
-                        uint64_t* ray_bounces, uint64_t* work) {
+                        uint64_t* ray_bounces, uint64_t* work, const FixedQueues* fixed = nullptr) {
     if (!c || !s || !g || !gain || !hits) return fail(RT_ERR_ARG, "NULL argument");
     rt_status st = check_params(p);
     if (st != RT_OK) return st;
@@ -475,12 +529,19 @@ rt_status coverage_impl(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const 
         return fail(RT_ERR_ARG, "grid origin, cell size and height must be finite, cell > 0");
     RT_HIP(hipSetDevice(c->device));
     const int64_t cells = (int64_t)g->nx * g->ny;
-    RT_HIP(hipMemsetAsync(gain, 0, (size_t)cells * sizeof(float), c->stream));
-    RT_HIP(hipMemsetAsync(hits, 0, (size_t)cells * sizeof(uint32_t), c->stream));
-    if (ray_bounces) RT_HIP(hipMemsetAsync(ray_bounces, 0, (size_t)(p->max_depth + 1) * sizeof(uint64_t), c->stream));
-    if (work) RT_HIP(hipMemsetAsync(work, 0, (size_t)4 * (p->max_depth + 1) * sizeof(uint64_t), c->stream));
+    if (fixed) {  // fill kernels: callers of the fixed-memory path may capture it in a graph
+        RT_HIP(rt::launch_fill_u32(gain, 0u, (size_t)cells, c->stream));
+        RT_HIP(rt::launch_fill_u32(hits, 0u, (size_t)cells, c->stream));
+        if (ray_bounces) RT_HIP(rt::launch_fill_u32(ray_bounces, 0u, (size_t)(p->max_depth + 1) * 2, c->stream));
+    } else {
+        RT_HIP(hipMemsetAsync(gain, 0, (size_t)cells * sizeof(float), c->stream));
+        RT_HIP(hipMemsetAsync(hits, 0, (size_t)cells * sizeof(uint32_t), c->stream));
+        if (ray_bounces)
+            RT_HIP(hipMemsetAsync(ray_bounces, 0, (size_t)(p->max_depth + 1) * sizeof(uint64_t), c->stream));
+        if (work) RT_HIP(hipMemsetAsync(work, 0, (size_t)4 * (p->max_depth + 1) * sizeof(uint64_t), c->stream));
+    }
     st = run_sbr(c, s, p, tx, rx_ant, g, work ? (rt::kModeCoverage | rt::kModeStats) : rt::kModeCoverage, gain, hits,
-                 ray_bounces, nullptr, nullptr, nullptr, 0, nullptr, work);
+                 ray_bounces, nullptr, nullptr, nullptr, 0, nullptr, work, nullptr, fixed);
     if (st != RT_OK) return st;
     if (gain_db) RT_HIP(rt::launch_finalize_db(gain, gain_db, cells, c->stream));
     return RT_OK;
@@ -491,6 +552,30 @@ rt_status rt_coverage_map(rt_ctx* c, rt_scene* s, const rt_trace_params* p, cons
                           const rt_device* rx_ant, const rt_grid* g, float* gain, uint32_t* hits, float* gain_db,
                           uint64_t* ray_bounces) {
     return coverage_impl(c, s, p, tx, rx_ant, g, gain, hits, gain_db, ray_bounces, nullptr);
+}
+
+rt_status rt_coverage_map_noalloc(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx,
+                                  const rt_device* rx_ant, const rt_grid* g, float* gain, uint32_t* hits,
+                                  float* gain_db, uint64_t* ray_bounces) {
+    if (!c) return fail(RT_ERR_ARG, "ctx is NULL");
+    if (!c->scratch) return fail(RT_ERR_DEVICE, "the context has no scratch address (rt_create did not set it)");
+    if (p && (p->max_depth < 0 || p->max_depth > 8)) return fail(RT_ERR_ARG, "max_depth must be in [0, 8]");
+    // queues of the largest chunk whose two queues fit the scratch beside the counters
+    int64_t chunk = kNoAllocMaxChunk;
+    const size_t qmax = (kNoAllocScratchBytes - kNoAllocCounterBytes) / 2;
+    while (chunk > 64 && (size_t)rt::kQueueRegions * rt::sbr_region_capacity(chunk, grid_for(c)) *
+                                 sizeof(rt::RayState) > qmax)
+        chunk >>= 1;
+    const size_t qbytes = (size_t)rt::kQueueRegions * rt::sbr_region_capacity(chunk, grid_for(c)) *
+                          sizeof(rt::RayState);
+    if (qbytes > qmax) return fail(RT_ERR_CAPACITY, "the ray queues of this device do not fit the fixed scratch");
+    unsigned char* base = (unsigned char*)c->scratch;
+    FixedQueues fq;
+    fq.counters = (uint32_t*)base;
+    fq.q[0] = (rt::RayState*)(base + kNoAllocCounterBytes);
+    fq.q[1] = (rt::RayState*)(base + kNoAllocCounterBytes + qmax);
+    fq.max_chunk = chunk;
+    return coverage_impl(c, s, p, tx, rx_ant, g, gain, hits, gain_db, ray_bounces, nullptr, &fq);
 }
 
 rt_status rt_coverage_maps(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx, int32_t ntx,

@@ -103,6 +103,8 @@ int64_t sbr_region_capacity(int64_t chunk, int grid);
 hipError_t launch_sbr_bounce(const SbrArgs& a, const MatTable& mats, int mode, int grid, hipStream_t s);
 hipError_t launch_fib_dirs(int64_t N, int64_t begin, int64_t stride, int64_t count, double* out, hipStream_t s);
 hipError_t launch_finalize_db(const float* gain, float* db, int64_t n, hipStream_t s);
+// p[0 .. n) = v (32-bit words), as a kernel (usable inside captured graphs).
+hipError_t launch_fill_u32(void* p, uint32_t v, size_t n, hipStream_t s);
 
 // ---------------------------------------------------------------- paths
 struct Cand {

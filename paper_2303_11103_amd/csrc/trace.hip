@@ -409,6 +409,11 @@ __global__ void fib_dirs_kernel(int64_t N, int64_t begin, int64_t stride, int64_
     out[3 * j + 2] = d.z;
 }
 
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void finalize_db_kernel(const float* __restrict__ g, float* __restrict__ db, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -454,6 +459,13 @@ hipError_t launch_fib_dirs(int64_t N, int64_t begin, int64_t stride, int64_t cou
     if (count <= 0) return hipSuccess;
     int64_t blocks = (count + 255) / 256;
     hipLaunchKernelGGL(fib_dirs_kernel, dim3((unsigned)blocks), dim3(256), 0, s, N, begin, stride, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(void* p, uint32_t v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = ((int64_t)n + 255) / 256;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, v, (int64_t)n);
     return hipGetLastError();
 }
 
