@@ -440,6 +440,17 @@ rt_status rt_mlp_sample_batch(rt_mlp* mlp, const float* maps, const uint32_t* in
  * grid's cell centres.  RT_ERR_ARG for an empty stack or one of 2^40 cells or
  * more. */
 rt_status rt_mlp_predict_maps(rt_mlp* mlp, const float* tx, int32_t T, const rt_grid* grid, float* maps);
+/* Surrogate maps with the ray tracer as fallback: the predicted maps [T][ny][nx]
+ * (dev, dB) of rt_mlp_predict_maps for the positions of tx [T] (host), then,
+ * when any cell is marked, every transmitter's coverage map by the ray tracer
+ * (rt_coverage_map with p, tx[k], rx_ant and the grid), whose dB values replace
+ * the prediction in the cells with fallback [ny][nx] (dev, uint8) != 0 (-inf
+ * where no ray crossed the cell).  fallback_cells (host, nullable) receives the
+ * number of marked cells.  The scene must belong to the surrogate's context.
+ * Grows per-handle scratch (positions and one map) as needed; synchronous. */
+rt_status rt_mlp_predict_maps_fallback(rt_mlp* mlp, rt_scene* scene, const rt_trace_params* p, const rt_device* tx,
+                                       int32_t T, const rt_device* rx_ant, const rt_grid* grid,
+                                       const uint8_t* fallback, float* maps, int64_t* fallback_cells);
 
 #ifdef __cplusplus
 }

@@ -110,6 +110,8 @@ SIGNATURES = {
     "rt_mlp_sample_batch": [P, P, P, I64, P, I32, ctypes.POINTER(rt_grid), ctypes.c_uint64, ctypes.c_uint64, P, P, P,
                             I64],
     "rt_mlp_predict_maps": [P, P, I32, ctypes.POINTER(rt_grid), P],
+    "rt_mlp_predict_maps_fallback": [P, P, ctypes.POINTER(rt_trace_params), P, I32, ctypes.POINTER(rt_device),
+                                     ctypes.POINTER(rt_grid), P, P, ctypes.POINTER(I64)],
 }
 _RESTYPE = {"rt_last_error": ctypes.c_char_p}
 

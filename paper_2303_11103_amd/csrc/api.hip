@@ -349,6 +349,7 @@ rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_dev
 rt_status rt_internal_fail(rt_status code, const char* msg) { return fail(code, msg); }
 hipStream_t rt_internal_stream(rt_ctx* c) { return c->stream; }
 int rt_internal_device(rt_ctx* c) { return c->device; }
+rt_ctx* rt_internal_scene_ctx(const rt_scene* s) { return s->ctx; }
 
 extern "C" {
 

@@ -750,6 +750,24 @@ __global__ __launch_bounds__(512) void infer_v2_kernel(InferV2Args a) {
     }
 }
 
+// Number of nonzero bytes of a mask (atomic count).
+__global__ void count_u8_kernel(const uint8_t* __restrict__ m, int64_t n, unsigned long long* __restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool on = i < n && m[i] != 0;
+    const uint64_t b = __ballot(on);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
+}
+
+// Traced cells replace predicted ones: out[c] = 10 log10(gain[c]) (-inf when
+// no ray crossed the cell) where fallback[c] != 0.
+__global__ void fallback_merge_kernel(const uint8_t* __restrict__ fallback, const float* __restrict__ gain,
+                                      int64_t n, float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !fallback[i]) return;
+    const float g = gain[i];
+    out[i] = g > 0.0f ? 10.0f * log10f(g) : -__builtin_inff();
+}
+
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -840,6 +858,18 @@ hipError_t launch_index_write(const uint8_t* mask, int64_t n, const uint64_t* of
 }
 
 int64_t v2_weights_halves() { return (int64_t)(kL1Frags + 3 * kLFrags) * kFragHalves; }
+
+hipError_t launch_count_u8(const uint8_t* m, int64_t n, unsigned long long* count, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(count_u8_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, m, n, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fallback_merge(const uint8_t* fallback, const float* gain, int64_t n, float* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fallback_merge_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, fallback, gain, n, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_infer_v2(const float* tx, int32_t T, double gx0, double gy0, double gcell, int32_t gnx, int32_t gny,
                            const float* ff, const MlpNorm& norm, _Float16* wfrag, const MlpLayout& lay,

@@ -4,6 +4,7 @@
 // map prediction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -15,6 +16,7 @@
 rt_status rt_internal_fail(rt_status code, const char* msg);
 hipStream_t rt_internal_stream(rt_ctx* c);
 int rt_internal_device(rt_ctx* c);
+rt_ctx* rt_internal_scene_ctx(const rt_scene* s);
 
 namespace {
 
@@ -67,6 +69,13 @@ struct rt_mlp {
     int num_cu = 256;
     int64_t step = 0;
     std::vector<void*> allocs;
+    // ray-tracer fallback scratch (grown on demand, freed on destroy)
+    float* fb_tx = nullptr;
+    size_t fb_tx_n = 0;
+    float* fb_gain = nullptr;
+    uint32_t* fb_hits = nullptr;
+    size_t fb_cells = 0;
+    unsigned long long* fb_count = nullptr;
 };
 
 namespace {
@@ -255,6 +264,8 @@ rt_status rt_mlp_destroy(rt_mlp* h) {
     (void)hipSetDevice(rt_internal_device(h->ctx));
     (void)hipStreamSynchronize(rt_internal_stream(h->ctx));
     for (void* p : h->allocs) (void)hipFree(p);
+    for (void* p : {(void*)h->fb_tx, (void*)h->fb_gain, (void*)h->fb_hits, (void*)h->fb_count})
+        if (p) (void)hipFree(p);
     delete h;
     return RT_OK;
 }
@@ -371,6 +382,65 @@ rt_status rt_mlp_predict_maps(rt_mlp* h, const float* tx, int32_t T, const rt_gr
     MLP_HIP(hipSetDevice(rt_internal_device(h->ctx)));
     MLP_HIP(rt::launch_infer_v2(tx, T, g->x0, g->y0, g->cell, g->nx, g->ny, h->ff, h->norm, h->wfrag, h->lay,
                                 h->params, maps, h->num_cu, s));
+    return RT_OK;
+}
+
+rt_status rt_mlp_predict_maps_fallback(rt_mlp* h, rt_scene* scene, const rt_trace_params* p, const rt_device* tx,
+                                       int32_t T, const rt_device* rx_ant, const rt_grid* g, const uint8_t* fallback,
+                                       float* maps, int64_t* fallback_cells) {
+    if (!h || !scene || !p || !tx || !rx_ant || !g || !fallback || !maps)
+        return rt_internal_fail(RT_ERR_ARG, "NULL argument");
+    if (rt_internal_scene_ctx(scene) != h->ctx)
+        return rt_internal_fail(RT_ERR_ARG, "scene and surrogate belong to different contexts");
+    if (T < 1 || g->nx < 1 || g->ny < 1) return rt_internal_fail(RT_ERR_ARG, "empty map stack");
+    if ((double)T * g->nx * g->ny >= 0x1p40) return rt_internal_fail(RT_ERR_ARG, "map stack of 2^40 cells or more");
+    for (int32_t k = 0; k < T; ++k)
+        if (!std::isfinite(tx[k].pos[0]) || !std::isfinite(tx[k].pos[1]) || !std::isfinite(tx[k].pos[2]))
+            return rt_internal_fail(RT_ERR_ARG, "a transmitter position is not finite");
+    hipStream_t s = rt_internal_stream(h->ctx);
+    MLP_HIP(hipSetDevice(rt_internal_device(h->ctx)));
+    const size_t cells = (size_t)g->nx * g->ny;
+    auto grow = [&](void** ptr, size_t& have, size_t want, size_t elem) -> hipError_t {
+        if (have >= want && *ptr) return hipSuccess;
+        if (*ptr) {
+            const hipError_t e = hipFree(*ptr);
+            if (e != hipSuccess) return e;
+            *ptr = nullptr;
+        }
+        have = 0;
+        const hipError_t e = hipMalloc(ptr, want * elem);
+        if (e == hipSuccess) have = want;
+        return e;
+    };
+    MLP_HIP(hipStreamSynchronize(s));  // earlier calls may still read the scratch being regrown
+    MLP_HIP(grow((void**)&h->fb_tx, h->fb_tx_n, (size_t)T * 3, sizeof(float)));
+    size_t cells_g = h->fb_cells, cells_h = h->fb_cells;
+    MLP_HIP(grow((void**)&h->fb_gain, cells_g, cells, sizeof(float)));
+    MLP_HIP(grow((void**)&h->fb_hits, cells_h, cells, sizeof(uint32_t)));
+    h->fb_cells = std::min(cells_g, cells_h);
+    if (!h->fb_count) MLP_HIP(hipMalloc((void**)&h->fb_count, sizeof(unsigned long long)));
+    std::vector<float> pos(3 * (size_t)T);
+    for (int32_t k = 0; k < T; ++k)
+        for (int i = 0; i < 3; ++i) pos[3 * k + i] = tx[k].pos[i];
+    MLP_HIP(hipMemcpyAsync(h->fb_tx, pos.data(), pos.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    // 1. the surrogate's maps
+    MLP_HIP(rt::launch_infer_v2(h->fb_tx, T, g->x0, g->y0, g->cell, g->nx, g->ny, h->ff, h->norm, h->wfrag, h->lay,
+                                h->params, maps, h->num_cu, s));
+    // 2. how many cells fall back
+    unsigned long long n = 0;
+    MLP_HIP(hipMemsetAsync(h->fb_count, 0, sizeof(unsigned long long), s));
+    MLP_HIP(rt::launch_count_u8(fallback, (int64_t)cells, h->fb_count, s));
+    MLP_HIP(hipMemcpyAsync(&n, h->fb_count, sizeof(n), hipMemcpyDeviceToHost, s));
+    MLP_HIP(hipStreamSynchronize(s));  // also ends the staging of pos
+    if (fallback_cells) *fallback_cells = (int64_t)n;
+    if (n == 0) return RT_OK;
+    // 3. every transmitter's traced map, merged into the fallback cells
+    for (int32_t k = 0; k < T; ++k) {
+        const rt_status st = rt_coverage_map(h->ctx, scene, p, tx + k, rx_ant, g, h->fb_gain, h->fb_hits, nullptr,
+                                             nullptr);
+        if (st != RT_OK) return st;
+        MLP_HIP(rt::launch_fallback_merge(fallback, h->fb_gain, (int64_t)cells, maps + (size_t)k * cells, s));
+    }
     return RT_OK;
 }
 

@@ -46,6 +46,10 @@ hipError_t launch_head(const __bf16* H4, const __bf16* Z4, const float* w5, cons
                        const MlpNorm& norm, const float* t, const float* m, int64_t n, const float* msum, float* pred,
                        float* loss, __bf16* dZ4, float* gw5, float* gb5, hipStream_t s);
 hipError_t launch_mask_sum(const float* m, int64_t n, float* out, hipStream_t s);
+// *count += number of nonzero bytes of m[0 .. n) (count cleared by the caller).
+hipError_t launch_count_u8(const uint8_t* m, int64_t n, unsigned long long* count, hipStream_t s);
+// out[c] = 10 log10(gain[c]) (or -inf) for the cells with fallback[c] != 0.
+hipError_t launch_fallback_merge(const uint8_t* fallback, const float* gain, int64_t n, float* out, hipStream_t s);
 hipError_t launch_transpose(const __bf16* in, int64_t R, int64_t C, __bf16* out, hipStream_t s);
 hipError_t launch_rowsum(const __bf16* dZt, int64_t rows, int64_t cols, float* db, hipStream_t s);
 hipError_t launch_reduce_splits(const float* part, int S, int64_t n, float* grad, hipStream_t s);

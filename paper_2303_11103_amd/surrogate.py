@@ -130,6 +130,29 @@ class MLP:
         check(lib.rt_mlp_predict_maps(self.h, _p(tx), tx.shape[0], ctypes.byref(g), _p(out)))
         return out
 
+    def predict_maps_fallback(self, scene: Scene, params: TraceParams, txs, grid, fallback, rx_ant=None,
+                              out=None):
+        """Maps [T][ny][nx] (dB) for the transmitters txs (objects with pos, yaw,
+        pitch, roll, pattern): the surrogate's prediction, with the cells where
+        the uint8 tensor fallback [ny][nx] is nonzero answered by the ray tracer.
+        Returns (maps, number of fallback cells)."""
+        from types import SimpleNamespace
+
+        from .rt import device_struct
+        T = len(txs)
+        dev = self.ctx.torch_device
+        if out is None:
+            out = torch.empty((T, grid.ny, grid.nx), dtype=torch.float32, device=dev)
+        rx_ant = rx_ant or SimpleNamespace(pos=(0.0, 0.0, 0.0), yaw=0.0, pitch=0.0, roll=0.0, pattern=0)
+        fb = fallback.to(torch.uint8).contiguous()
+        tx_arr = (L.rt_device * T)(*[device_struct(t) for t in txs])
+        p, r, g = params.c(), device_struct(rx_ant), grid_struct(grid)
+        n = ctypes.c_int64()
+        self.ctx._bind_stream()
+        check(lib.rt_mlp_predict_maps_fallback(self.h, scene.h, ctypes.byref(p), tx_arr, T, ctypes.byref(r),
+                                               ctypes.byref(g), _p(fb), _p(out), ctypes.byref(n)))
+        return out, int(n.value)
+
     def close(self):
         if self.h:
             lib.rt_mlp_destroy(self.h)

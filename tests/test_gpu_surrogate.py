@@ -61,3 +61,34 @@ def test_trained_surrogate_beats_free_space_and_outruns_the_tracer():
     assert rmse < 0.75 * rmse_fs, (rmse, rmse_fs)
     assert sur_s_per_map * 5 < trace_s_per_map, (sur_s_per_map, trace_s_per_map)
     m.close()
+
+
+def test_predict_maps_with_ray_tracer_fallback():
+    """rt_mlp_predict_maps_fallback: marked cells carry the ray tracer's map of
+    each transmitter (bit for bit what rt_coverage_map gives), the others the
+    surrogate's prediction (bit for bit rt_mlp_predict_maps); with no marked
+    cell nothing is traced."""
+    m_lib = lib()
+    from paper_2303_11103_amd import surrogate as S
+    w = sg.toy_workload()
+    sc = scene(w.scene)
+    grid = w.grid
+    p = m_lib.TraceParams(w.scene.freq_hz, w.max_depth, w.num_rays)
+    txs = [sg.Device((0.0, 0.0, 10.0)), sg.Device((-40.0, 25.0, 12.0)), sg.Device((60.0, -30.0, 20.0))]
+    mm = S.MLP(ctx(), batch=1024, ff_scale=1.0, seed=11, center=(0, 0, 10, 0, 0), half=(100, 100, 10, 100, 100),
+               prior=(w.scene.freq_hz, grid.z))
+    rng = np.random.default_rng(12)
+    fb = torch.tensor((rng.random((grid.ny, grid.nx)) < 0.1).astype(np.uint8), device="cuda")
+    out, n = mm.predict_maps_fallback(sc, p, txs, grid, fb)
+    assert n == int(fb.sum())
+    pred = mm.predict_maps(torch.tensor([t.pos for t in txs], dtype=torch.float32, device="cuda"), grid)
+    sel = fb.bool()
+    for k, tx in enumerate(txs):
+        ref = m_lib.coverage_map(ctx(), sc, p, tx, grid)["gain_db"]
+        # the two traces differ only in the order of their fp32 atomic additions
+        assert torch.allclose(out[k][sel], ref[sel], rtol=0.0, atol=1e-4)
+        assert torch.equal(torch.isinf(out[k][sel]), torch.isinf(ref[sel]))
+        assert torch.equal(out[k][~sel], pred[k][~sel])
+    out0, n0 = mm.predict_maps_fallback(sc, p, txs, grid, torch.zeros_like(fb))
+    assert n0 == 0 and torch.equal(out0, pred)
+    mm.close()
