@@ -121,7 +121,7 @@ typedef struct {
     int32_t num_materials;
     int64_t bvh_nodes;
     int32_t bvh_depth;
-    int32_t reserved;
+    int32_t num_wedges;     /* edges that diffract (see rt_scene_wedges) */
     double build_ms;        /* host time of scene preparation + BVH build */
 } rt_scene_info_t;
 
@@ -278,6 +278,42 @@ rt_status rt_paths_power(rt_ctx* ctx, const float* a, const int32_t* depth, int6
 /* Number of distinct candidate face sequences found by the last
  * rt_compute_paths call for its last transmitter. */
 rt_status rt_last_candidate_count(rt_ctx* ctx, int64_t* count);
+
+/* Wedges of the scene for first-order diffraction (Sec. II-B): edges shared
+ * by exactly two triangles of two different faces, not on the ground (the
+ * lowest z of the mesh), whose interior angle alpha between the faces'
+ * half-planes (the smaller of the two: convex solids) is below pi.  Sorted by
+ * (0-face, n-face, first vertex, second vertex); the 0-face is the face with
+ * the smaller id.  count (host) receives the number of wedges; the first
+ * min(capacity, count) records are written to out (host) [..][16] doubles:
+ * first vertex a[3], unit edge direction e[3], t0[3] (unit vector in the
+ * 0-face orthogonal to e, into the face), n0[3] (the 0-face normal on the
+ * exterior side), length, n = 2 - alpha/pi (exterior angle n pi), 0-face id,
+ * n-face id.  out may be NULL when capacity is 0. */
+rt_status rt_scene_wedges(const rt_scene* scene, int32_t capacity, double* out, int32_t* count);
+
+/* First-order diffraction paths (Sec. II-B: first-order diffraction; the
+ * uniform theory of diffraction for a wedge, Kouyoumjian and Pathak, with the
+ * Fresnel coefficients of the two faces in place of the perfect-conductor
+ * signs, Luebbers): for every (tx, rx) and every wedge, the diffraction point
+ * Q on the edge with equal angles of the incident and diffracted rays to the
+ * edge (Keller's law), kept when Q lies inside the edge, tx and rx lie in the
+ * wedge's exterior and both legs are unoccluded.  Its coefficient is
+ *   a = lambda/(4 pi) F_rx(-s) . Dbar . F_tx(s') / sqrt(s' s (s' + s))
+ * (carrier phase excluded, as for rt_compute_paths), with the dyadic
+ * Dbar = -b' b D_s - p' p D_h of the UTD coefficients in edge-fixed unit
+ * vectors, s' = |Q - tx|, s = |rx - Q|; tau = (s' + s)/c0.  Outputs, shape
+ * [ntx][nrx][P] (dev), with the layouts of rt_compute_paths:
+ *   a [..][2], T [..][2][2][2] (so that a = lambda/(4 pi (s + s')) F_rx^T T F_tx),
+ *   tau [..], aod [..][2] (angles of s'), aoa [..][2] (angles of -s),
+ *   wedge [..] int32 wedge index (rt_scene_wedges order, -1 unused),
+ *   num_paths [ntx][nrx] int32 (not truncated).
+ * Paths of one (tx, rx) are sorted by wedge index; unused slots get a = 0,
+ * tau = -1.  RT_ERR_CAPACITY when some (tx, rx) has more than P paths (the
+ * message gives the required P).  Synchronous. */
+rt_status rt_compute_diffraction(rt_ctx* ctx, rt_scene* scene, double freq_hz, const rt_device* tx, int32_t ntx,
+                                 const rt_device* rx, int32_t nrx, int32_t P, float* a, float* T, float* tau,
+                                 float* aod, float* aoa, int32_t* wedge, int32_t* num_paths);
 
 /* Gradient of a loss of received powers (Sec. I and III: gradients with
  * respect to material properties and transmitter orientation and position).

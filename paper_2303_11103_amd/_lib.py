@@ -52,7 +52,7 @@ class rt_mlp_config(ctypes.Structure):
 
 class rt_scene_info_t(ctypes.Structure):
     _fields_ = [("num_triangles", ctypes.c_int64), ("num_faces", ctypes.c_int32), ("num_materials", ctypes.c_int32),
-                ("bvh_nodes", ctypes.c_int64), ("bvh_depth", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("bvh_nodes", ctypes.c_int64), ("bvh_depth", ctypes.c_int32), ("num_wedges", ctypes.c_int32),
                 ("build_ms", ctypes.c_double)]
 
 
@@ -87,6 +87,8 @@ SIGNATURES = {
     "rt_profile_read": [P, I32, P, P],
     "rt_compute_paths": [P, P, ctypes.POINTER(rt_trace_params), P, I32, P, I32, P, P, P, P, P, P, P, P],
     "rt_last_candidate_count": [P, ctypes.POINTER(I64)],
+    "rt_scene_wedges": [P, I32, P, ctypes.POINTER(I32)],
+    "rt_compute_diffraction": [P, P, ctypes.c_double, P, I32, P, I32, I32, P, P, P, P, P, P, P],
     "rt_paths_power": [P, P, P, I64, I32, P],
     "rt_paths_power_grad": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), P, I32, I32, P, P,
                             P, P],

@@ -125,7 +125,7 @@ struct rt_scene {
     std::vector<rt_material> mats;
     std::vector<float> scat;   // scattering coefficient per material (empty: none)
     uint64_t scat_seed = 0;
-    DevBuf nodes, tris, shades, faces, face_tris, leaf_of_input;
+    DevBuf nodes, tris, shades, faces, face_tris, leaf_of_input, wedges;
     rt::DevScene dev{};
 };
 
@@ -427,6 +427,7 @@ rt_status rt_scene_create(rt_ctx* c, const float* V, int64_t nv, const int32_t* 
     std::vector<int32_t> leaf(h.tris.size());
     for (size_t k = 0; k < h.tris.size(); ++k) leaf[h.tris[k].orig] = (int32_t)k;
     up(s->leaf_of_input, leaf.data(), leaf.size() * sizeof(int32_t));
+    up(s->wedges, h.wedges.data(), h.wedges.size() * sizeof(rt::Wedge));
     if (e != hipSuccess) {
         rt_scene_destroy(s);
         return fail(e == hipErrorOutOfMemory ? RT_ERR_OOM : RT_ERR_DEVICE, hipGetErrorString(e));
@@ -441,6 +442,8 @@ rt_status rt_scene_create(rt_ctx* c, const float* V, int64_t nv, const int32_t* 
     s->dev.num_nodes = (int32_t)h.nodes.size();
     s->dev.stack_need = h.stack_need;
     s->dev.leaf_of_input = (const int32_t*)s->leaf_of_input.p;
+    s->dev.wedges = (const rt::Wedge*)s->wedges.p;
+    s->dev.num_wedges = (int32_t)h.wedges.size();
     *out = s;
     return RT_OK;
 }
@@ -471,7 +474,7 @@ rt_status rt_scene_info(const rt_scene* s, rt_scene_info_t* out) {
     out->num_materials = (int32_t)s->mats.size();
     out->bvh_nodes = (int64_t)s->host.nodes.size();
     out->bvh_depth = s->host.depth;
-    out->reserved = 0;
+    out->num_wedges = (int32_t)s->host.wedges.size();
     out->build_ms = s->host.build_ms;
     return RT_OK;
 }
@@ -485,7 +488,7 @@ rt_status rt_scene_face_ids(const rt_scene* s, int32_t* ids) {
 rt_status rt_scene_destroy(rt_scene* s) {
     if (!s) return RT_OK;
     if (s->ctx) (void)hipSetDevice(s->ctx->device);
-    for (DevBuf* b : {&s->nodes, &s->tris, &s->shades, &s->faces, &s->face_tris, &s->leaf_of_input})
+    for (DevBuf* b : {&s->nodes, &s->tris, &s->shades, &s->faces, &s->face_tris, &s->leaf_of_input, &s->wedges})
         if (b->p) (void)hipFree(b->p);
     delete s;
     return RT_OK;
@@ -842,6 +845,98 @@ rt_status rt_paths_power(rt_ctx* c, const float* a, const int32_t* depth, int64_
 rt_status rt_last_candidate_count(rt_ctx* c, int64_t* count) {
     if (!c || !count) return fail(RT_ERR_ARG, "NULL argument");
     *count = c->last_candidates;
+    return RT_OK;
+}
+
+rt_status rt_scene_wedges(const rt_scene* s, int32_t capacity, double* out, int32_t* count) {
+    if (!s || !count || (capacity > 0 && !out)) return fail(RT_ERR_ARG, "NULL argument");
+    const auto& w = s->host.wedges;
+    *count = (int32_t)w.size();
+    for (int32_t i = 0; i < capacity && i < (int32_t)w.size(); ++i) {
+        double* o = out + 16 * (size_t)i;
+        for (int k = 0; k < 3; ++k) {
+            o[k] = w[i].a[k];
+            o[3 + k] = w[i].e[k];
+            o[6 + k] = w[i].t0[k];
+            o[9 + k] = w[i].n0[k];
+        }
+        o[12] = w[i].len;
+        o[13] = w[i].n;
+        o[14] = w[i].face0;
+        o[15] = w[i].facen;
+    }
+    return RT_OK;
+}
+
+rt_status rt_compute_diffraction(rt_ctx* c, rt_scene* s, double freq_hz, const rt_device* tx, int32_t ntx,
+                                 const rt_device* rx, int32_t nrx, int32_t P, float* a, float* T, float* tau,
+                                 float* aod, float* aoa, int32_t* wedge, int32_t* num_paths) {
+    if (!c || !s || !tx || !rx || !a || !T || !tau || !aod || !aoa || !wedge || !num_paths)
+        return fail(RT_ERR_ARG, "NULL argument");
+    if (!(freq_hz > 0) || !std::isfinite(freq_hz)) return fail(RT_ERR_ARG, "freq_hz must be positive");
+    if (ntx < 1 || nrx < 1) return fail(RT_ERR_ARG, "need at least one tx and one rx");
+    if (P < 1 || P > 256) return fail(RT_ERR_ARG, "P must be in [1, 256]");
+    rt_status st;
+    for (int i = 0; i < ntx; ++i)
+        if ((st = check_device(tx + i, "tx", s->host.max_abs)) != RT_OK) return st;
+    for (int i = 0; i < nrx; ++i)
+        if ((st = check_device(rx + i, "rx", s->host.max_abs)) != RT_OK) return st;
+    RT_HIP(hipSetDevice(c->device));
+    const size_t per = (size_t)nrx * P;
+    // unsorted records (fd = 1: the wedge id in the faces slot), the sorted
+    // depths the sort writes, and the per-receiver counts
+    const size_t rec_bytes = per * (2 + 8 + 1 + 2 + 2) * sizeof(float) + per * 3 * sizeof(int32_t) +
+                             (size_t)nrx * sizeof(uint32_t);
+    RT_HIP(ensure(c->paths, rec_bytes));
+    RT_HIP(ensure(c->rx, (size_t)nrx * 3 * sizeof(double)));
+    RT_HIP(ensure(c->rx_ant, (size_t)nrx * sizeof(rt::Antenna)));
+    std::vector<double> rxp(3 * (size_t)nrx);
+    std::vector<rt::Antenna> rxa(nrx);
+    for (int i = 0; i < nrx; ++i) {
+        for (int k = 0; k < 3; ++k) rxp[3 * i + k] = rx[i].pos[k];
+        rxa[i] = make_antenna(rx + i);
+    }
+    RT_HIP(hipMemcpyAsync(c->rx.p, rxp.data(), rxp.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    RT_HIP(hipMemcpyAsync(c->rx_ant.p, rxa.data(), rxa.size() * sizeof(rt::Antenna), hipMemcpyHostToDevice,
+                          c->stream));
+    char* base = (char*)c->paths.p;
+    rt::PathArgs pa{};
+    pa.sc = s->dev;
+    pa.freq = freq_hz;
+    pa.lambda = kC0 / freq_hz;
+    pa.rx = (const double*)c->rx.p;
+    pa.rx_ant = (const rt::Antenna*)c->rx_ant.p;
+    pa.nrx = nrx;
+    pa.P = P;
+    pa.fd = 1;
+    pa.a = (float*)base; base += per * 2 * sizeof(float);
+    pa.T = (float*)base; base += per * 8 * sizeof(float);
+    pa.tau = (float*)base; base += per * sizeof(float);
+    pa.aod = (float*)base; base += per * 2 * sizeof(float);
+    pa.aoa = (float*)base; base += per * 2 * sizeof(float);
+    pa.depth = (int32_t*)base; base += per * sizeof(int32_t);
+    pa.faces = (int32_t*)base; base += per * sizeof(int32_t);
+    int32_t* depth_sorted = (int32_t*)base; base += per * sizeof(int32_t);
+    pa.counts = (uint32_t*)base;
+    rt::MatTable mats = make_mats(s, freq_hz);
+    int worst = 0;
+    std::vector<int32_t> counts_h(nrx);
+    for (int t = 0; t < ntx; ++t) {
+        for (int i = 0; i < 3; ++i) pa.tx[i] = tx[t].pos[i];
+        pa.tx_ant = make_antenna(tx + t);
+        RT_HIP(hipMemsetAsync(pa.counts, 0, (size_t)nrx * sizeof(uint32_t), c->stream));
+        RT_HIP(rt::launch_diffraction_paths(pa, mats, c->stream));
+        const size_t off = (size_t)t * per;
+        RT_HIP(rt::launch_sort_paths(pa, nrx, a + 2 * off, T + 8 * off, tau + off, aod + 2 * off, aoa + 2 * off,
+                                     depth_sorted, wedge + off, num_paths + (size_t)t * nrx, c->stream));
+        RT_HIP(hipMemcpyAsync(counts_h.data(), num_paths + (size_t)t * nrx, (size_t)nrx * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, c->stream));
+        RT_HIP(hipStreamSynchronize(c->stream));
+        for (int i = 0; i < nrx; ++i) worst = std::max(worst, counts_h[i]);
+    }
+    if (worst > P)
+        return fail(RT_ERR_CAPACITY, "a receiver has " + std::to_string(worst) +
+                                         " diffracted paths; raise P to at least that");
     return RT_OK;
 }
 

@@ -35,6 +35,8 @@ struct DevScene {
     int32_t num_nodes;
     int32_t stack_need;  // worst-case traversal stack entries of the tree
     const int32_t* leaf_of_input;  // [nt] leaf-order index of each input triangle
+    const Wedge* wedges;           // [num_wedges] diffraction wedges
+    int32_t num_wedges;
 };
 
 struct SbrArgs {
@@ -143,6 +145,9 @@ hipError_t launch_extract_pairs(const uint64_t* pairs, uint64_t pairs_cap, const
 hipError_t launch_extract_candidates(const uint64_t* table, uint64_t cap, int32_t max_depth, Cand* out,
                                      uint32_t* count, uint32_t max_out, hipStream_t s);
 hipError_t launch_image_paths(const PathArgs& a, const MatTable& mats, int64_t max_items, hipStream_t s);
+// First-order diffraction: one thread per (receiver, wedge) writes the valid
+// paths into the unsorted records of a (depth = 1, faces[0] = wedge id, fd = 1).
+hipError_t launch_diffraction_paths(const PathArgs& a, const MatTable& mats, hipStream_t s);
 hipError_t launch_sort_paths(const PathArgs& a, int32_t nrx, float* a_out, float* T_out, float* tau_out,
                              float* aod_out, float* aoa_out, int32_t* depth_out, int32_t* faces_out,
                              int32_t* num_paths_out, hipStream_t s);

@@ -68,6 +68,24 @@ struct alignas(32) Face {
 };
 static_assert(sizeof(Face) == 64, "face record size");
 
+// Wedge of the mesh for first-order diffraction: an edge shared by two
+// triangles of different faces whose solid interior angle alpha is below pi.
+// a: first vertex, e: unit edge direction, t0: unit vector in the 0-face
+// (the face with the smaller id) orthogonal to e pointing into the face, n0:
+// the 0-face's normal on the exterior side; n = 2 - alpha / pi (exterior
+// angle n pi).  128 bytes.
+struct alignas(16) Wedge {
+    double a[3];
+    double e[3];
+    double t0[3];
+    double n0[3];
+    double len;     // edge length
+    double n;
+    int32_t face0, facen;
+    int32_t mat0, matn;
+};
+static_assert(sizeof(Wedge) == 128, "wedge record size");
+
 // Material constants derived on the host at the carrier frequency.
 struct Mat {
     float eta_re, eta_im;      // complex relative permittivity eps_r - j sigma/(eps0 w)

@@ -9,6 +9,7 @@
 #include "scene.h"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -185,6 +186,83 @@ void cross(const double* a, const double* b, double* o) {
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 double norm(const double* a) { return std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
+
+// Wedges for first-order diffraction.  Mesh edges are matched by their two
+// vertex positions; an edge is a wedge when exactly two triangles of two
+// different faces share it, it does not lie on the ground (both vertices at
+// the lowest z of the scene), and the interior angle alpha between the faces'
+// half-planes (taken as the smaller one: convex solids) is below pi - 1e-6.
+// The edge runs from the first to the second vertex as they appear in the
+// lower-indexed triangle; the 0-face is the face with the smaller id.
+void extract_wedges(const float* V, const int32_t* F, int64_t nt, const int32_t* tri_mat, HostScene& out) {
+    using P3 = std::array<double, 3>;
+    auto vert = [&](int32_t i) { return P3{(double)V[3 * i], (double)V[3 * i + 1], (double)V[3 * i + 2]}; };
+    double zmin = INFINITY;
+    struct Use {
+        int64_t tri;
+        P3 third, p, q;
+    };
+    std::map<std::pair<P3, P3>, std::vector<Use>> edges;
+    for (int64_t k = 0; k < nt; ++k) {
+        for (int i = 0; i < 3; ++i) {
+            const P3 p = vert(F[3 * k + i]), q = vert(F[3 * k + (i + 1) % 3]), r = vert(F[3 * k + (i + 2) % 3]);
+            zmin = std::min(zmin, p[2]);
+            edges[p < q ? std::make_pair(p, q) : std::make_pair(q, p)].push_back(Use{k, r, p, q});
+        }
+    }
+    auto sub = [](const P3& a, const P3& b) { return P3{a[0] - b[0], a[1] - b[1], a[2] - b[2]}; };
+    auto dotp = [](const P3& a, const P3& b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+    auto into = [&](const P3& a, const P3& e, const P3& v) {
+        P3 w = sub(v, a);
+        const double d = dotp(w, e);
+        for (int i = 0; i < 3; ++i) w[i] -= d * e[i];
+        const double l = std::sqrt(dotp(w, w));
+        return P3{w[0] / l, w[1] / l, w[2] / l};
+    };
+    std::vector<std::pair<Wedge, P3>> ws;  // wedge and its second vertex (the sort key)
+    for (const auto& kv : edges) {
+        const auto& u = kv.second;
+        if (u.size() != 2) continue;
+        const int32_t f1 = out.face_of_input[u[0].tri], f2 = out.face_of_input[u[1].tri];
+        if (f1 == f2) continue;
+        const P3 a = u[0].p, b = u[0].q;
+        if (a[2] <= zmin && b[2] <= zmin) continue;
+        const P3 d = sub(b, a);
+        const double len = std::sqrt(dotp(d, d));
+        const P3 e{d[0] / len, d[1] / len, d[2] / len};
+        const P3 u1 = into(a, e, u[0].third), u2 = into(a, e, u[1].third);
+        const double alpha = std::acos(std::min(1.0, std::max(-1.0, dotp(u1, u2))));
+        if (alpha >= M_PI - 1e-6) continue;
+        const bool first0 = f1 < f2;
+        const P3 t0 = first0 ? u1 : u2, tn = first0 ? u2 : u1;
+        P3 n0{e[1] * t0[2] - e[2] * t0[1], e[2] * t0[0] - e[0] * t0[2], e[0] * t0[1] - e[1] * t0[0]};
+        if (dotp(n0, tn) > 0.0)
+            for (double& x : n0) x = -x;
+        Wedge w{};
+        for (int i = 0; i < 3; ++i) {
+            w.a[i] = a[i];
+            w.e[i] = e[i];
+            w.t0[i] = t0[i];
+            w.n0[i] = n0[i];
+        }
+        w.len = len;
+        w.n = 2.0 - alpha / M_PI;
+        w.face0 = first0 ? f1 : f2;
+        w.facen = first0 ? f2 : f1;
+        w.mat0 = tri_mat[first0 ? u[0].tri : u[1].tri];
+        w.matn = tri_mat[first0 ? u[1].tri : u[0].tri];
+        ws.emplace_back(w, b);
+    }
+    std::sort(ws.begin(), ws.end(), [](const std::pair<Wedge, P3>& x, const std::pair<Wedge, P3>& y) {
+        if (x.first.face0 != y.first.face0) return x.first.face0 < y.first.face0;
+        if (x.first.facen != y.first.facen) return x.first.facen < y.first.facen;
+        for (int i = 0; i < 3; ++i)
+            if (x.first.a[i] != y.first.a[i]) return x.first.a[i] < y.first.a[i];
+        return x.second < y.second;
+    });
+    out.wedges.clear();
+    for (const auto& w : ws) out.wedges.push_back(w.first);
+}
 
 }  // namespace
 
@@ -443,6 +521,7 @@ int build_scene(const float* V, int64_t nv, const int32_t* F, int64_t nt, const 
         int32_t f = out.face_of_input[k];
         out.face_tris[out.faces[f].first + fill[f]++] = new_of_old[k];
     }
+    extract_wedges(V, F, nt, tri_mat, out);
     out.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return 0;
 }

@@ -14,6 +14,7 @@ struct HostScene {
     std::vector<Face> faces;
     std::vector<int32_t> face_tris;   // per face, its triangles (leaf-order indices)
     std::vector<int32_t> face_of_input;
+    std::vector<Wedge> wedges;        // diffraction wedges, sorted by (face0, facen, a, end vertex)
     int32_t num_faces = 0;
     int depth = 0;                    // depth of the binary build tree
     int stack_need = 0;               // worst-case traversal stack entries of the 4-wide tree

@@ -134,7 +134,16 @@ class Scene:
     def info(self) -> dict:
         inf = L.rt_scene_info_t()
         check(lib.rt_scene_info(self.h, ctypes.byref(inf)))
-        return {k: getattr(inf, k) for k, _ in L.rt_scene_info_t._fields_ if k != "reserved"}
+        return {k: getattr(inf, k) for k, _ in L.rt_scene_info_t._fields_}
+
+    def wedges(self) -> np.ndarray:
+        """Diffraction wedges, float64 [count, 16]: a[3], e[3], t0[3], n0[3],
+        length, n, 0-face id, n-face id."""
+        n = ctypes.c_int32()
+        check(lib.rt_scene_wedges(self.h, 0, None, ctypes.byref(n)))
+        out = np.empty((max(n.value, 1), 16), dtype=np.float64)
+        check(lib.rt_scene_wedges(self.h, n.value, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
+        return out[:n.value]
 
     def face_ids(self) -> np.ndarray:
         out = np.empty(self.nt, dtype=np.int32)
@@ -244,6 +253,29 @@ def paths_power(ctx: Context, paths):
     ctx._bind_stream()
     check(lib.rt_paths_power(ctx.h, _ptr(a), _ptr(depth), ntx * nrx, P, _ptr(out)))
     return out
+
+
+def compute_diffraction(ctx: Context, scene: Scene, freq_hz: float, txs, rxs, P: int = 64):
+    """First-order diffraction paths for every (tx, rx); dict of device tensors
+    shaped [ntx, nrx, P, ...] (a, T, tau, aod, aoa, wedge) and num_paths."""
+    ntx, nrx = len(txs), len(rxs)
+    dev = ctx.torch_device
+    o = {
+        "a": torch.empty((ntx, nrx, P, 2), dtype=torch.float32, device=dev),
+        "T": torch.empty((ntx, nrx, P, 2, 2, 2), dtype=torch.float32, device=dev),
+        "tau": torch.empty((ntx, nrx, P), dtype=torch.float32, device=dev),
+        "aod": torch.empty((ntx, nrx, P, 2), dtype=torch.float32, device=dev),
+        "aoa": torch.empty((ntx, nrx, P, 2), dtype=torch.float32, device=dev),
+        "wedge": torch.empty((ntx, nrx, P), dtype=torch.int32, device=dev),
+        "num_paths": torch.empty((ntx, nrx), dtype=torch.int32, device=dev),
+    }
+    tx_arr = (L.rt_device * ntx)(*[device_struct(t) for t in txs])
+    rx_arr = (L.rt_device * nrx)(*[device_struct(r) for r in rxs])
+    ctx._bind_stream()
+    check(lib.rt_compute_diffraction(ctx.h, scene.h, float(freq_hz), tx_arr, ntx, rx_arr, nrx, int(P), _ptr(o["a"]),
+                                     _ptr(o["T"]), _ptr(o["tau"]), _ptr(o["aod"]), _ptr(o["aoa"]), _ptr(o["wedge"]),
+                                     _ptr(o["num_paths"])))
+    return o
 
 
 def last_candidate_count(ctx: Context) -> int:

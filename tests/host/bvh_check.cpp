@@ -6,7 +6,8 @@
 //
 // input  (binary): int64 nv, nt, nm, nr; float V[nv][3]; int32 F[nt][3];
 //                  int32 mat[nt]; double O[nr][3]; double D[nr][3]
-// output (binary): int32 face_of_input[nt]; int32 hit[nr]; double t[nr]
+// output (binary): int32 face_of_input[nt]; int32 hit[nr]; double t[nr];
+//                  int32 nw; double wedge[nw][16]
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -126,6 +127,23 @@ int main(int argc, char** argv) {
     fwrite(s.face_of_input.data(), 4, nt, g);
     fwrite(hit.data(), 4, nr, g);
     fwrite(th.data(), 8, nr, g);
+    // diffraction wedges: count, then per wedge a[3] e[3] t0[3] n0[3] length n face0 facen
+    const int32_t nw = (int32_t)s.wedges.size();
+    fwrite(&nw, 4, 1, g);
+    for (const Wedge& w : s.wedges) {
+        double rec[16];
+        for (int i = 0; i < 3; ++i) {
+            rec[i] = w.a[i];
+            rec[3 + i] = w.e[i];
+            rec[6 + i] = w.t0[i];
+            rec[9 + i] = w.n0[i];
+        }
+        rec[12] = w.len;
+        rec[13] = w.n;
+        rec[14] = w.face0;
+        rec[15] = w.facen;
+        fwrite(rec, 8, 16, g);
+    }
     fclose(g);
     printf("nodes %zu depth %d stack %d faces %d\n", s.nodes.size(), s.depth, s.stack_need, s.num_faces);
     return 0;

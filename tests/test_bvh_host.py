@@ -44,8 +44,11 @@ def _run(exe, s, O, D):
     nt, nr = s.nt, len(O)
     faces = np.frombuffer(raw[:4 * nt], dtype=np.int32)
     hit = np.frombuffer(raw[4 * nt:4 * nt + 4 * nr], dtype=np.int32)
-    t = np.frombuffer(raw[4 * nt + 4 * nr:], dtype=np.float64)
-    return faces, hit, t
+    off = 4 * nt + 4 * nr + 8 * nr
+    t = np.frombuffer(raw[4 * nt + 4 * nr:off], dtype=np.float64)
+    nw = int(np.frombuffer(raw[off:off + 4], dtype=np.int32)[0])
+    wedges = np.frombuffer(raw[off + 4:], dtype=np.float64).reshape(nw, 16)
+    return faces, hit, t, wedges
 
 
 @pytest.mark.parametrize("name", ["toy", "urban", "city"])
@@ -53,7 +56,7 @@ def test_bvh_closest_hits_and_faces_match_oracle(checker, name):
     s = {"toy": sg.make_toy, "urban": lambda: sg.make_urban(0), "city": lambda: sg.make_city(0, blocks=10)}[name]()
     lo, hi = (-90, 90) if name == "toy" else (-230, 230) if name == "urban" else (-200, 200)
     O, D = sg.random_rays(3000, seed=3, lo=lo, hi=hi, zlo=0.5, zhi=80)
-    faces, hit, t = _run(checker, s, O, D)
+    faces, hit, t, _ = _run(checker, s, O, D)
     ref_faces, _ = geom.face_ids(s.V, s.F, s.tri_mat)
     assert np.array_equal(faces, ref_faces)
     g = geom.Geometry(s)
@@ -63,3 +66,21 @@ def test_bvh_closest_hits_and_faces_match_oracle(checker, name):
     assert np.array_equal(hit[ok], tri[ok])
     h = ok & (tri >= 0)
     assert np.max(np.abs(t[h] - tt[h]) / (1 + tt[h])) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["toy", "urban", "city"])
+def test_diffraction_wedges_match_oracle(checker, name):
+    """The host extraction of diffraction wedges equals the oracle's: same
+    wedges in the same order, same frames and exterior angles."""
+    from oracle import diffraction
+    s = {"toy": sg.make_toy, "urban": lambda: sg.make_urban(0), "city": lambda: sg.make_city(0, blocks=6)}[name]()
+    O, D = sg.random_rays(4, seed=3, lo=-50, hi=50, zlo=0.5, zhi=80)
+    _, _, _, wg = _run(checker, s, O, D)
+    ref = diffraction.wedges(geom.Geometry(s))
+    assert len(ref) == wg.shape[0] > 0
+    for w, r in zip(ref, wg):
+        assert np.array_equal(w.a, r[0:3])
+        assert np.allclose(w.e, r[3:6], atol=1e-15) and np.allclose(w.t0, r[6:9], atol=1e-15)
+        assert np.allclose(w.n0, r[9:12], atol=1e-15)
+        assert abs(w.length - r[12]) < 1e-12 * w.length and abs(w.n - r[13]) < 1e-14
+        assert (w.face0, w.facen) == (int(r[14]), int(r[15]))
