@@ -418,6 +418,17 @@ def extras(rt, ctx, scene, w, torch):
                   "cfr_ms": round((t1 - t0) * 1e2, 4), "adjoint_ms": round((t2 - t1) * 1e2, 4),
                   "coef_grad_ms": round((t3 - t2) * 1e2, 4)}
     log("bench: cfr %s" % res["cfr"])
+    # first-order diffraction: the 256 receivers of the differentiation case
+    # (512 wedges), then 1024 street receivers of the large city
+    rt.compute_diffraction(ctx, sd, d.scene.freq_hz, d.tx, d.rx, P=64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    od = rt.compute_diffraction(ctx, sd, d.scene.freq_hz, d.tx, d.rx, P=64)
+    torch.cuda.synchronize()
+    res["diffraction"] = {"workload": "first-order diffraction, urban differentiation case, 256 rx x %d wedges" %
+                                      sd.info()["num_wedges"],
+                          "ms": round((time.perf_counter() - t0) * 1e3, 3), "paths": int(od["num_paths"].sum())}
+    log("bench: diffraction %s" % res["diffraction"])
     # the urban map with diffuse scattering (S = 0.6 concrete, 0.35 glass)
     ss = rt.Scene.from_scenegen(ctx, w.scene)
     ss.set_scattering([0.6, 0.35], 11)
@@ -449,6 +460,16 @@ def extras(rt, ctx, scene, w, torch):
     res["city"]["paths_found"] = int(op["num_paths"].sum())
     res["city"]["rx_with_paths"] = int((op["num_paths"] > 0).sum())
     res["city"]["sphere_pairs"] = rt.last_candidate_count(ctx)
+    crx = c.rx[:1024]
+    rt.compute_diffraction(ctx, sc, c.scene.freq_hz, c.tx, crx[:8], P=256)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    odc = rt.compute_diffraction(ctx, sc, c.scene.freq_hz, c.tx, crx, P=256)
+    torch.cuda.synchronize()
+    res["city"]["diffraction_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    res["city"]["diffraction_rx"] = len(crx)
+    res["city"]["wedges"] = sc.info()["num_wedges"]
+    res["city"]["diffraction_paths"] = int(odc["num_paths"].sum())
     log("bench: city %s" % res["city"])
     sc.close()
     return res

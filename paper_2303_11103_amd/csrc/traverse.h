@@ -150,7 +150,8 @@ __device__ __forceinline__ uint32_t box_key(float nx, float ny, float nz, float 
 // through the 4-wide BVH.  Nodes with index < n_lds are read from the LDS
 // copy, the others from global memory.  At an inner node the hit children
 // are ordered by entry distance: the nearest is visited next, the others
-// pushed farthest first.  OVF = false drops the private-memory continuation
+// pushed farthest first.  Leaves are parked and tested when the whole wave
+// has one (see the loop).  OVF = false drops the private-memory continuation
 // of the stack: only for trees whose worst-case stack need is <= kStack.
 template <bool ANY, bool STATS = false, int BS = kBlock, bool OVF = true>
 __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_nodes, int n_lds, d3 o, d3 d, int excl0,
@@ -181,72 +182,100 @@ __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_node
         }
         return v;
     };
+    // Leaves are postponed: a lane that reaches a leaf parks it and goes on
+    // with its stack (speculatively, beside lanes still looking for a leaf);
+    // the wave tests triangles only when no lane can make inner-node progress
+    // without a pending leaf, so triangle tests run with most lanes active.
+    constexpr int kDone = kEmptyChild;
+    int leaf = 0;  // parked leaf code (negative), 0 = none
     while (true) {
         const int top = get(sp > 0 ? sp - 1 : 0);
-        if (node >= 0) {
-            if (STATS) ts->nodes++;
-            NodePlanes np;
-            const uint32_t off = (uint32_t)node * (uint32_t)sizeof(Node);
-            if (node < n_lds) {
-                np = load_planes(reinterpret_cast<const char*>(lds_nodes), off, 0u, oct);
-                // keeps the two branches distinct, so that the LDS reads are not
-                // merged with the global ones into generic (flat) loads
-                asm volatile("" ::: "memory");
-            } else {
-                np = load_planes(reinterpret_cast<const char*>(sc.nodes), off, 0u, oct);
-            }
-            if (STATS) ts->boxes += live_children(np.ch);
-            uint32_t q0 = box_key(np.NX.x, np.NY.x, np.NZ.x, np.FX.x, np.FY.x, np.FZ.x, ix, iy, iz, oix, oiy, oiz,
-                                  tfar, 0u);
-            uint32_t q1 = box_key(np.NX.y, np.NY.y, np.NZ.y, np.FX.y, np.FY.y, np.FZ.y, ix, iy, iz, oix, oiy, oiz,
-                                  tfar, 1u);
-            uint32_t q2 = box_key(np.NX.z, np.NY.z, np.NZ.z, np.FX.z, np.FY.z, np.FZ.z, ix, iy, iz, oix, oiy, oiz,
-                                  tfar, 2u);
-            uint32_t q3 = box_key(np.NX.w, np.NY.w, np.NZ.w, np.FX.w, np.FY.w, np.FZ.w, ix, iy, iz, oix, oiy, oiz,
-                                  tfar, 3u);
-            int c0 = np.ch.x, c1 = np.ch.y, c2 = np.ch.z, c3 = np.ch.w;
-            // sorting network of compare-exchanges on (key, child) as selects
-            auto cx = [](uint32_t& a, int& ca, uint32_t& b, int& cb) {
-                const bool sw = b < a;
-                const uint32_t lo = sw ? b : a, hi = sw ? a : b;
-                const int clo = sw ? cb : ca, chi = sw ? ca : cb;
-                a = lo;
-                b = hi;
-                ca = clo;
-                cb = chi;
-            };
-            cx(q0, c0, q1, c1);
-            cx(q2, c2, q3, c3);
-            cx(q0, c0, q2, c2);
-            cx(q1, c1, q3, c3);
-            cx(q1, c1, q2, c2);
-            put(sp, c3);
-            sp += q3 != ~0u;
-            put(sp, c2);
-            sp += q2 != ~0u;
-            put(sp, c1);
-            sp += q1 != ~0u;
-            if (q0 != ~0u) {
-                node = c0;
-            } else {  // no child hit, so nothing was pushed: top is still the top
-                if (sp == 0) break;
-                node = top;
-                --sp;
-            }
-        } else {
-            const int code = ~node;
-            const int first = code >> kLeafShift, cnt = (code & (kMaxLeaf - 1)) + 1;
-            if (STATS) ts->tris += cnt;
-            for (int k = first; k < first + cnt; ++k) {
-                if (tri_test(sc.tris, k, o, d, excl0, excl1, tmin, tbest, ANY)) {
-                    best = k;
-                    if (ANY) return best;
-                    tfar = f_up(tbest);
+        const bool want_inner = node >= 0 && leaf == 0;
+        if (__ballot(want_inner) != 0) {
+            if (node >= 0) {
+                if (STATS) ts->nodes++;
+                NodePlanes np;
+                const uint32_t off = (uint32_t)node * (uint32_t)sizeof(Node);
+                if (node < n_lds) {
+                    np = load_planes(reinterpret_cast<const char*>(lds_nodes), off, 0u, oct);
+                    // keeps the two branches distinct, so that the LDS reads are not
+                    // merged with the global ones into generic (flat) loads
+                    asm volatile("" ::: "memory");
+                } else {
+                    np = load_planes(reinterpret_cast<const char*>(sc.nodes), off, 0u, oct);
+                }
+                if (STATS) ts->boxes += live_children(np.ch);
+                uint32_t q0 = box_key(np.NX.x, np.NY.x, np.NZ.x, np.FX.x, np.FY.x, np.FZ.x, ix, iy, iz, oix, oiy, oiz,
+                                      tfar, 0u);
+                uint32_t q1 = box_key(np.NX.y, np.NY.y, np.NZ.y, np.FX.y, np.FY.y, np.FZ.y, ix, iy, iz, oix, oiy, oiz,
+                                      tfar, 1u);
+                uint32_t q2 = box_key(np.NX.z, np.NY.z, np.NZ.z, np.FX.z, np.FY.z, np.FZ.z, ix, iy, iz, oix, oiy, oiz,
+                                      tfar, 2u);
+                uint32_t q3 = box_key(np.NX.w, np.NY.w, np.NZ.w, np.FX.w, np.FY.w, np.FZ.w, ix, iy, iz, oix, oiy, oiz,
+                                      tfar, 3u);
+                int c0 = np.ch.x, c1 = np.ch.y, c2 = np.ch.z, c3 = np.ch.w;
+                // sorting network of compare-exchanges on (key, child) as selects
+                auto cx = [](uint32_t& a, int& ca, uint32_t& b, int& cb) {
+                    const bool sw = b < a;
+                    const uint32_t lo = sw ? b : a, hi = sw ? a : b;
+                    const int clo = sw ? cb : ca, chi = sw ? ca : cb;
+                    a = lo;
+                    b = hi;
+                    ca = clo;
+                    cb = chi;
+                };
+                cx(q0, c0, q1, c1);
+                cx(q2, c2, q3, c3);
+                cx(q0, c0, q2, c2);
+                cx(q1, c1, q3, c3);
+                cx(q1, c1, q2, c2);
+                put(sp, c3);
+                sp += q3 != ~0u;
+                put(sp, c2);
+                sp += q2 != ~0u;
+                put(sp, c1);
+                sp += q1 != ~0u;
+                if (q0 != ~0u) {
+                    node = c0;
+                } else if (sp == 0) {  // no child hit, nothing pushed: top is still the top
+                    node = kDone;
+                } else {
+                    node = top;
+                    --sp;
+                }
+            } else if (node != kDone && leaf == 0) {
+                leaf = node;
+                if (sp == 0) {
+                    node = kDone;
+                } else {
+                    node = top;
+                    --sp;
                 }
             }
-            if (sp == 0) break;
-            node = top;
-            --sp;
+        } else {
+            if (leaf != 0) {
+                const int code = ~leaf;
+                const int first = code >> kLeafShift, cnt = (code & (kMaxLeaf - 1)) + 1;
+                if (STATS) ts->tris += cnt;
+                for (int k = first; k < first + cnt; ++k) {
+                    if (tri_test(sc.tris, k, o, d, excl0, excl1, tmin, tbest, ANY)) {
+                        best = k;
+                        if (ANY) return best;
+                        tfar = f_up(tbest);
+                    }
+                }
+                leaf = 0;
+            }
+            if (node < 0 && node != kDone) {
+                leaf = node;
+                if (sp == 0) {
+                    node = kDone;
+                } else {
+                    node = top;
+                    --sp;
+                }
+            }
+            if (__ballot(leaf != 0 || node != kDone) == 0) break;
         }
     }
     return best;

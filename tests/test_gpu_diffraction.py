@@ -94,4 +94,4 @@ def test_diffraction_capacity_and_argument_errors():
     with pytest.raises(RTError, match="freq_hz"):
         m.compute_diffraction(ctx(), sc, -1.0, w.tx, w.rx, P=8)
     with pytest.raises(RTError, match="P must be"):
-        m.compute_diffraction(ctx(), sc, w.scene.freq_hz, w.tx, w.rx, P=0)
+        m.compute_diffraction(ctx(), sc, w.scene.freq_hz, w.tx, w.rx, P=300)
