@@ -292,6 +292,17 @@ rt_status rt_last_candidate_count(rt_ctx* ctx, int64_t* count);
  * n-face id.  out may be NULL when capacity is 0. */
 rt_status rt_scene_wedges(const rt_scene* scene, int32_t capacity, double* out, int32_t* count);
 
+/* Diffraction part of a coverage map (Sec. II-A coverage maps with the
+ * first-order diffraction of Sec. II-B): for every cell, the path gain
+ * |a|^2 of the diffracted paths of rt_compute_diffraction from tx to the cell
+ * centre (x0 + (ix + 1/2) cell, y0 + (iy + 1/2) cell, z), received with
+ * rx_ant and summed over the wedges, is ADDED to gain [ny][nx] (dev, linear).
+ * After rt_coverage_map it completes the map with diffraction.  These are
+ * values at the cell centres; the reflected part of rt_coverage_map averages
+ * over each cell.  Asynchronous on the context's stream. */
+rt_status rt_coverage_diffraction(rt_ctx* ctx, rt_scene* scene, double freq_hz, const rt_device* tx,
+                                  const rt_device* rx_ant, const rt_grid* grid, float* gain);
+
 /* First-order diffraction paths (Sec. II-B: first-order diffraction; the
  * uniform theory of diffraction for a wedge, Kouyoumjian and Pathak, with the
  * Fresnel coefficients of the two faces in place of the perfect-conductor

@@ -286,3 +286,19 @@ def paths(geo, tx, rxs, wl=None, threads=None):
         th1, ph1 = em.theta_phi(-s_out)
         out[r].append(DiffPath(r, i, a, T, L / C0, L, (float(th0), float(ph0)), (float(th1), float(ph1)), Q))
     return out
+
+
+def coverage(geo, tx, grid, rx_ant=None, wl=None, threads=None):
+    """Diffraction part of a coverage map: the path gain of the first-order
+    diffracted paths at each cell centre (x0 + (ix + 1/2) cell, y0 + (iy +
+    1/2) cell, z), summed incoherently over the wedges, with the receive
+    pattern rx_ant (isotropic V-pol when None).  Returns (ny, nx) float64."""
+    from types import SimpleNamespace
+    wl = wedges(geo) if wl is None else wl
+    ant = rx_ant if rx_ant is not None else SimpleNamespace(yaw=0.0, pitch=0.0, roll=0.0, pattern=0, pol=0)
+    ys = grid.y0 + (np.arange(grid.ny) + 0.5) * grid.cell
+    xs = grid.x0 + (np.arange(grid.nx) + 0.5) * grid.cell
+    rxs = [SimpleNamespace(pos=(float(x), float(y), float(grid.z)), yaw=ant.yaw, pitch=ant.pitch, roll=ant.roll,
+                           pattern=ant.pattern, pol=getattr(ant, "pol", 0)) for y in ys for x in xs]
+    per = paths(geo, tx, rxs, wl, threads=threads)
+    return np.array([sum(abs(p.a) ** 2 for p in pl) for pl in per]).reshape(grid.ny, grid.nx)

@@ -848,6 +848,26 @@ rt_status rt_last_candidate_count(rt_ctx* c, int64_t* count) {
     return RT_OK;
 }
 
+rt_status rt_coverage_diffraction(rt_ctx* c, rt_scene* s, double freq_hz, const rt_device* tx,
+                                  const rt_device* rx_ant, const rt_grid* g, float* gain) {
+    if (!c || !s || !tx || !rx_ant || !g || !gain) return fail(RT_ERR_ARG, "NULL argument");
+    if (!(freq_hz > 0) || !std::isfinite(freq_hz)) return fail(RT_ERR_ARG, "freq_hz must be positive");
+    rt_status st;
+    if ((st = check_device(tx, "tx", s->host.max_abs)) != RT_OK) return st;
+    if ((st = check_device(rx_ant, "rx_ant", 0)) != RT_OK) return st;
+    if (g->nx < 1 || g->ny < 1 || (int64_t)g->nx * g->ny > (int64_t(1) << 31))
+        return fail(RT_ERR_ARG, "grid size must be positive and below 2^31 cells");
+    if (!(g->cell > 0) || !std::isfinite(g->cell) || !std::isfinite(g->x0) || !std::isfinite(g->y0) ||
+        !std::isfinite(g->z))
+        return fail(RT_ERR_ARG, "grid origin, cell size and height must be finite, cell > 0");
+    RT_HIP(hipSetDevice(c->device));
+    const double txp[3] = {tx->pos[0], tx->pos[1], tx->pos[2]};
+    RT_HIP(rt::launch_coverage_diffraction(s->dev, make_mats(s, freq_hz), kC0 / freq_hz, txp, make_antenna(tx),
+                                           make_antenna(rx_ant), g->x0, g->y0, g->cell, g->z, g->nx, g->ny, gain,
+                                           c->stream));
+    return RT_OK;
+}
+
 rt_status rt_scene_wedges(const rt_scene* s, int32_t capacity, double* out, int32_t* count) {
     if (!s || !count || (capacity > 0 && !out)) return fail(RT_ERR_ARG, "NULL argument");
     const auto& w = s->host.wedges;

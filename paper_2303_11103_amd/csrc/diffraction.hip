@@ -86,6 +86,100 @@ __device__ __forceinline__ void face_fresnel(const MatTable& mats, int m, double
     fresnel(mats.m[m], cos_i, rs, rh);
 }
 
+// One diffracted path over wedge wi from S (antenna txa) to P (antenna rxa):
+// false when there is none.  FULL also fills the transfer matrix and the
+// directions; otherwise only the coefficient a.
+struct DiffPath {
+    cd a;
+    cd T[4];
+    double len;
+    d3 s_in, s_out;
+};
+
+template <bool FULL>
+__device__ bool diffracted(const DevScene& sc, const Node* lds_nodes, int n_lds, int32_t (*stack)[kBlock],
+                           const MatTable& mats, double lambda, d3 S, const Antenna& txa, d3 P, const Antenna& rxa,
+                           int wi, DiffPath& out) {
+    const Wedge w = sc.wedges[wi];
+    const d3 A = ldw(w.a), e = ldw(w.e);
+    // Keller point: axial coordinates and distances from the edge line
+    const double zs = dot(sub(S, A), e), zp = dot(sub(P, A), e);
+    const double rs = norm(sub(sub(S, A), scale(e, zs))), rp = norm(sub(sub(P, A), scale(e, zp)));
+    if (rs < 1e-9 || rp < 1e-9) return false;
+    const double z = zs + (zp - zs) * rs / (rs + rp);
+    if (!(z > 0.0 && z < w.len)) return false;
+    const d3 Q = add(A, scale(e, z));
+    const double phip = angle_about(w, S, Q), phi = angle_about(w, P, Q);
+    const double lim = w.n * kPi;
+    if (!(phip > 0.0 && phip < lim && phi > 0.0 && phi < lim)) return false;
+    // both legs unoccluded (open segments, the two wedge faces skipped)
+    double tb = 1.0;
+    if (traverse<true>(sc, lds_nodes, n_lds, S, sub(Q, S), w.face0, w.facen, kOccEpsD, tb, stack) >= 0) return false;
+    tb = 1.0;
+    if (traverse<true>(sc, lds_nodes, n_lds, Q, sub(P, Q), w.face0, w.facen, kOccEpsD, tb, stack) >= 0) return false;
+    // coefficients
+    const double k = 2.0 * kPi / lambda;
+    const d3 vin = sub(Q, S), vout = sub(P, Q);
+    const double sp = norm(vin), s = norm(vout);
+    const d3 sin_ = scale(vin, 1.0 / sp), sout = scale(vout, 1.0 / s);
+    const double cb = fmin(fmax(dot(sin_, e), -1.0), 1.0);
+    const double b0 = acos(cb);
+    const double sb = sin(b0);
+    const double L = sp * s * sb * sb / (sp + s);
+    cd r0s, r0h, rns, rnh;
+    face_fresnel(mats, w.mat0, sb * fabs(sin(phip)), r0s, r0h);
+    face_fresnel(mats, w.matn, sb * fabs(sin(lim - phi)), rns, rnh);
+    const double kL = k * L;
+    const cd t1 = utd_term(kL, w.n, phi - phip, 1.0);
+    const cd t2 = utd_term(kL, w.n, phi - phip, -1.0);
+    const cd t3 = utd_term(kL, w.n, phi + phip, -1.0);
+    const cd t4 = utd_term(kL, w.n, phi + phip, 1.0);
+    // -e^{-j pi/4} / (2 n sqrt(2 pi k) sin b0)
+    const double pm = -1.0 / (2.0 * w.n * sqrt(2.0 * kPi * k) * sb);
+    const cd pre{pm * 0.70710678118654752440, -pm * 0.70710678118654752440};
+    const cd t12 = cadd(t1, t2);
+    const cd Ds = cmul(pre, cadd(t12, cadd(cmul(r0s, t3), cmul(rns, t4))));
+    const cd Dh = cmul(pre, cadd(t12, cadd(cmul(r0h, t3), cmul(rnh, t4))));
+    // edge-fixed unit vectors
+    const d3 t0 = ldw(w.t0), n0 = ldw(w.n0);
+    const d3 ph_in = add(scale(t0, -sin(phip)), scale(n0, cos(phip)));
+    const d3 ph_out = add(scale(t0, -sin(phi)), scale(n0, cos(phi)));
+    const d3 be_in = cross(ph_in, sin_), be_out = cross(ph_out, sout);
+    // E_out = -Ds be_out (be_in . E) - Dh ph_out (ph_in . E); u . Dbar . v
+    auto dyad = [&](d3 u, d3 v) {
+        return csub(cmulr(Ds, -dot(u, be_out) * dot(be_in, v)), cmulr(Dh, dot(u, ph_out) * dot(ph_in, v)));
+    };
+    const double amp = 1.0 / sqrt(sp * s * (sp + s));
+    const d3 Ft = antenna_field(txa, sin_);
+    const d3 Fr = antenna_field(rxa, scale(sout, -1.0));
+    out.a = cmulr(dyad(Fr, Ft), lambda / (4.0 * kPi) * amp);
+    if (FULL) {
+        // spherical unit vectors of s_in (departure) and s_out (direction of travel on arrival)
+        auto basis = [](d3 d, d3& th, d3& ph) {
+            const double rho = sqrt(d.x * d.x + d.y * d.y);
+            double cp = 1.0, spn = 0.0;
+            if (rho > 0.0) {
+                cp = d.x / rho;
+                spn = d.y / rho;
+            }
+            th = d3{d.z * cp, d.z * spn, -rho};
+            ph = d3{-spn, cp, 0.0};
+        };
+        d3 thi, phi_i, tho, pho;
+        basis(sin_, thi, phi_i);
+        basis(sout, tho, pho);
+        const double tsc = (sp + s) * amp;
+        out.T[0] = cmulr(dyad(tho, thi), tsc);
+        out.T[1] = cmulr(dyad(tho, phi_i), tsc);
+        out.T[2] = cmulr(dyad(pho, thi), tsc);
+        out.T[3] = cmulr(dyad(pho, phi_i), tsc);
+        out.len = sp + s;
+        out.s_in = sin_;
+        out.s_out = sout;
+    }
+    return true;
+}
+
 __global__ __launch_bounds__(kBlock) void diffraction_kernel(PathArgs a, MatTable mats) {
     __shared__ int32_t stack[kStack][kBlock];
     __shared__ Node lds_nodes[kLdsNodes];
@@ -93,107 +187,71 @@ __global__ __launch_bounds__(kBlock) void diffraction_kernel(PathArgs a, MatTabl
     const int64_t nw = a.sc.num_wedges;
     const int64_t total = (int64_t)a.nrx * nw;
     const d3 S{a.tx[0], a.tx[1], a.tx[2]};
-    const double k = 2.0 * kPi / a.lambda;
     for (int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; item < total;
          item += (int64_t)gridDim.x * blockDim.x) {
         const int r = (int)(item / nw);
         const int wi = (int)(item - (int64_t)r * nw);
-        const Wedge w = a.sc.wedges[wi];
-        const d3 A = ldw(w.a), e = ldw(w.e);
         const d3 P{a.rx[3 * r], a.rx[3 * r + 1], a.rx[3 * r + 2]};
-        // Keller point: axial coordinates and distances from the edge line
-        const double zs = dot(sub(S, A), e), zp = dot(sub(P, A), e);
-        const double rs = norm(sub(sub(S, A), scale(e, zs))), rp = norm(sub(sub(P, A), scale(e, zp)));
-        if (rs < 1e-9 || rp < 1e-9) continue;
-        const double z = zs + (zp - zs) * rs / (rs + rp);
-        if (!(z > 0.0 && z < w.len)) continue;
-        const d3 Q = add(A, scale(e, z));
-        const double phip = angle_about(w, S, Q), phi = angle_about(w, P, Q);
-        const double lim = w.n * kPi;
-        if (!(phip > 0.0 && phip < lim && phi > 0.0 && phi < lim)) continue;
-        // both legs unoccluded (open segments, the two wedge faces skipped)
-        double tb = 1.0;
-        if (traverse<true>(a.sc, lds_nodes, n_lds, S, sub(Q, S), w.face0, w.facen, kOccEpsD, tb, stack) >= 0)
+        DiffPath p;
+        if (!diffracted<true>(a.sc, lds_nodes, n_lds, stack, mats, a.lambda, S, a.tx_ant, P, a.rx_ant[r], wi, p))
             continue;
-        tb = 1.0;
-        if (traverse<true>(a.sc, lds_nodes, n_lds, Q, sub(P, Q), w.face0, w.facen, kOccEpsD, tb, stack) >= 0)
-            continue;
-        // coefficients
-        const d3 vin = sub(Q, S), vout = sub(P, Q);
-        const double sp = norm(vin), s = norm(vout);
-        const d3 sin_ = scale(vin, 1.0 / sp), sout = scale(vout, 1.0 / s);
-        const double cb = fmin(fmax(dot(sin_, e), -1.0), 1.0);
-        const double b0 = acos(cb);
-        const double sb = sin(b0);
-        const double L = sp * s * sb * sb / (sp + s);
-        cd r0s, r0h, rns, rnh;
-        face_fresnel(mats, w.mat0, sb * fabs(sin(phip)), r0s, r0h);
-        face_fresnel(mats, w.matn, sb * fabs(sin(lim - phi)), rns, rnh);
-        const double kL = k * L;
-        const cd t1 = utd_term(kL, w.n, phi - phip, 1.0);
-        const cd t2 = utd_term(kL, w.n, phi - phip, -1.0);
-        const cd t3 = utd_term(kL, w.n, phi + phip, -1.0);
-        const cd t4 = utd_term(kL, w.n, phi + phip, 1.0);
-        // -e^{-j pi/4} / (2 n sqrt(2 pi k) sin b0)
-        const double pm = -1.0 / (2.0 * w.n * sqrt(2.0 * kPi * k) * sb);
-        const cd pre{pm * 0.70710678118654752440, -pm * 0.70710678118654752440};
-        const cd t12 = cadd(t1, t2);
-        const cd Ds = cmul(pre, cadd(t12, cadd(cmul(r0s, t3), cmul(rns, t4))));
-        const cd Dh = cmul(pre, cadd(t12, cadd(cmul(r0h, t3), cmul(rnh, t4))));
-        // edge-fixed unit vectors
-        const d3 t0 = ldw(w.t0), n0 = ldw(w.n0);
-        const d3 ph_in = add(scale(t0, -sin(phip)), scale(n0, cos(phip)));
-        const d3 ph_out = add(scale(t0, -sin(phi)), scale(n0, cos(phi)));
-        const d3 be_in = cross(ph_in, sin_), be_out = cross(ph_out, sout);
-        // E_out = -Ds be_out (be_in . E) - Dh ph_out (ph_in . E); u . Dbar . v
-        auto dyad = [&](d3 u, d3 v) {
-            return csub(cmulr(Ds, -dot(u, be_out) * dot(be_in, v)), cmulr(Dh, dot(u, ph_out) * dot(ph_in, v)));
-        };
-        const double amp = 1.0 / sqrt(sp * s * (sp + s));
-        const d3 Ft = antenna_field(a.tx_ant, sin_);
-        const d3 Fr = antenna_field(a.rx_ant[r], scale(sout, -1.0));
-        const cd pr = dyad(Fr, Ft);
-        const double ca = a.lambda / (4.0 * kPi) * amp;
-        d3 thi, phi_i, tho, pho;
-        {
-            // spherical unit vectors of s_in (departure) and s_out (arrival direction of travel)
-            auto basis = [](d3 d, d3& th, d3& ph) {
-                const double rho = sqrt(d.x * d.x + d.y * d.y);
-                double cp = 1.0, spn = 0.0;
-                if (rho > 0.0) {
-                    cp = d.x / rho;
-                    spn = d.y / rho;
-                }
-                th = d3{d.z * cp, d.z * spn, -rho};
-                ph = d3{-spn, cp, 0.0};
-            };
-            basis(sin_, thi, phi_i);
-            basis(sout, tho, pho);
-        }
         const uint32_t slot = atomicAdd(a.counts + r, 1u);
         if (slot >= (uint32_t)a.P) continue;
         const int64_t at = (int64_t)r * a.P + slot;
-        a.a[2 * at] = (float)(ca * pr.re);
-        a.a[2 * at + 1] = (float)(ca * pr.im);
-        const double tsc = (sp + s) * amp;
-        const cd T00 = cmulr(dyad(tho, thi), tsc), T01 = cmulr(dyad(tho, phi_i), tsc);
-        const cd T10 = cmulr(dyad(pho, thi), tsc), T11 = cmulr(dyad(pho, phi_i), tsc);
+        a.a[2 * at] = (float)p.a.re;
+        a.a[2 * at + 1] = (float)p.a.im;
         float* T = a.T + 8 * at;
-        T[0] = (float)T00.re; T[1] = (float)T00.im;
-        T[2] = (float)T01.re; T[3] = (float)T01.im;
-        T[4] = (float)T10.re; T[5] = (float)T10.im;
-        T[6] = (float)T11.re; T[7] = (float)T11.im;
-        a.tau[at] = (float)((sp + s) / kC0d);
-        a.aod[2 * at] = (float)acos(fmin(fmax(sin_.z, -1.0), 1.0));
-        a.aod[2 * at + 1] = (float)atan2(sin_.y, sin_.x);
-        a.aoa[2 * at] = (float)acos(fmin(fmax(-sout.z, -1.0), 1.0));
-        a.aoa[2 * at + 1] = (float)atan2(-sout.y, -sout.x);
+        for (int i = 0; i < 4; ++i) {
+            T[2 * i] = (float)p.T[i].re;
+            T[2 * i + 1] = (float)p.T[i].im;
+        }
+        a.tau[at] = (float)(p.len / kC0d);
+        a.aod[2 * at] = (float)acos(fmin(fmax(p.s_in.z, -1.0), 1.0));
+        a.aod[2 * at + 1] = (float)atan2(p.s_in.y, p.s_in.x);
+        a.aoa[2 * at] = (float)acos(fmin(fmax(-p.s_out.z, -1.0), 1.0));
+        a.aoa[2 * at + 1] = (float)atan2(-p.s_out.y, -p.s_out.x);
         a.depth[at] = 1;
         a.faces[at] = wi;
     }
 }
 
+// Diffraction part of a coverage map: one thread per cell adds the path gain
+// |a|^2 of every wedge's diffracted path to the cell centre (fixed wedge
+// order, so the sum is deterministic).
+__global__ __launch_bounds__(kBlock) void coverage_diffraction_kernel(DevScene sc, MatTable mats, double lambda,
+                                                                      d3 S, Antenna txa, Antenna rxa, double gx0,
+                                                                      double gy0, double gcell, double gz,
+                                                                      int32_t gnx, int64_t cells,
+                                                                      float* __restrict__ gain) {
+    __shared__ int32_t stack[kStack][kBlock];
+    __shared__ Node lds_nodes[kLdsNodes];
+    const int n_lds = stage_nodes(sc, lds_nodes);
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t iy = c / gnx, ix = c - iy * gnx;
+        const d3 P{gx0 + ((double)ix + 0.5) * gcell, gy0 + ((double)iy + 0.5) * gcell, gz};
+        double acc = 0.0;
+        for (int wi = 0; wi < sc.num_wedges; ++wi) {
+            DiffPath p;
+            if (diffracted<false>(sc, lds_nodes, n_lds, stack, mats, lambda, S, txa, P, rxa, wi, p))
+                acc += p.a.re * p.a.re + p.a.im * p.a.im;
+        }
+        gain[c] += (float)acc;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_coverage_diffraction(const DevScene& sc, const MatTable& mats, double lambda, const double* tx,
+                                      const Antenna& txa, const Antenna& rxa, double gx0, double gy0, double gcell,
+                                      double gz, int32_t gnx, int32_t gny, float* gain, hipStream_t s) {
+    const int64_t cells = (int64_t)gnx * gny;
+    if (cells <= 0 || sc.num_wedges <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((cells + kBlock - 1) / kBlock, 16384);
+    hipLaunchKernelGGL(coverage_diffraction_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, sc, mats, lambda,
+                       d3{tx[0], tx[1], tx[2]}, txa, rxa, gx0, gy0, gcell, gz, gnx, cells, gain);
+    return hipGetLastError();
+}
 
 hipError_t launch_diffraction_paths(const PathArgs& a, const MatTable& mats, hipStream_t s) {
     const int64_t total = (int64_t)a.nrx * a.sc.num_wedges;

@@ -148,6 +148,11 @@ hipError_t launch_image_paths(const PathArgs& a, const MatTable& mats, int64_t m
 // First-order diffraction: one thread per (receiver, wedge) writes the valid
 // paths into the unsorted records of a (depth = 1, faces[0] = wedge id, fd = 1).
 hipError_t launch_diffraction_paths(const PathArgs& a, const MatTable& mats, hipStream_t s);
+// Diffraction part of a coverage map: gain[c] += sum over wedges of |a|^2 of the
+// diffracted path from tx to the centre of cell c (one thread per cell).
+hipError_t launch_coverage_diffraction(const DevScene& sc, const MatTable& mats, double lambda, const double* tx,
+                                      const Antenna& txa, const Antenna& rxa, double gx0, double gy0, double gcell,
+                                      double gz, int32_t gnx, int32_t gny, float* gain, hipStream_t s);
 hipError_t launch_sort_paths(const PathArgs& a, int32_t nrx, float* a_out, float* T_out, float* tau_out,
                              float* aod_out, float* aoa_out, int32_t* depth_out, int32_t* faces_out,
                              int32_t* num_paths_out, hipStream_t s);

@@ -278,6 +278,20 @@ def compute_diffraction(ctx: Context, scene: Scene, freq_hz: float, txs, rxs, P:
     return o
 
 
+def coverage_diffraction(ctx: Context, scene: Scene, freq_hz: float, tx, grid, gain=None, rx_ant=None):
+    """Adds the diffracted path gain at every cell centre to gain (a float32
+    [ny, nx] device tensor, zeros when None) and returns it."""
+    from types import SimpleNamespace
+    if gain is None:
+        gain = torch.zeros((grid.ny, grid.nx), dtype=torch.float32, device=ctx.torch_device)
+    rx_ant = rx_ant or SimpleNamespace(pos=(0.0, 0.0, 0.0), yaw=0.0, pitch=0.0, roll=0.0, pattern=0)
+    t, r, g = device_struct(tx), device_struct(rx_ant), grid_struct(grid)
+    ctx._bind_stream()
+    check(lib.rt_coverage_diffraction(ctx.h, scene.h, float(freq_hz), ctypes.byref(t), ctypes.byref(r),
+                                      ctypes.byref(g), _ptr(gain)))
+    return gain
+
+
 def last_candidate_count(ctx: Context) -> int:
     n = ctypes.c_int64()
     check(lib.rt_last_candidate_count(ctx.h, ctypes.byref(n)))

@@ -95,3 +95,31 @@ def test_diffraction_capacity_and_argument_errors():
         m.compute_diffraction(ctx(), sc, -1.0, w.tx, w.rx, P=8)
     with pytest.raises(RTError, match="P must be"):
         m.compute_diffraction(ctx(), sc, w.scene.freq_hz, w.tx, w.rx, P=300)
+
+
+@pytest.mark.parametrize("case", ["toy", "urban"])
+def test_coverage_diffraction_matches_oracle(case):
+    """rt_coverage_diffraction adds, per cell, the path gain of the diffracted
+    paths to the cell centre: equal to the oracle's sum over wedges."""
+    m = lib()
+    if case == "toy":
+        w = sg.toy_workload()
+        grid = sg.Grid(-100.0, -100.0, 5.0, 40, 40, 1.5)
+        rx_ant = sg.Device((0.0, 0.0, 0.0))
+    else:
+        w = sg.diff_workload()
+        grid = sg.Grid(-240.0, -240.0, 16.0, 30, 30, 1.5)
+        rx_ant = sg.Device((0.0, 0.0, 0.0), pattern=sg.PATTERN_DIPOLE, pol=sg.POL_H)
+    sc = scene(w.scene)
+    gt = m.coverage_diffraction(ctx(), sc, w.scene.freq_hz, w.tx[0], grid, rx_ant=rx_ant)
+    got = gt.cpu().numpy().astype(np.float64)
+    # the call adds to the map it is given
+    twice = m.coverage_diffraction(ctx(), sc, w.scene.freq_hz, w.tx[0], grid, gain=gt.clone(), rx_ant=rx_ant)
+    assert torch.allclose(twice, 2 * gt, rtol=1e-6, atol=0.0)
+    g = geom.Geometry(w.scene)
+    ref = odiff.coverage(g, w.tx[0], grid, rx_ant=rx_ant)
+    lit = ref > 1e-15
+    print("%s: %d of %d cells reached by diffraction" % (case, int(lit.sum()), ref.size), flush=True)
+    assert lit.sum() >= 50
+    assert np.max(np.abs(got[lit] - ref[lit]) / ref[lit]) < 1e-3
+    assert np.max(np.abs(got[~lit])) < 1e-15
