@@ -229,15 +229,20 @@ __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_node
                 cx(q0, c0, q2, c2);
                 cx(q1, c1, q3, c3);
                 cx(q1, c1, q2, c2);
+                // a nearest child that is a leaf is parked at once when the lane
+                // holds none; the next-nearest child is then visited next
+                const bool park = q0 != ~0u && c0 < 0 && leaf == 0;
+                if (park) leaf = c0;
                 put(sp, c3);
                 sp += q3 != ~0u;
                 put(sp, c2);
                 sp += q2 != ~0u;
                 put(sp, c1);
-                sp += q1 != ~0u;
-                if (q0 != ~0u) {
-                    node = c0;
-                } else if (sp == 0) {  // no child hit, nothing pushed: top is still the top
+                sp += (q1 != ~0u) & !park;
+                const bool has_next = park ? q1 != ~0u : q0 != ~0u;
+                if (has_next) {
+                    node = park ? c1 : c0;
+                } else if (sp == 0) {  // nothing pushed: top is still the top
                     node = kDone;
                 } else {
                     node = top;
