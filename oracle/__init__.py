@@ -28,6 +28,7 @@ Modules
   covgrad   coverage-map region gain and its central finite differences
   channel   channel frequency responses of paths (synthetic arrays, Doppler, OFDM)
   scatter   Lambertian diffuse scattering for coverage maps (SplitMix64 draws)
+  scatpaths diffusely scattered paths (Lambertian ray-tube model)
   diffraction  first-order wedge diffraction (UTD) paths
   mlp       float64 Fourier-feature MLP with manual backward (surrogate)
 """

@@ -27,7 +27,11 @@ Conventions (primitives are faces, see ``geom``):
   (theta_hat(d_K), phi_hat(d_K));
 * AoD = (theta, phi) of d_0, AoA = (theta, phi) of -d_K, global frame,
   theta = acos(z), phi = atan2(y, x);
-* line of sight (K = 0) is included when tx -> rx is unoccluded.
+* line of sight (K = 0) is included when tx -> rx is unoccluded;
+* with scattering coefficients S per material (Sec. II-B diffuse reflections,
+  the Lambertian power split of ``oracle.scatter``) a reflection keeps the
+  specular share 1 - S^2 of the reflected power: a and T carry the factor
+  sqrt(1 - S^2) per reflection (S taken in float32, as stored by the library).
 """
 from __future__ import annotations
 
@@ -138,15 +142,28 @@ def coefficients(geo, tx, rx, faces, X, lam=None):
     return complex(a), T, L, d0, dK
 
 
+def specular_share(geo, faces, scat):
+    """Product of sqrt(1 - S^2) over the reflections of a face sequence."""
+    if scat is None:
+        return 1.0
+    S = np.asarray(scat, dtype=np.float32).astype(np.float64)
+    w = 1.0
+    for f in faces:
+        s = S[geo.face_mat[f]]
+        w *= np.sqrt(1.0 - s * s)
+    return w
+
+
 def _angles(d):
     th, ph = em.theta_phi(d)
     return float(th), float(ph)
 
 
-def paths(geo, tx, rxs, sequences, threads=None):
+def paths(geo, tx, rxs, sequences, threads=None, scat=None):
     """Valid paths for every rx and every face sequence (the empty sequence
-    is line of sight).  ``sequences`` is an iterable of tuples of face ids.
-    Returns a list (per rx) of Path lists sorted by (depth, faces)."""
+    is line of sight).  ``sequences`` is an iterable of tuples of face ids;
+    ``scat`` (optional) the scattering coefficient per material.  Returns a
+    list (per rx) of Path lists sorted by (depth, faces)."""
     seqs = sorted(set(tuple(s) for s in sequences) | {()}, key=lambda s: (len(s), s))
     lam = C0 / geo.freq
     cand = []
@@ -175,6 +192,9 @@ def paths(geo, tx, rxs, sequences, threads=None):
         if blocked[ci]:
             continue
         a, T, L, d0, dK = coefficients(geo, tx, rxs[r], s, X, lam)
+        if scat is not None:
+            ws = specular_share(geo, s, scat)
+            a, T = a * ws, T * ws
         out[r].append(Path(r, s, a, T, L / C0, L, _angles(d0), _angles(-dK), X))
     return out
 
