@@ -444,6 +444,19 @@ def extras(rt, ctx, scene, w, torch):
                          "coverage_map_ms": round(ms, 3), "ray_bounces": rbs,
                          "M_ray_bounces_per_s": round(rbs / (ms / 1e3) / 1e6, 1)}
     log("bench: scattering %s" % res["scattering"])
+    # scattered paths: 16 receivers of the differentiation case, 1e6 rays, depth 3
+    ps = rt.TraceParams(d.scene.freq_hz, d.max_depth, d.num_rays)
+    rt.compute_scattering(ctx, ss, ps, d.tx, d.rx[:16], P=400_000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    osp = rt.compute_scattering(ctx, ss, ps, d.tx, d.rx[:16], P=400_000)
+    torch.cuda.synchronize()
+    res["scattering"]["paths_workload"] = "scattered paths, differentiation case, 1e6 rays, depth 3, 16 rx"
+    res["scattering"]["paths_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    res["scattering"]["scattered_paths"] = int(osp["num_paths"].sum())
+    log("bench: scattered paths %.2f ms, %d paths" % (res["scattering"]["paths_ms"],
+                                                      res["scattering"]["scattered_paths"]))
+    del osp
     ss.close()
     # large procedural city: paths to the 4096 street receivers
     c = sg.city_workload()

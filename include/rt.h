@@ -157,9 +157,11 @@ rt_status rt_scene_create(rt_ctx* ctx, const float* V, int64_t nv, const int32_t
  * carrying the reflected field components in that direction's transverse
  * basis; otherwise it is specular.  The draws come from the SplitMix64 stream
  * with the given seed: draw (i (max_depth + 1) + k) 3 + j for lattice ray i,
- * interaction depth k and j = 0 (diffuse or not), 1, 2 (direction).  Paths
- * stay specular; rt_coverage_grad replays the same draws.  RT_ERR_ARG for a count
- * that differs from the scene's or S outside [0, 1]. */
+ * interaction depth k and j = 0 (diffuse or not), 1, 2 (direction);
+ * rt_coverage_grad replays the same draws.  The paths of rt_compute_paths (and
+ * their gradients) keep the specular share: a and T carry sqrt(1 - S^2) per
+ * reflection; rt_compute_scattering returns the diffusely scattered paths.
+ * RT_ERR_ARG for a count that differs from the scene's or S outside [0, 1]. */
 rt_status rt_scene_set_scattering(rt_scene* scene, const float* S, int32_t nm, uint64_t seed);
 
 /* Replace the material table (same count); no rebuild.  Synchronous. */
@@ -253,7 +255,9 @@ rt_status rt_profile_read(rt_ctx* ctx, int32_t n, int64_t* launches, double* ms)
  * candidate, duplicates are removed, the image method is applied to every
  * candidate for every receiver and the line-of-sight path is added.  A path
  * is kept when its reflection points lie on their faces, on the front sides,
- * and every segment is unoccluded.  Outputs, shape [ntx][nrx][P] with
+ * and every segment is unoccluded.  With scattering coefficients
+ * (rt_scene_set_scattering) every reflection keeps its specular share
+ * sqrt(1 - S^2).  Outputs, shape [ntx][nrx][P] with
  * P = max_paths_per_rx, paths of one (tx, rx) sorted by (depth, faces):
  *   a [..][2] (dev) complex coefficient (re, im) excluding exp(-j 2 pi f tau)
  *   T [..][2][2][2] (dev) 2x2 complex transfer matrix from (theta, phi) at
@@ -278,6 +282,37 @@ rt_status rt_paths_power(rt_ctx* ctx, const float* a, const int32_t* depth, int6
 /* Number of distinct candidate face sequences found by the last
  * rt_compute_paths call for its last transmitter. */
 rt_status rt_last_candidate_count(rt_ctx* ctx, int64_t* count);
+
+/* Diffusely scattered paths (Sec. II-B: diffuse reflections among the
+ * interactions; Sec. II-A: scattering can be enabled for paths) with the
+ * Lambertian model of rt_scene_set_scattering: for every transmitter the
+ * lattice rays (num_rays, ray_begin, ray_stride, t_min of p) are traced with
+ * up to max_depth specular reflections, and hit k (1..max_depth) of lattice
+ * ray i, at point h of a face with coefficient S > 0 (normal n facing the
+ * ray, ray length s), scatters to every receiver R in front of the face
+ * ((R - h) . n > 0) whose open segment h -> R is unoccluded:
+ *   a = lambda/(4 pi) S w sqrt((4 pi / N) cos_s / pi) / r_s F_rx(-k) . E_s,
+ * k = (R - h)/r_s, r_s = |R - h|, cos_s = k . n, E_s the reflected components
+ * (r_perp a_perp, r_par a_par) of the ray's field on the transverse basis of
+ * k (perp = k x n / |k x n|, par = perp x k), w the product of sqrt(1 - S^2)
+ * over the earlier reflections.  Each ray stands for the solid angle 4 pi / N
+ * of the full lattice, also in sub-lattices.  tau = (s + r_s)/c0; carrier
+ * phase excluded, as for rt_compute_paths.  Outputs, shape [ntx][nrx][P] (dev):
+ *   a [..][2], T [..][2][2][2] (a = lambda/(4 pi c0 tau) F_rx^T T F_tx in the
+ *   (theta, phi) bases of departure and arrival, as for rt_compute_paths),
+ *   tau [..], aod [..][2] (angles of the ray's departure), aoa [..][2]
+ *   (angles of -k), depth [..] int32 k, ray [..] int64 lattice index i,
+ *   faces [..][max(max_depth, 1)] int32 faces of the k hits (scattering face
+ *   last, -1 padded), num_paths [ntx][nrx] int64 (not truncated).
+ * Paths of a receiver are ordered by (ray, depth); unused slots get a = T = 0,
+ * tau = -1, depth = -1, ray = -1.  P may exceed 256 (up to 2^40).
+ * RT_ERR_CAPACITY when some receiver has more than P paths (the message gives
+ * the required P; the first P are written).  No paths when no material
+ * scatters.  Synchronous. */
+rt_status rt_compute_scattering(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p, const rt_device* tx,
+                                int32_t ntx, const rt_device* rx, int32_t nrx, int64_t P, float* a, float* T,
+                                float* tau, float* aod, float* aoa, int32_t* depth, int64_t* ray, int32_t* faces,
+                                int64_t* num_paths);
 
 /* Wedges of the scene for first-order diffraction (Sec. II-B): edges shared
  * by exactly two triangles of two different faces, not on the ground (the

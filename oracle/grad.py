@@ -27,8 +27,9 @@ from . import image, native
 from .consts import C0, OCC_EPS
 
 
-def _powers(geo, tx, rxs, seqs, check_occlusion=True):
-    """P_r for frozen face sequences; also a per-rx tuple of validity flags."""
+def _powers(geo, tx, rxs, seqs, check_occlusion=True, scat=None):
+    """P_r for frozen face sequences; also a per-rx tuple of validity flags.
+    ``scat``: scattering coefficients per material (specular share, see image)."""
     lam = C0 / geo.freq
     P = np.zeros(len(rxs))
     valid = []
@@ -63,7 +64,7 @@ def _powers(geo, tx, rxs, seqs, check_occlusion=True):
             valid[r][j] = False
             continue
         a, _, _, _, _ = image.coefficients(geo, tx, rxs[r], s, X, lam)
-        P[r] += abs(a) ** 2
+        P[r] += abs(a * image.specular_share(geo, s, scat)) ** 2
     return P, [tuple(v) for v in valid]
 
 
@@ -107,14 +108,16 @@ def param_values(geo, tx):
                            [float(tx.yaw), float(tx.pitch)]])
 
 
-def fd_gradient(geo, tx, rxs, seqs, mask=None, rel_h=1e-4):
+def fd_gradient(geo, tx, rxs, seqs, mask=None, rel_h=1e-4, scat=None):
     """Central-difference gradient of ``loss`` over the rx in mask.
 
+    ``scat`` (optional): scattering coefficients per material; every
+    reflection then keeps its specular share sqrt(1 - S^2).
     Returns (grad, mask_used, unstable) where unstable[r] is True when some
     perturbation changed the validity of one of rx r's paths; such receivers
     are removed from mask_used and the gradient is computed without them.
     """
-    P0, v0 = _powers(geo, tx, rxs, seqs)
+    P0, v0 = _powers(geo, tx, rxs, seqs, scat=scat)
     if mask is None:
         mask = P0 > 0
     theta = param_values(geo, tx)
@@ -125,8 +128,8 @@ def fd_gradient(geo, tx, rxs, seqs, mask=None, rel_h=1e-4):
         h = rel_h * max(abs(theta[k]), 1.0)
         gp, tp = _perturbed(geo, tx, k, +h)
         gm, tm = _perturbed(geo, tx, k, -h)
-        Pp, vp = _powers(gp, tp, rxs, seqs)
-        Pm, vm = _powers(gm, tm, rxs, seqs)
+        Pp, vp = _powers(gp, tp, rxs, seqs, scat=scat)
+        Pm, vm = _powers(gm, tm, rxs, seqs, scat=scat)
         for r in range(len(rxs)):
             if vp[r] != v0[r] or vm[r] != v0[r]:
                 unstable[r] = True

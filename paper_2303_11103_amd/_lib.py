@@ -91,6 +91,8 @@ SIGNATURES = {
     "rt_coverage_diffraction": [P, P, ctypes.c_double, ctypes.POINTER(rt_device), ctypes.POINTER(rt_device),
                                 ctypes.POINTER(rt_grid), P],
     "rt_compute_diffraction": [P, P, ctypes.c_double, P, I32, P, I32, I32, P, P, P, P, P, P, P],
+    "rt_compute_scattering": [P, P, ctypes.POINTER(rt_trace_params), P, I32, P, I32, I64, P, P, P, P, P, P, P, P,
+                              P],
     "rt_paths_power": [P, P, P, I64, I32, P],
     "rt_paths_power_grad": [P, P, ctypes.POINTER(rt_trace_params), ctypes.POINTER(rt_device), P, I32, I32, P, P,
                             P, P],

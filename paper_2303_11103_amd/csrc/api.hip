@@ -106,6 +106,7 @@ struct rt_ctx {
     DevBuf rx_ant;     // Antenna [nrx]
     DevBuf paths;      // unsorted path records
     DevBuf chan;       // channel responses: element offsets and velocities
+    DevBuf scat;       // scattered paths: points, masks, prefixes, counts of one chunk
     void* scratch = nullptr;  // this device's copy of the fixed scratch array
     int64_t last_candidates = 0;
     // launch timing of the shoot-and-bounce kernels
@@ -378,7 +379,7 @@ rt_status rt_destroy(rt_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (DevBuf* b : {&c->queue[0], &c->queue[1], &c->counters, &c->table, &c->cands, &c->rx, &c->rx_ant, &c->paths,
-                      &c->pairs, &c->pair_rx, &c->rgrid, &c->chan})
+                      &c->pairs, &c->pair_rx, &c->rgrid, &c->chan, &c->scat})
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
@@ -957,6 +958,99 @@ rt_status rt_compute_diffraction(rt_ctx* c, rt_scene* s, double freq_hz, const r
     if (worst > P)
         return fail(RT_ERR_CAPACITY, "a receiver has " + std::to_string(worst) +
                                          " diffracted paths; raise P to at least that");
+    return RT_OK;
+}
+
+rt_status rt_compute_scattering(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx, int32_t ntx,
+                                const rt_device* rx, int32_t nrx, int64_t P, float* a, float* T, float* tau,
+                                float* aod, float* aoa, int32_t* depth, int64_t* ray, int32_t* faces,
+                                int64_t* num_paths) {
+    if (!c || !s || !tx || !rx || !a || !T || !tau || !aod || !aoa || !depth || !ray || !faces || !num_paths)
+        return fail(RT_ERR_ARG, "NULL argument");
+    rt_status st = check_params(p);
+    if (st != RT_OK) return st;
+    if (ntx < 1 || nrx < 1) return fail(RT_ERR_ARG, "need at least one tx and one rx");
+    if (P < 1 || P > (int64_t(1) << 40)) return fail(RT_ERR_ARG, "P must be in [1, 2^40]");
+    for (int i = 0; i < ntx; ++i)
+        if ((st = check_device(tx + i, "tx", s->host.max_abs)) != RT_OK) return st;
+    for (int i = 0; i < nrx; ++i)
+        if ((st = check_device(rx + i, "rx", s->host.max_abs)) != RT_OK) return st;
+    RT_HIP(hipSetDevice(c->device));
+    const int D = p->max_depth;
+    const int fd = std::max(D, 1);
+    const int64_t count = traced_count(p);
+    // chunk of rays: records, masks and prefixes within about 1 GiB
+    const int64_t per_ray = (int64_t)std::max(D, 1) * (int64_t)(sizeof(rt::ScatPoint) + (nrx * 12 + 63) / 64);
+    int64_t chunk = std::min<int64_t>(int64_t(1) << 20, std::max<int64_t>(64, (int64_t(1) << 30) / per_ray));
+    chunk = std::min<int64_t>(chunk, count);
+    const int64_t nrec_pad = (chunk * std::max(D, 1) + 63) / 64 * 64;
+    const int64_t nwords = nrec_pad / 64;
+    const size_t pts_bytes = (size_t)chunk * std::max(D, 1) * sizeof(rt::ScatPoint);
+    const size_t mask_bytes = (size_t)nrx * nwords * sizeof(uint64_t);
+    const size_t pre_bytes = ((size_t)nrx * nwords * sizeof(uint32_t) + 255) / 256 * 256;
+    const size_t cnt_bytes = (size_t)nrx * 2 * sizeof(int64_t);
+    RT_HIP(ensure(c->scat, pts_bytes + mask_bytes + pre_bytes + cnt_bytes));
+    RT_HIP(ensure(c->rx, (size_t)nrx * 3 * sizeof(double)));
+    RT_HIP(ensure(c->rx_ant, (size_t)nrx * sizeof(rt::Antenna)));
+    std::vector<double> rxp(3 * (size_t)nrx);
+    std::vector<rt::Antenna> rxa(nrx);
+    for (int i = 0; i < nrx; ++i) {
+        for (int k = 0; k < 3; ++k) rxp[3 * i + k] = rx[i].pos[k];
+        rxa[i] = make_antenna(rx + i);
+    }
+    RT_HIP(hipMemcpyAsync(c->rx.p, rxp.data(), rxp.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    RT_HIP(hipMemcpyAsync(c->rx_ant.p, rxa.data(), rxa.size() * sizeof(rt::Antenna), hipMemcpyHostToDevice,
+                          c->stream));
+    char* buf = (char*)c->scat.p;
+    rt::ScatArgs sa{};
+    sa.sc = s->dev;
+    sa.num_rays = p->num_rays;
+    sa.begin = p->ray_begin;
+    sa.stride = p->ray_stride;
+    sa.max_depth = D;
+    sa.nrx = nrx;
+    sa.tmin = p->t_min;
+    sa.lambda = kC0 / p->freq_hz;
+    sa.rx = (const double*)c->rx.p;
+    sa.rx_ant = (const rt::Antenna*)c->rx_ant.p;
+    sa.points = (rt::ScatPoint*)buf; buf += pts_bytes;
+    sa.nrec_pad = nrec_pad;
+    sa.masks = (uint64_t*)buf; buf += mask_bytes;
+    sa.prefix = (uint32_t*)buf; buf += pre_bytes;
+    sa.chunk_total = (int64_t*)buf;
+    sa.P = P;
+    sa.fd = fd;
+    rt::MatTable mats = make_mats(s, p->freq_hz);
+    int64_t worst = 0;
+    std::vector<int64_t> counts_h(nrx);
+    for (int t = 0; t < ntx; ++t) {
+        for (int i = 0; i < 3; ++i) sa.tx[i] = tx[t].pos[i];
+        sa.tx_ant = make_antenna(tx + t);
+        const size_t off = (size_t)t * nrx * P;
+        sa.a = a + 2 * off;
+        sa.T = T + 8 * off;
+        sa.tau = tau + off;
+        sa.aod = aod + 2 * off;
+        sa.aoa = aoa + 2 * off;
+        sa.depth = depth + off;
+        sa.ray = ray + off;
+        sa.faces = faces + off * fd;
+        sa.base = num_paths + (size_t)t * nrx;
+        RT_HIP(rt::launch_fill_u32(sa.base, 0u, (size_t)nrx * 2, c->stream));
+        for (int64_t pos0 = 0; pos0 < count; pos0 += chunk) {
+            sa.pos0 = pos0;
+            sa.n = std::min<int64_t>(chunk, count - pos0);
+            RT_HIP(rt::launch_scatter_chunk(sa, mats, c->stream));
+        }
+        RT_HIP(rt::launch_scatter_tail(sa, c->stream));
+        RT_HIP(hipMemcpyAsync(counts_h.data(), sa.base, (size_t)nrx * sizeof(int64_t), hipMemcpyDeviceToHost,
+                              c->stream));
+        RT_HIP(hipStreamSynchronize(c->stream));
+        for (int i = 0; i < nrx; ++i) worst = std::max(worst, counts_h[i]);
+    }
+    if (worst > P)
+        return fail(RT_ERR_CAPACITY, "a receiver has " + std::to_string(worst) +
+                                         " scattered paths; raise P to at least that");
     return RT_OK;
 }
 

@@ -260,6 +260,15 @@ __device__ __forceinline__ void fresnel(const Mat& m, double cos_i, cd& r_perp, 
     r_par = cdiv(csub(ec, s), cadd(ec, s));
 }
 
+// Field factor of a specular reflection on a scattering material: the
+// reflected power splits into S^2 diffuse and 1 - S^2 specular (the Lambertian
+// model of the coverage maps), so a specular path carries sqrt(1 - S^2) per
+// reflection (1 when the material does not scatter).
+__device__ __forceinline__ double specular_share(const Mat& m) {
+    const double S = (double)m.scat;
+    return sqrt(1.0 - S * S);
+}
+
 // Unit vector perpendicular to the plane of incidence; any unit vector
 // orthogonal to d at normal incidence (the result does not depend on it).
 __device__ __forceinline__ d3 perp_basis(d3 d, d3 n) {

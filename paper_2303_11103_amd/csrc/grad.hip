@@ -303,6 +303,13 @@ __global__ void power_grad_kernel(GradArgs g, MatTable mats) {
             const cd num = cmulr(csub(ev, cd{2.0 * sin2.v, 0.0}), cos_i.v);
             drl_v = cdiv(num, cmul(sv, cmul(ecs, ecs)));
         }
+        {  // specular share of a scattering material (a constant factor)
+            const double share = specular_share(m);
+            rp = rp * dc(share);
+            rl = rl * dc(share);
+            drp_v = cmulr(drp_v, share);
+            drl_v = cmulr(drl_v, share);
+        }
         const D3 ep = dperp(din, n);
         const D3 eli = dcross(ep, din), elr = dcross(ep, dout);
         const C ap = cdot(E, ep), al = cdot(E, eli);

@@ -157,6 +157,51 @@ hipError_t launch_sort_paths(const PathArgs& a, int32_t nrx, float* a_out, float
                              float* aod_out, float* aoa_out, int32_t* depth_out, int32_t* faces_out,
                              int32_t* num_paths_out, hipStream_t s);
 
+// Diffusely scattered paths: scattering points of a chunk of lattice rays,
+// [ray][depth] (128 bytes).
+struct alignas(16) ScatPoint {
+    double p[3];    // the hit point
+    double n[3];    // unit normal facing the incident ray
+    double g[8];    // 2x2 complex G: (perp, par) from departure (theta, phi), times S w r_{perp,par}
+    double s;       // ray length from the transmitter
+    int32_t face;   // face of the hit (-1: no hit at this depth)
+    int32_t scat;   // 1 when the hit scatters (S > 0)
+};
+static_assert(sizeof(ScatPoint) == 128, "scattering point size");
+
+struct ScatArgs {
+    DevScene sc;
+    int64_t num_rays, begin, stride;
+    int64_t pos0, n;          // lattice positions [pos0, pos0 + n) of this chunk
+    int32_t max_depth, nrx;
+    double tmin, lambda;
+    double tx[3];
+    Antenna tx_ant;
+    const double* rx;         // [nrx][3]
+    const Antenna* rx_ant;    // [nrx]
+    ScatPoint* points;        // [n][max_depth]
+    int64_t nrec_pad;         // n * max_depth rounded up to a multiple of 64
+    uint64_t* masks;          // [nrx][nrec_pad / 64] visibility bits
+    uint32_t* prefix;         // [nrx][nrec_pad / 64] visible records before each word (this chunk)
+    int64_t* chunk_total;     // [nrx]
+    int64_t* base;            // [nrx] paths of the earlier chunks (after the last chunk: the counts)
+    int64_t P;                // slots per receiver
+    float* a;                 // [nrx][P][2]
+    float* T;                 // [nrx][P][8]
+    float* tau;               // [nrx][P]
+    float* aod;               // [nrx][P][2]
+    float* aoa;               // [nrx][P][2]
+    int32_t* depth;           // [nrx][P]
+    int64_t* ray;             // [nrx][P]
+    int32_t* faces;           // [nrx][P][fd]
+    int32_t fd;               // max_depth
+};
+// Points, visibility, scan and write passes of one chunk; base must hold the
+// counts of the earlier chunks (zero before the first).
+hipError_t launch_scatter_chunk(const ScatArgs& a, const MatTable& mats, hipStream_t s);
+// Empty-slot values for the slots at or after every receiver's final count.
+hipError_t launch_scatter_tail(const ScatArgs& a, hipStream_t s);
+
 struct GradArgs {
     DevScene sc;
     double freq, lambda;

@@ -213,6 +213,9 @@ __global__ __launch_bounds__(kBlock) void image_paths_kernel(PathArgs a, MatTabl
             const double cos_i = -dot(din, n);
             cd rp, rl;
             fresnel(mats.m[F.mat], cos_i, rp, rl);
+            const double share = specular_share(mats.m[F.mat]);
+            rp = cmulr(rp, share);
+            rl = cmulr(rl, share);
             const d3 ep = perp_basis(din, n);
             const d3 eli = cross(ep, din), elr = cross(ep, dout);
             E = reflect_field(E, ep, eli, elr, rp, rl);

@@ -278,6 +278,35 @@ def compute_diffraction(ctx: Context, scene: Scene, freq_hz: float, txs, rxs, P:
     return o
 
 
+def compute_scattering(ctx: Context, scene: Scene, params: TraceParams, txs, rxs, P: int = 4096):
+    """Diffusely scattered paths for every (tx, rx) (the scene's scattering
+    coefficients, see Scene.set_scattering); dict of device tensors shaped
+    [ntx, nrx, P, ...] (a, T, tau, aod, aoa, depth, ray, faces) and num_paths
+    (int64).  Raises RTError (RT_ERR_CAPACITY) when a receiver has more than P."""
+    ntx, nrx = len(txs), len(rxs)
+    fd = max(params.max_depth, 1)
+    dev = ctx.torch_device
+    o = {
+        "a": torch.empty((ntx, nrx, P, 2), dtype=torch.float32, device=dev),
+        "T": torch.empty((ntx, nrx, P, 2, 2, 2), dtype=torch.float32, device=dev),
+        "tau": torch.empty((ntx, nrx, P), dtype=torch.float32, device=dev),
+        "aod": torch.empty((ntx, nrx, P, 2), dtype=torch.float32, device=dev),
+        "aoa": torch.empty((ntx, nrx, P, 2), dtype=torch.float32, device=dev),
+        "depth": torch.empty((ntx, nrx, P), dtype=torch.int32, device=dev),
+        "ray": torch.empty((ntx, nrx, P), dtype=torch.int64, device=dev),
+        "faces": torch.empty((ntx, nrx, P, fd), dtype=torch.int32, device=dev),
+        "num_paths": torch.empty((ntx, nrx), dtype=torch.int64, device=dev),
+    }
+    tx_arr = (L.rt_device * ntx)(*[device_struct(t) for t in txs])
+    rx_arr = (L.rt_device * nrx)(*[device_struct(r) for r in rxs])
+    ctx._bind_stream()
+    p = params.c()
+    check(lib.rt_compute_scattering(ctx.h, scene.h, ctypes.byref(p), tx_arr, ntx, rx_arr, nrx, int(P), _ptr(o["a"]),
+                                    _ptr(o["T"]), _ptr(o["tau"]), _ptr(o["aod"]), _ptr(o["aoa"]), _ptr(o["depth"]),
+                                    _ptr(o["ray"]), _ptr(o["faces"]), _ptr(o["num_paths"])))
+    return o
+
+
 def coverage_diffraction(ctx: Context, scene: Scene, freq_hz: float, tx, grid, gain=None, rx_ant=None):
     """Adds the diffracted path gain at every cell centre to gain (a float32
     [ny, nx] device tensor, zeros when None) and returns it."""
