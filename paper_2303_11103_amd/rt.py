@@ -379,9 +379,29 @@ def _cfr_args(paths, freq_hz, num_subcarriers, spacing, tx_el, rx_el, v_tx, v_rx
     return args, shape, keep
 
 
+def combine_paths(*path_sets):
+    """One path list of several kinds for paths_cfr / paths_cfr_adjoint:
+    the outputs of compute_paths, compute_diffraction and compute_scattering
+    for the same transmitters and receivers, concatenated along the slot axis
+    (a, tau, aod, aoa, depth; a diffracted path counts as depth 1)."""
+    keys = ("a", "tau", "aod", "aoa")
+    out = {k: torch.cat([ps[k] for ps in path_sets], dim=2).contiguous() for k in keys}
+    depth = []
+    for ps in path_sets:
+        if "depth" in ps:
+            depth.append(ps["depth"].to(torch.int32))
+        else:
+            depth.append(torch.where(ps["wedge"] >= 0, 1, -1).to(torch.int32))
+    out["depth"] = torch.cat(depth, dim=2).contiguous()
+    if out["depth"].shape[2] >= 2 ** 31:
+        raise ValueError("more than 2^31 - 1 path slots per receiver")
+    return out
+
+
 def paths_cfr(ctx: Context, paths, freq_hz, num_subcarriers=128, spacing=30e3, tx_el=None, rx_el=None, v_tx=None,
               v_rx=None, num_time_steps=1, fs=None):
-    """Channel frequency responses of the paths of compute_paths: complex64
+    """Channel frequency responses of the paths of compute_paths (or of
+    combine_paths over specular, diffracted and scattered paths): complex64
     tensor [ntx, nrx, T, nr_el, nt_el, K] (synthetic arrays from element
     offsets tx_el / rx_el [n][3] in metres, Doppler from velocities v_tx
     [ntx][3] / v_rx [nrx][3] in m/s, T time steps at fs Hz)."""

@@ -228,3 +228,40 @@ def test_power_gradient_with_scattering_matches_central_differences():
     scale = np.abs(fd)
     big = scale > 1e-6 * scale.max()
     assert np.max(np.abs(gg - fd)[big] / scale[big]) < 1e-3, (gg, fd)
+
+
+def test_channel_response_over_specular_diffracted_and_scattered_paths():
+    """combine_paths + rt_paths_cfr: the response of the combined list equals
+    the oracle's response of the same paths and the sum of the three kinds'
+    responses."""
+    from oracle import channel
+    m = lib()
+    s, tx, rxs, S, N, D = _case("toy")
+    rxs = rxs[:3]
+    sc = _scene_with(s, S)
+    p = m.TraceParams(freq_hz=s.freq_hz, max_depth=D, num_rays=N, max_paths_per_rx=32)
+    spec = m.compute_paths(ctx(), sc, p, [tx], rxs)
+    diff = m.compute_diffraction(ctx(), sc, s.freq_hz, [tx], rxs, P=32)
+    ps = m.TraceParams(freq_hz=s.freq_hz, max_depth=D, num_rays=5000)
+    scat = m.compute_scattering(ctx(), sc, ps, [tx], rxs, P=12_000)
+    comb = m.combine_paths(spec, diff, scat)
+    kw = dict(num_subcarriers=32, spacing=30e3)
+    H = m.paths_cfr(ctx(), comb, s.freq_hz, **kw)
+    parts = sum(m.paths_cfr(ctx(), q, s.freq_hz, **kw) for q in (spec, m.combine_paths(diff), scat))
+    a = comb["a"][0].cpu().numpy()
+    tau = comb["tau"][0].cpu().numpy()
+    aod = comb["aod"][0].cpu().numpy()
+    aoa = comb["aoa"][0].cpu().numpy()
+    depth = comb["depth"][0].cpu().numpy()
+    Hn = H.cpu().numpy()
+    kinds = [0, 0, 0]
+    for r in range(len(rxs)):
+        pl = [(complex(a[r, j, 0], a[r, j, 1]), float(tau[r, j]), tuple(aod[r, j].astype(float)),
+               tuple(aoa[r, j].astype(float))) for j in range(a.shape[1]) if depth[r, j] >= 0]
+        scale = sum(abs(x[0]) for x in pl)
+        ref = channel.cfr(pl, s.freq_hz, 32, 30e3)
+        assert np.max(np.abs(Hn[0, r] - ref)) <= 1e-5 * scale, r
+        assert torch.max(torch.abs(H[0, r] - parts[0, r])).item() <= 1e-5 * scale
+        for k, q in enumerate((spec["depth"], diff["wedge"], scat["depth"])):
+            kinds[k] += int((q[0, r] >= 0).sum())
+    assert min(kinds) > 0, kinds
