@@ -59,7 +59,7 @@ def test_trained_surrogate_beats_free_space_and_outruns_the_tracer():
           % (rmse, rmse_fs, trace_s_per_map, sur_s_per_map))
     assert sel.sum() > 1000
     assert rmse < 0.75 * rmse_fs, (rmse, rmse_fs)
-    assert sur_s_per_map * 5 < trace_s_per_map, (sur_s_per_map, trace_s_per_map)
+    assert sur_s_per_map * 20 < trace_s_per_map, (sur_s_per_map, trace_s_per_map)
     m.close()
 
 
