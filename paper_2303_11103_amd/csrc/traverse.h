@@ -79,11 +79,8 @@ __device__ __forceinline__ uint32_t live_children(int4 ch) {
            (uint32_t)(ch.w != kEmptyChild);
 }
 
-// Copies the first min(num_nodes, kLdsNodes) nodes into LDS (whole block).
-// The LDS copy is swizzled: 16-byte slot s of node n is stored at slot
-// s ^ (n & 7).  Lanes of a wave that read the same plane of different nodes
-// then spread over eight groups of LDS banks instead of one (a node is 128
-// bytes, so without the swizzle slot s of every node falls on the same banks).
+// Copies the first min(num_nodes, kLdsNodes) nodes into LDS (whole block),
+// in the global layout.
 __device__ __forceinline__ int stage_nodes(const DevScene& sc, Node* lds) {
     const int n = sc.num_nodes < kLdsNodes ? sc.num_nodes : kLdsNodes;
     const float4* src = reinterpret_cast<const float4*>(sc.nodes);
