@@ -67,6 +67,11 @@ def test_null_and_invalid_arguments_fail_on_host():
     assert lib.rt_set_stream(None, None) == _lib.RT_ERR_ARG
     assert lib.rt_scene_info(None, None) == _lib.RT_ERR_ARG
     assert lib.rt_profile_enable(None, 1) == _lib.RT_ERR_ARG
+    for name in ("rt_compute_paths", "rt_compute_scattering", "rt_compute_diffraction", "rt_coverage_map_noalloc"):
+        scalar = {ctypes.c_int32: 1, ctypes.c_int64: 1, ctypes.c_double: 3.5e9}
+        args = [scalar.get(t) for t in _lib.SIGNATURES[name]]   # NULL for every pointer
+        assert getattr(lib, name)(*args) == _lib.RT_ERR_ARG, name
+        assert b"NULL" in lib.rt_last_error() or b"params" in lib.rt_last_error(), name
     # destroy functions accept NULL
     assert lib.rt_destroy(None) == _lib.RT_OK
     assert lib.rt_scene_destroy(None) == _lib.RT_OK
