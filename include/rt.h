@@ -286,7 +286,8 @@ rt_status rt_last_candidate_count(rt_ctx* ctx, int64_t* count);
 /* Diffusely scattered paths (Sec. II-B: diffuse reflections among the
  * interactions; Sec. II-A: scattering can be enabled for paths) with the
  * Lambertian model of rt_scene_set_scattering: for every transmitter the
- * lattice rays (num_rays, ray_begin, ray_stride, t_min of p) are traced with
+ * lattice rays (num_rays, ray_begin, ray_stride, t_min of p; its
+ * max_paths_per_rx and cand_mode are not used) are traced with
  * up to max_depth specular reflections, and hit k (1..max_depth) of lattice
  * ray i, at point h of a face with coefficient S > 0 (normal n facing the
  * ray, ray length s), scatters to every receiver R in front of the face
