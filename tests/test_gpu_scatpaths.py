@@ -265,3 +265,17 @@ def test_channel_response_over_specular_diffracted_and_scattered_paths():
         for k, q in enumerate((spec["depth"], diff["wedge"], scat["depth"])):
             kinds[k] += int((q[0, r] >= 0).sum())
     assert min(kinds) > 0, kinds
+
+
+def test_two_transmitters_equal_separate_calls():
+    m = lib()
+    s, tx, rxs, S, N, D = _case("toy")
+    tx2 = sg.Device((35.0, -30.0, 8.0), pattern=sg.PATTERN_TR38901, yaw=2.5, pol=sg.POL_SLANT_M45)
+    sc = _scene_with(s, S)
+    p = m.TraceParams(freq_hz=s.freq_hz, max_depth=D, num_rays=8000)
+    both = m.compute_scattering(ctx(), sc, p, [tx, tx2], rxs, P=20_000)
+    for t, one in enumerate((tx, tx2)):
+        single = m.compute_scattering(ctx(), sc, p, [one], rxs, P=20_000)
+        for k in ("a", "T", "tau", "aod", "aoa", "depth", "ray", "faces", "num_paths"):
+            assert torch.equal(both[k][t], single[k][0]), (t, k)
+    assert int(both["num_paths"][1].sum()) > 1000
