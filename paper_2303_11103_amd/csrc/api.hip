@@ -59,6 +59,8 @@ hipError_t ensure(DevBuf& b, size_t bytes) {
 // copy per GPU, alive until the process ends).  Host code uses only the
 // addresses hipGetSymbolAddress returns for it, never the array's name.
 constexpr size_t kNoAllocCounterBytes = 64 << 10;
+static_assert(9 * rt::kQueueRegions * rt::kCounterStride * sizeof(uint32_t) <= kNoAllocCounterBytes,
+              "queue counters of nine depths must fit the fixed scratch");
 constexpr size_t kNoAllocScratchBytes = (size_t(112) << 20) + kNoAllocCounterBytes;
 constexpr int64_t kNoAllocMaxChunk = int64_t(1) << 19;  // rays per launch sequence
 constexpr int kMaxDevices = 64;
@@ -96,7 +98,7 @@ struct rt_ctx {
     hipStream_t stream = nullptr;
     int num_cu = 256;
     DevBuf queue[2];
-    DevBuf counters;   // uint32 [depth + 1][kQueueRegions] queue region counts
+    DevBuf counters;   // uint32 [depth + 1][kQueueRegions][kCounterStride] queue region counts
     DevBuf table;      // candidate prefix table
     DevBuf pairs;      // reception-sphere (receiver, prefix slot) set
     DevBuf pair_rx;    // receiver of each extracted pair
@@ -252,7 +254,7 @@ rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_dev
         const size_t qbytes = (size_t)rt::kQueueRegions * region_cap * sizeof(rt::RayState);
         RT_HIP(ensure(c->queue[0], qbytes));
         RT_HIP(ensure(c->queue[1], qbytes));
-        RT_HIP(ensure(c->counters, (size_t)(p->max_depth + 1) * rt::kQueueRegions * sizeof(uint32_t)));
+        RT_HIP(ensure(c->counters, (size_t)(p->max_depth + 1) * rt::kQueueRegions * rt::kCounterStride * sizeof(uint32_t)));
         queue[0] = (rt::RayState*)c->queue[0].p;
         queue[1] = (rt::RayState*)c->queue[1].p;
         cnt = (uint32_t*)c->counters.p;
@@ -313,15 +315,15 @@ rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_dev
     for (int64_t pos0 = 0; pos0 < count; pos0 += chunk) {
         a.pos0 = pos0;
         a.chunk = std::min(chunk, count - pos0);
-        const size_t nwords = (size_t)(p->max_depth + 1) * rt::kQueueRegions;
+        const size_t nwords = (size_t)(p->max_depth + 1) * rt::kQueueRegions * rt::kCounterStride;
         if (fixed) RT_HIP(rt::launch_fill_u32(cnt, 0u, nwords, c->stream));
         else RT_HIP(hipMemsetAsync(cnt, 0, nwords * sizeof(uint32_t), c->stream));
         for (int k = 0; k <= p->max_depth; ++k) {
             a.depth = k;
             a.in = k ? queue[(k - 1) & 1] : nullptr;
-            a.in_count = k ? cnt + (size_t)(k - 1) * rt::kQueueRegions : nullptr;
+            a.in_count = k ? cnt + (size_t)(k - 1) * rt::kQueueRegions * rt::kCounterStride : nullptr;
             a.out = queue[k & 1];
-            a.out_count = cnt + (size_t)k * rt::kQueueRegions;
+            a.out_count = cnt + (size_t)k * rt::kQueueRegions * rt::kCounterStride;
             a.region_cap = region_cap;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (profiling) {

@@ -23,6 +23,10 @@ static_assert(sizeof(RayState) == 96, "ray state size");
 
 constexpr uint64_t kEmptyKey = ~0ull;
 constexpr int kQueueRegions = 64;
+// The region counters sit 64 bytes apart: every wave's append is a
+// device-scope atomic performed past the L2, and counters that share a line
+// contend with each other.
+constexpr int kCounterStride = 16;  // 32-bit words between two region counters
 
 struct DevScene {
     const Node* nodes;
@@ -64,9 +68,9 @@ struct SbrArgs {
     // wave appends its survivors to region (wave % kQueueRegions) through
     // that region's counter, which spreads the queue atomics over 64 addresses.
     const RayState* in;
-    const uint32_t* in_count;   // [kQueueRegions] counts of the input regions
+    const uint32_t* in_count;   // [kQueueRegions * kCounterStride] counts of the input regions
     RayState* out;
-    uint32_t* out_count;        // [kQueueRegions]
+    uint32_t* out_count;        // [kQueueRegions * kCounterStride]
     int64_t region_cap;
     uint64_t* stats;    // [max_depth + 1] traced rays per depth (nullable)
     uint64_t* work;     // stats mode: [4][max_depth + 1] rays, inner-node visits, child-box tests, triangle tests

@@ -245,7 +245,7 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
     // region counts up to r (registers, so no LDS is taken from the stack)
     uint32_t incl = 0;
     if (!FIRST) {
-        incl = a.in_count[lane];
+        incl = a.in_count[lane * kCounterStride];
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t v = __shfl_up(incl, off);
             if (lane >= off) incl += v;
@@ -391,7 +391,7 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
         if (m) {
             uint32_t b = 0;
             const int region = (int)(wave % kQueueRegions);
-            if (lane == 0) b = atomicAdd(a.out_count + region, (uint32_t)__popcll(m));
+            if (lane == 0) b = atomicAdd(a.out_count + region * kCounterStride, (uint32_t)__popcll(m));
             b = __shfl(b, 0);
             if (alive)
                 store_ray<(MODE & kModeSphere) != 0>(
