@@ -7,7 +7,7 @@ concrete/glass/metal at 28 GHz), a TR 38.901 transmitter (pitch +10 deg) 2 m
 above the tallest roof near the centre, 1e8 Fibonacci-lattice rays, up to 5
 specular reflections, 2000x2000 cells of 1 m at 1.5 m height.  One step =
 ray generation, closest-hit BVH traversal, coverage deposit, Fresnel
-reflection and queue compaction for every bounce (six chunks of 2^24 rays),
+reflection and queue compaction for every bounce (one chunk of 1e8 rays),
 then the dB map.  The urban canyon (8x8 boxes, 1e7 rays, depth 3, 400x400
 cells) is measured the same way as a secondary object.
 

@@ -221,7 +221,7 @@ rt_status rt_coverage_maps(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* 
  * passes (and owns) every output.  The ray queues and queue counters live in
  * a fixed device array of the library (112 MiB + 64 KiB, one copy per GPU,
  * held until the process ends), so the lattice is traced in chunks of at most
- * 2^19 rays instead of 2^24; clears use fill kernels, not memsets.  Nothing is
+ * 2^19 rays instead of 2^27; clears use fill kernels, not memsets.  Nothing is
  * allocated and no HIP events are created (rt_profile_enable does not apply).
  * Returns RT_ERR_CAPACITY if the queues for this device's launch width do not
  * fit the array.  Every call on one GPU shares that array: calls that overlap

@@ -34,7 +34,9 @@ rt_status fail(rt_status code, const std::string& msg) {
 
 constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kC0 = 299792458.0;
-constexpr int64_t kChunk = int64_t(1) << 24;  // rays per launch sequence (queue memory bound)
+// Rays per launch sequence.  The two ray queues of a chunk take 2 x 12.9 GB at
+// 2^27 rays (a 1e8-ray lattice in one sequence of max_depth + 1 launches).
+constexpr int64_t kChunk = int64_t(1) << 27;
 
 struct DevBuf {
     void* p = nullptr;

@@ -36,7 +36,7 @@ def _run(entry, c, s, p, tx, grid):
 
 def _same(a, b):
     # integer outputs bit-exact; the fp32 gain sums differ only in the order of
-    # their atomic additions (chunks of 2^19 rays here, 2^24 in rt_coverage_map)
+    # their atomic additions (chunks of 2^19 rays here, 2^27 in rt_coverage_map)
     assert np.array_equal(a["hits"], b["hits"])
     assert np.array_equal(a["ray_bounces"], b["ray_bounces"])
     hit = b["hits"] > 0
