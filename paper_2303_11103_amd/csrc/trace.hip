@@ -333,6 +333,14 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
             if (best >= 0 && a.depth < a.max_depth) {
                 alive = true;
                 const Shade sh = a.sc.shades[best];
+                // the material's fields in one round trip to memory (used here, so
+                // that no load is sunk into the branches below)
+                Mat mt{};
+                mt.eta_re = mats.m[sh.mat].eta_re;
+                mt.eta_im = mats.m[sh.mat].eta_im;
+                mt.pec = mats.m[sh.mat].pec;
+                mt.scat = mats.m[sh.mat].scat;
+                asm volatile("" ::"v"(mt.eta_re), "v"(mt.eta_im), "v"(mt.pec), "v"(mt.scat));
                 d3 n{sh.n[0], sh.n[1], sh.n[2]};
                 if (dot(d, n) > 0.0) n = scale(n, -1.0);
                 const double cos_i = -dot(d, n);
@@ -342,7 +350,7 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
                 const d3 eli = cross(ep, d);
                 const d3 elr = cross(ep, dr);
                 cf rp, rl;
-                fresnel(mats.m[sh.mat], (float)cos_i, rp, rl);
+                fresnel(mt, (float)cos_i, rp, rl);
                 const f3 fep{(float)ep.x, (float)ep.y, (float)ep.z};
                 const f3 feli{(float)eli.x, (float)eli.y, (float)eli.z};
                 f3 felr{(float)elr.x, (float)elr.y, (float)elr.z};
@@ -351,10 +359,10 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
                 // components ride on that direction's transverse basis
                 d3 dout = dr;
                 f3 fepo = fep;
-                if ((MODE & (kModeCoverage | kModeRecord)) && mats.m[sh.mat].scat > 0.0f) {
+                if ((MODE & (kModeCoverage | kModeRecord)) && mt.scat > 0.0f) {
                     const uint64_t ri = (uint64_t)(a.begin + (int64_t)st.ray * a.stride);
                     const uint64_t c0 = (ri * (uint64_t)(a.max_depth + 1) + (uint64_t)a.depth) * 3ull;
-                    const double S = (double)mats.m[sh.mat].scat;
+                    const double S = (double)mt.scat;
                     if (uniform01(a.scat_seed, c0) < S * S) {
                         dout = lambert_dir(n, uniform01(a.scat_seed, c0 + 1), uniform01(a.scat_seed, c0 + 2));
                         const d3 eps = perp_basis(dout, n);

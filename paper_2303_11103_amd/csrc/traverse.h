@@ -40,6 +40,9 @@ __device__ __forceinline__ bool tri_test(const Tri* __restrict__ tris, int k, d3
     const int4 meta = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(tp) + 80);
     const d3 v0{q0.x, q0.y, q1.x}, e1{q1.y, q2.x, q2.y}, e2{q3.x, q3.y, q4.x};
     const double thr = q4.y;
+    // uses the vertex here, so that its load is not sunk below the determinant
+    // test into a second round trip to memory
+    asm volatile("" ::"v"(q0.x), "v"(q0.y), "v"(q1.x));
     const d3 P = cross(d, e2);
     double det = dot(e1, P);
     if (meta.x == excl0 || meta.x == excl1 || fabs(det) < thr) return false;
