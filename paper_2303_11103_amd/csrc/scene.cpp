@@ -104,9 +104,9 @@ private:
     }
 
     // Binned SAH, count / 8 bins per axis clamped to [16, 128] (large nodes,
-    // where a coarse split costs most, get fine bins).  Returns the split
-    // position, -2 when a leaf is cheaper (only allowed when count <=
-    // kMaxLeaf), -1 when no valid split exists.
+    // where a coarse split costs most, get fine bins), plus one partition by
+    // primitive size.  Returns the split position, -2 when a leaf is cheaper
+    // (only allowed when count <= kMaxLeaf), -1 when no valid split exists.
     int32_t sah_split(int32_t first, int32_t count, const Box& cb, const Box& b, bool leaf_ok) {
         constexpr int kMaxBins = 128;
         const int kBins = std::min(kMaxBins, std::max(16, count / 8));
@@ -148,10 +148,36 @@ private:
                 }
             }
         }
-        if (best_axis < 0) return -1;
-        double parent = b.area();
-        double split_cost = kTrav + kIsect * best / std::max(parent, 1e-300);
+        // candidate: the primitives whose own box has at least a quarter of the
+        // node's surface area apart from the others (a large ground polygon
+        // otherwise inflates every node on its way down to a leaf)
+        const double parent_area = b.area();
+        int n_large = 0;
+        Box large_box, small_box;
+        for (int32_t i = first; i < first + count; ++i) {
+            if (prims_[i].box.area() >= 0.25 * parent_area) {
+                ++n_large;
+                large_box.grow(prims_[i].box);
+            } else {
+                small_box.grow(prims_[i].box);
+            }
+        }
+        bool size_split = false;
+        if (n_large > 0 && n_large < count) {
+            const double cost = large_box.area() * n_large + small_box.area() * (count - n_large);
+            if (cost < best) {
+                best = cost;
+                size_split = true;
+            }
+        }
+        if (best_axis < 0 && !size_split) return -1;
+        double split_cost = kTrav + kIsect * best / std::max(parent_area, 1e-300);
         if (leaf_ok && kIsect * count <= split_cost) return -2;
+        if (size_split) {
+            auto it = std::partition(prims_.begin() + first, prims_.begin() + first + count,
+                                     [&](const Prim& p) { return p.box.area() >= 0.25 * parent_area; });
+            return (int32_t)(it - prims_.begin());
+        }
         double lo = cb.lo[best_axis], ext = cb.hi[best_axis] - cb.lo[best_axis];
         auto it = std::partition(prims_.begin() + first, prims_.begin() + first + count, [&](const Prim& p) {
             int k = (int)((p.c[best_axis] - lo) / ext * kBins);
