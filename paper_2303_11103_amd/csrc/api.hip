@@ -924,6 +924,7 @@ rt_status rt_compute_diffraction(rt_ctx* c, rt_scene* s, double freq_hz, const r
     RT_HIP(hipMemcpyAsync(c->rx.p, rxp.data(), rxp.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     RT_HIP(hipMemcpyAsync(c->rx_ant.p, rxa.data(), rxa.size() * sizeof(rt::Antenna), hipMemcpyHostToDevice,
                           c->stream));
+    RT_HIP(hipStreamSynchronize(c->stream));  // host staging vectors go out of scope
     char* base = (char*)c->paths.p;
     rt::PathArgs pa{};
     pa.sc = s->dev;
@@ -1005,6 +1006,7 @@ rt_status rt_compute_scattering(rt_ctx* c, rt_scene* s, const rt_trace_params* p
     RT_HIP(hipMemcpyAsync(c->rx.p, rxp.data(), rxp.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     RT_HIP(hipMemcpyAsync(c->rx_ant.p, rxa.data(), rxa.size() * sizeof(rt::Antenna), hipMemcpyHostToDevice,
                           c->stream));
+    RT_HIP(hipStreamSynchronize(c->stream));  // host staging vectors go out of scope
     char* buf = (char*)c->scat.p;
     rt::ScatArgs sa{};
     sa.sc = s->dev;
