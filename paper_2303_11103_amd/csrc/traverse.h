@@ -188,6 +188,13 @@ __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_node
     // without a pending leaf, so triangle tests run with most lanes active.
     constexpr int kDone = kEmptyChild;
     int leaf = 0;  // parked leaf code (negative), 0 = none
+    // A leaf code leaves bits 23-30 all ones when the scene has at most 2^18
+    // triangles; the references to leaves then carry the float exponent of
+    // the leaf box's entry distance there, and a leaf taken off the stack or
+    // parked is skipped when that exponent exceeds the one of the (widened)
+    // closest hit: the box lies wholly beyond it.
+    const uint32_t keep = sc.nt <= (1 << 18) ? 0x807FFFFFu : 0xFFFFFFFFu;
+    const uint32_t dist_bits = ~keep;
     while (true) {
         const int top = get(sp > 0 ? sp - 1 : 0);
         const bool want_inner = node >= 0 && leaf == 0;
@@ -229,6 +236,12 @@ __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_node
                 cx(q0, c0, q2, c2);
                 cx(q1, c1, q3, c3);
                 cx(q1, c1, q2, c2);
+                // the entry distance's exponent into the leaf references (inner node
+                // indices have zeros there and stay as they are)
+                c0 = (int)((uint32_t)c0 & (q0 | keep));
+                c1 = (int)((uint32_t)c1 & (q1 | keep));
+                c2 = (int)((uint32_t)c2 & (q2 | keep));
+                c3 = (int)((uint32_t)c3 & (q3 | keep));
                 // a nearest child that is a leaf is parked at once when the lane
                 // holds none; the next-nearest child is then visited next
                 const bool park = q0 != ~0u && c0 < 0 && leaf == 0;
@@ -259,14 +272,16 @@ __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_node
             }
         } else {
             if (leaf != 0) {
-                const int code = ~leaf;
-                const int first = code >> kLeafShift, cnt = (code & (kMaxLeaf - 1)) + 1;
-                if (STATS) ts->tris += cnt;
-                for (int k = first; k < first + cnt; ++k) {
-                    if (tri_test(sc.tris, k, o, d, excl0, excl1, tmin, tbest, ANY)) {
-                        best = k;
-                        if (ANY) return best;
-                        tfar = f_up(tbest);
+                if (((uint32_t)leaf & dist_bits) <= (__float_as_uint(tfar * kWiden) & 0x7F800000u)) {
+                    const int code = ~(leaf | (int)dist_bits);
+                    const int first = code >> kLeafShift, cnt = (code & (kMaxLeaf - 1)) + 1;
+                    if (STATS) ts->tris += cnt;
+                    for (int k = first; k < first + cnt; ++k) {
+                        if (tri_test(sc.tris, k, o, d, excl0, excl1, tmin, tbest, ANY)) {
+                            best = k;
+                            if (ANY) return best;
+                            tfar = f_up(tbest);
+                        }
                     }
                 }
                 leaf = 0;
