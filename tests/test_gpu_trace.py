@@ -31,7 +31,8 @@ def test_scene_faces_match_oracle_grouping():
         assert info["bvh_depth"] <= 30
 
 
-@pytest.mark.parametrize("case", ["toy", "urban_stride", "urban_full_small", "city_stride", "city_full_stride"])
+@pytest.mark.parametrize("case", ["toy", "urban_stride", "urban_full_small", "city_stride", "city_full_stride",
+                                  "city_over_2_18_triangles"])
 def test_hits_match_oracle(case):
     m = lib()
     if case == "toy":
@@ -46,9 +47,15 @@ def test_hits_match_oracle(case):
     elif case == "city_stride":
         w = sg.city_workload(num_rays=100_000_000, blocks=12)
         p = params(w, ray_begin=11, ray_stride=2003)     # 49 925 rays of the 1e8 lattice, 5 bounces
-    else:
+    elif case == "city_full_stride":
         w = sg.city_workload()                           # the full large city: 50x50 blocks, ~220k triangles
         p = params(w, ray_begin=13, ray_stride=40009)    # 2 500 rays of the 1e8 lattice, 5 bounces
+    else:
+        # more than 2^18 triangles: leaf codes use every bit, so the traversal
+        # keeps no entry distances in the references to leaves
+        w = sg.city_workload(blocks=56)
+        assert w.scene.nt > (1 << 18)
+        p = params(w, ray_begin=17, ray_stride=40009)
     tri, t = m.trace_record(ctx(), scene(w.scene), p, w.tx[0])
     orc = sbr.trace(w.scene, w.tx[0], oracle_params(p), record=True)
     compared, excluded = compare_hits(tri.cpu().numpy(), t.cpu().numpy(), orc)
