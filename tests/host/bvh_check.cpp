@@ -146,5 +146,25 @@ int main(int argc, char** argv) {
     }
     fclose(g);
     printf("nodes %zu depth %d stack %d faces %d\n", s.nodes.size(), s.depth, s.stack_need, s.num_faces);
+    // number of inner nodes above the leaf that holds input triangle 0
+    std::vector<std::pair<int32_t, int>> todo = {{0, 1}};
+    int depth0 = -1;
+    while (!todo.empty() && depth0 < 0) {
+        const auto [ref, dep] = todo.back();
+        todo.pop_back();
+        const Node& n = s.nodes[ref];
+        for (int c = 0; c < 4; ++c) {
+            const int32_t ch = n.child[c];
+            if (ch == kEmptyChild) continue;
+            if (ch >= 0) {
+                todo.push_back({ch, dep + 1});
+                continue;
+            }
+            const int code = ~ch, first = code >> kLeafShift, cnt = (code & (kMaxLeaf - 1)) + 1;
+            for (int k = first; k < first + cnt; ++k)
+                if (s.tris[k].orig == 0) depth0 = dep;
+        }
+    }
+    printf("leaf_depth_of_triangle_0 %d\n", depth0);
     return 0;
 }

@@ -48,7 +48,7 @@ def _run(exe, s, O, D):
     t = np.frombuffer(raw[4 * nt + 4 * nr:off], dtype=np.float64)
     nw = int(np.frombuffer(raw[off:off + 4], dtype=np.int32)[0])
     wedges = np.frombuffer(raw[off + 4:], dtype=np.float64).reshape(nw, 16)
-    return faces, hit, t, wedges
+    return faces, hit, t, wedges, r.stdout
 
 
 @pytest.mark.parametrize("name", ["toy", "urban", "city"])
@@ -56,7 +56,7 @@ def test_bvh_closest_hits_and_faces_match_oracle(checker, name):
     s = {"toy": sg.make_toy, "urban": lambda: sg.make_urban(0), "city": lambda: sg.make_city(0, blocks=10)}[name]()
     lo, hi = (-90, 90) if name == "toy" else (-230, 230) if name == "urban" else (-200, 200)
     O, D = sg.random_rays(3000, seed=3, lo=lo, hi=hi, zlo=0.5, zhi=80)
-    faces, hit, t, _ = _run(checker, s, O, D)
+    faces, hit, t, _, _ = _run(checker, s, O, D)
     ref_faces, _ = geom.face_ids(s.V, s.F, s.tri_mat)
     assert np.array_equal(faces, ref_faces)
     g = geom.Geometry(s)
@@ -75,7 +75,7 @@ def test_diffraction_wedges_match_oracle(checker, name):
     from oracle import diffraction
     s = {"toy": sg.make_toy, "urban": lambda: sg.make_urban(0), "city": lambda: sg.make_city(0, blocks=6)}[name]()
     O, D = sg.random_rays(4, seed=3, lo=-50, hi=50, zlo=0.5, zhi=80)
-    _, _, _, wg = _run(checker, s, O, D)
+    _, _, _, wg, _ = _run(checker, s, O, D)
     ref = diffraction.wedges(geom.Geometry(s))
     assert len(ref) == wg.shape[0] > 0
     for w, r in zip(ref, wg):
@@ -84,3 +84,15 @@ def test_diffraction_wedges_match_oracle(checker, name):
         assert np.allclose(w.n0, r[9:12], atol=1e-15)
         assert abs(w.length - r[12]) < 1e-12 * w.length and abs(w.n - r[13]) < 1e-14
         assert (w.face0, w.facen) == (int(r[14]), int(r[15]))
+
+
+def test_ground_quad_leaf_sits_near_the_root(checker):
+    """The size partition of the SAH build: the city's ground quad (input
+    triangles 0 and 1, each with a box of the whole city's footprint) becomes
+    a leaf within two levels of the root (a binned split alone carried it
+    four levels down, widening the boxes of every node on the way)."""
+    s = sg.make_city(0, blocks=10)
+    O, D = sg.random_rays(4, seed=3, lo=-50, hi=50, zlo=0.5, zhi=80)
+    *_, out = _run(checker, s, O, D)
+    line = [l for l in out.splitlines() if l.startswith("leaf_depth_of_triangle_0")][0]
+    assert 1 <= int(line.split()[1]) <= 2
