@@ -199,8 +199,11 @@ rt_status rt_trace_record(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p
  * reflection operators so far) and F_rx the receive pattern of rx_ant.
  *   gain [ny][nx] (dev) linear path gain, hits [ny][nx] (dev) crossings;
  *   gain_db [ny][nx] (dev, nullable) 10 log10(gain) (-inf where no hit);
- *   ray_bounces (dev, nullable) uint64 [max_depth+1]: traced segments per
- *   depth (their sum is the number of closest-hit queries).
+ *   ray_bounces (dev, nullable) uint64 [max_depth+1]: rays that reached each
+ *   depth (segments processed).  The segments of depths below max_depth are
+ *   closest-hit queries; a last-depth segment is searched only when it crosses
+ *   the plane inside the grid, and only up to the crossing, which gives the
+ *   same deposits.
  * The map is cleared first.  Sub-lattices (ray_begin, ray_stride) add only
  * their own rays with the weight of the full lattice N. */
 rt_status rt_coverage_map(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p, const rt_device* tx,

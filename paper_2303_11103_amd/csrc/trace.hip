@@ -296,8 +296,36 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
             const d3 d = st.d;
             double tbest = __builtin_inf();
             TravStats ts;
-            const int best = traverse<false, (MODE & kModeStats) != 0, kTraceBlock, OVF>(
-                a.sc, lds_nodes, n_lds, o, d, st.excl, st.excl, a.tmin, tbest, stack, &ts);
+            // The last bounce of a coverage map only deposits: its segment
+            // matters up to the coverage plane, so it is searched only up to
+            // there, and only until a first hit (any hit at t <= tc blocks the
+            // deposit, exactly as the closest hit would); rays that do not cross
+            // the plane inside the grid are not searched at all.
+            bool search = true;
+            const bool last = !FIRST && (MODE & kModeCoverage) && a.depth == a.max_depth;
+            if (last) {
+                search = false;
+                if (fabs(d.z) >= 1e-12) {
+                    const double tc = (a.gz - o.z) / d.z;
+                    if (tc > 0.0) {
+                        const double x = o.x + tc * d.x, y = o.y + tc * d.y;
+                        const double fx = floor((x - a.gx0) / a.gcell), fy = floor((y - a.gy0) / a.gcell);
+                        if (fx >= 0.0 && fx < (double)a.gnx && fy >= 0.0 && fy < (double)a.gny) {
+                            search = true;
+                            tbest = __longlong_as_double(__double_as_longlong(tc) + 1);  // next double above tc
+                        }
+                    }
+                }
+            }
+            int best = -1;
+            if (last) {
+                if (search)
+                    best = traverse<false, (MODE & kModeStats) != 0, kTraceBlock, OVF, true>(
+                        a.sc, lds_nodes, n_lds, o, d, st.excl, st.excl, a.tmin, tbest, stack, &ts);
+            } else {
+                best = traverse<false, (MODE & kModeStats) != 0, kTraceBlock, OVF>(
+                    a.sc, lds_nodes, n_lds, o, d, st.excl, st.excl, a.tmin, tbest, stack, &ts);
+            }
             if (MODE & kModeStats) {
                 const int nd = a.max_depth + 1;
                 atomicAdd((unsigned long long*)&a.work[a.depth], 1ull);

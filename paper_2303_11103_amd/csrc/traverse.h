@@ -153,7 +153,9 @@ __device__ __forceinline__ uint32_t box_key(float nx, float ny, float nz, float 
 // pushed farthest first.  Leaves are parked and tested when the whole wave
 // has one (see the loop).  OVF = false drops the private-memory continuation
 // of the stack: only for trees whose worst-case stack need is <= kStack.
-template <bool ANY, bool STATS = false, int BS = kBlock, bool OVF = true>
+// STOP = true returns at the first hit closer than the tbest passed in (an
+// occlusion test of the segment up to that distance).
+template <bool ANY, bool STATS = false, int BS = kBlock, bool OVF = true, bool STOP = false>
 __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_nodes, int n_lds, d3 o, d3 d, int excl0,
                                         int excl1, double tmin, double& tbest, int32_t (*stack)[BS],
                                         TravStats* ts = nullptr) {
@@ -279,7 +281,7 @@ __device__ __forceinline__ int traverse(const DevScene& sc, const Node* lds_node
                     for (int k = first; k < first + cnt; ++k) {
                         if (tri_test(sc.tris, k, o, d, excl0, excl1, tmin, tbest, ANY)) {
                             best = k;
-                            if (ANY) return best;
+                            if (ANY || STOP) return best;
                             tfar = f_up(tbest);
                         }
                     }
