@@ -200,10 +200,10 @@ rt_status rt_trace_record(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p
  *   gain [ny][nx] (dev) linear path gain, hits [ny][nx] (dev) crossings;
  *   gain_db [ny][nx] (dev, nullable) 10 log10(gain) (-inf where no hit);
  *   ray_bounces (dev, nullable) uint64 [max_depth+1]: rays that reached each
- *   depth (segments processed).  The segments of depths below max_depth are
- *   closest-hit queries; a last-depth segment is searched only when it crosses
- *   the plane inside the grid, and only up to the crossing, which gives the
- *   same deposits.
+ *   depth.  The segments of depths below max_depth are closest-hit queries;
+ *   a last-depth ray whose segment cannot cross the plane inside the grid is
+ *   counted but dropped before that launch, and the others are searched only
+ *   up to the crossing, which gives the same deposits.
  * The map is cleared first.  Sub-lattices (ray_begin, ray_stride) add only
  * their own rays with the weight of the full lattice N. */
 rt_status rt_coverage_map(rt_ctx* ctx, rt_scene* scene, const rt_trace_params* p, const rt_device* tx,

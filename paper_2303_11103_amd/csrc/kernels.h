@@ -68,7 +68,9 @@ struct SbrArgs {
     // wave appends its survivors to region (wave % kQueueRegions) through
     // that region's counter, which spreads the queue atomics over 64 addresses.
     const RayState* in;
-    const uint32_t* in_count;   // [kQueueRegions * kCounterStride] counts of the input regions
+    // [kQueueRegions * kCounterStride]: word 0 of a region counts its rays, word 1
+    // the rays its waves dropped before a last bounce (they add to the depth's count)
+    const uint32_t* in_count;
     RayState* out;
     uint32_t* out_count;        // [kQueueRegions * kCounterStride]
     int64_t region_cap;

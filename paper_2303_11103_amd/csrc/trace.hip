@@ -229,6 +229,17 @@ __device__ void sphere_pairs(const SbrArgs& a, const Ray& st, d3 o, d3 d, double
     }
 }
 
+// Whether the ray o + t d, t > 0, crosses the coverage plane z = gz inside
+// the grid; tc is the crossing's ray parameter.
+__device__ __forceinline__ bool crosses_grid(const SbrArgs& a, d3 o, d3 d, double& tc) {
+    if (!(fabs(d.z) >= 1e-12)) return false;
+    tc = (a.gz - o.z) / d.z;
+    if (!(tc > 0.0)) return false;
+    const double x = o.x + tc * d.x, y = o.y + tc * d.y;
+    const double fx = floor((x - a.gx0) / a.gcell), fy = floor((y - a.gy0) / a.gcell);
+    return fx >= 0.0 && fx < (double)a.gnx && fy >= 0.0 && fy < (double)a.gny;
+}
+
 template <int MODE, bool FIRST, bool OVF>
 #ifndef RT_TRACE_WAVES_PER_EU
 #define RT_TRACE_WAVES_PER_EU 4
@@ -252,8 +263,13 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
         }
     }
     const int64_t count = FIRST ? a.chunk : (int64_t)__shfl(incl, 63);
-    if (a.stats && blockIdx.x == 0 && threadIdx.x == 0)
-        atomicAdd((unsigned long long*)&a.stats[a.depth], (unsigned long long)count);
+    if (a.stats && blockIdx.x < 1 && threadIdx.x < 64) {
+        // rays of this depth: the queue plus those dropped before a last bounce
+        uint32_t dropped = FIRST ? 0u : a.in_count[lane * kCounterStride + 1];
+        for (int off = 32; off >= 1; off >>= 1) dropped += __shfl_xor(dropped, off);
+        if (threadIdx.x == 0) atomicAdd((unsigned long long*)&a.stats[a.depth], (unsigned long long)(count + dropped));
+    }
+    uint32_t wave_dropped = 0;  // rays of this wave dropped before the last bounce
     for (int64_t base = wave * 64; base < count; base += nwaves * 64) {
         const int64_t item = base + lane;
         const bool active = item < count;
@@ -271,7 +287,7 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
             region_off = item - (int64_t)start;
         }
         Ray st;
-        bool alive = false;
+        bool alive = false, dropped = false;
         if (active) {
             if (FIRST) {
                 const int64_t pos = lattice_position(a, a.pos0 + item);
@@ -304,18 +320,9 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
             bool search = true;
             const bool last = !FIRST && (MODE & kModeCoverage) && a.depth == a.max_depth;
             if (last) {
-                search = false;
-                if (fabs(d.z) >= 1e-12) {
-                    const double tc = (a.gz - o.z) / d.z;
-                    if (tc > 0.0) {
-                        const double x = o.x + tc * d.x, y = o.y + tc * d.y;
-                        const double fx = floor((x - a.gx0) / a.gcell), fy = floor((y - a.gy0) / a.gcell);
-                        if (fx >= 0.0 && fx < (double)a.gnx && fy >= 0.0 && fy < (double)a.gny) {
-                            search = true;
-                            tbest = __longlong_as_double(__double_as_longlong(tc) + 1);  // next double above tc
-                        }
-                    }
-                }
+                double tc;
+                search = crosses_grid(a, o, d, tc);
+                if (search) tbest = __longlong_as_double(__double_as_longlong(tc) + 1);  // next double above tc
             }
             int best = -1;
             if (last) {
@@ -413,6 +420,16 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
                 st.o = p;
                 st.d = dout;
                 st.excl = sh.face;
+                // a ray entering the last bounce of a map only deposits there: one
+                // that cannot cross the coverage plane inside the grid is dropped
+                // here (and still counted as a ray of that depth)
+                if ((MODE & ~kModeStats) == kModeCoverage && a.depth + 1 == a.max_depth) {
+                    double tc;
+                    if (!crosses_grid(a, p, dout, tc)) {
+                        alive = false;
+                        dropped = true;
+                    }
+                }
                 if (MODE & kModeCandidates) {
                     if (st.prefix != -2) st.prefix = cand_insert(a.table, a.table_mask, st.prefix, sh.face, a.overflow);
                 }
@@ -422,6 +439,7 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
                 }
             }
         }
+        if ((MODE & ~kModeStats) == kModeCoverage) wave_dropped += (uint32_t)__popcll(__ballot(dropped));
         // wave-ballot compaction of the survivors into the next queue
         const uint64_t m = __ballot(alive);
         if (m) {
@@ -434,6 +452,9 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
                     a.out + region * a.region_cap + b + __popcll(m & ((1ull << lane) - 1ull)), st);
         }
     }
+    // the dropped rays go to word 1 of the region counter (the next launch adds
+    // them to its ray count)
+    if (lane == 0 && wave_dropped) atomicAdd(a.out_count + (wave % kQueueRegions) * kCounterStride + 1, wave_dropped);
 }
 
 __global__ void fib_dirs_kernel(int64_t N, int64_t begin, int64_t stride, int64_t count, double* out) {
