@@ -234,7 +234,8 @@ rt_status rt_coverage_map_noalloc(rt_ctx* ctx, rt_scene* scene, const rt_trace_p
                                   const rt_device* rx_ant, const rt_grid* grid, float* gain, uint32_t* hits,
                                   float* gain_db, uint64_t* ray_bounces);
 
-/* rt_coverage_map that also counts, per depth k, the traced rays, the BVH
+/* rt_coverage_map that also counts, per depth k, the traced rays (at the last
+ * depth without the rays dropped before it, see ray_bounces above), the BVH
  * inner nodes visited, the child boxes tested at those nodes (the node's
  * non-empty slots) and the triangles tested:
  *   work [4][max_depth+1] (dev) uint64 (rays, node visits, box tests,
