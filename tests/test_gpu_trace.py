@@ -129,6 +129,31 @@ def test_coverage_matches_oracle(name):
     assert rb[0] == p.traced() and np.all(np.diff(rb) <= 0)
 
 
+@pytest.mark.parametrize("name", ["toy", "urban_stride", "city_stride"])
+def test_ray_bounce_counts_match_oracle(name):
+    """Rays per depth of a coverage map equal the rays the oracle traces at each
+    depth; the last depth's count includes the rays dropped before it because
+    their segment cannot cross the coverage plane inside the grid."""
+    m = lib()
+    if name == "toy":
+        w = sg.toy_workload()
+        p = params(w)
+    elif name == "urban_stride":
+        w = sg.urban_workload()
+        p = params(w, ray_begin=5, ray_stride=97)
+    else:
+        w = sg.city_workload(num_rays=100_000_000, blocks=12)
+        p = params(w, ray_begin=11, ray_stride=2003)
+    out = m.coverage_map(ctx(), scene(w.scene), p, w.tx[0], w.grid)
+    rb = out["ray_bounces"].cpu().numpy().astype(np.int64)
+    res = sbr.trace(w.scene, w.tx[0], oracle_params(p), record=True)
+    ref = np.asarray([int((h != -2).sum()) for h in res.hit_tri], dtype=np.int64)
+    amb = int(res.ambiguous.sum())
+    assert rb.shape == ref.shape == (p.max_depth + 1,)
+    assert rb[0] == ref[0] == p.traced()
+    assert np.all(np.abs(rb - ref) <= amb), (rb, ref, amb)
+
+
 def test_coverage_full_lattice_equals_sum_of_sublattices():
     """Bench configuration (urban, 1e7 rays, depth 3): the full map equals the
     sum of the maps of 10 disjoint sub-lattices (same kernels, different
