@@ -91,6 +91,10 @@ def _coverage_case(name):
     if name == "urban_tr38901":
         w = sg.diff_workload(num_rays=300_000)
         return w, params(w)
+    if name == "urban_small_grid":  # most rays cannot deposit at the last bounce: they are dropped before it
+        w = sg.urban_workload(num_rays=1_000_000)
+        w.grid = sg.Grid(37.0, -83.0, 2.0, 45, 35, 2.5)
+        return w, params(w)
     if name == "urban_dipole_slant":  # dipole transmitter at -45 degrees, H-pol receive pattern
         w = sg.urban_workload(num_rays=1_000_000)
         w.tx[0].pattern = sg.PATTERN_DIPOLE
@@ -101,7 +105,7 @@ def _coverage_case(name):
     raise KeyError(name)
 
 
-@pytest.mark.parametrize("name", ["toy", "urban", "urban_tr38901", "urban_dipole_slant"])
+@pytest.mark.parametrize("name", ["toy", "urban", "urban_tr38901", "urban_small_grid", "urban_dipole_slant"])
 def test_coverage_matches_oracle(name):
     m = lib()
     w, p = _coverage_case(name)
@@ -129,7 +133,7 @@ def test_coverage_matches_oracle(name):
     assert rb[0] == p.traced() and np.all(np.diff(rb) <= 0)
 
 
-@pytest.mark.parametrize("name", ["toy", "urban_stride", "city_stride"])
+@pytest.mark.parametrize("name", ["toy", "urban_stride", "urban_small_grid", "city_stride"])
 def test_ray_bounce_counts_match_oracle(name):
     """Rays per depth of a coverage map equal the rays the oracle traces at each
     depth; the last depth's count includes the rays dropped before it because
@@ -141,6 +145,8 @@ def test_ray_bounce_counts_match_oracle(name):
     elif name == "urban_stride":
         w = sg.urban_workload()
         p = params(w, ray_begin=5, ray_stride=97)
+    elif name == "urban_small_grid":
+        w, p = _coverage_case(name)
     else:
         w = sg.city_workload(num_rays=100_000_000, blocks=12)
         p = params(w, ray_begin=11, ray_stride=2003)
