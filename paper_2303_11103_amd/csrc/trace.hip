@@ -240,6 +240,25 @@ __device__ __forceinline__ bool crosses_grid(const SbrArgs& a, d3 o, d3 d, doubl
     return fx >= 0.0 && fx < (double)a.gnx && fy >= 0.0 && fy < (double)a.gny;
 }
 
+// Whether the ray o + t d, t >= 0, enters the receivers' height band and grid
+// rectangle (the region where reception spheres are looked up).
+__device__ __forceinline__ bool reaches_rx_region(const SbrArgs& a, d3 o, d3 d) {
+    double t0 = 0.0, t1 = __builtin_inf();
+    auto clip = [&](double oc, double dc, double lo, double hi) {
+        if (dc != 0.0) {
+            const double ta = (lo - oc) / dc, tb = (hi - oc) / dc;
+            t0 = fmax(t0, fmin(ta, tb));
+            t1 = fmin(t1, fmax(ta, tb));
+        } else if (oc < lo || oc > hi) {
+            t1 = -1.0;
+        }
+    };
+    clip(o.z, d.z, a.rz_lo, a.rz_hi);
+    clip(o.x, d.x, a.rgx0, a.rgx0 + a.rgnx * a.rgcell);
+    clip(o.y, d.y, a.rgy0, a.rgy0 + a.rgny * a.rgcell);
+    return t0 <= t1;
+}
+
 template <int MODE, bool FIRST, bool OVF>
 #ifndef RT_TRACE_WAVES_PER_EU
 #define RT_TRACE_WAVES_PER_EU 4
@@ -324,12 +343,15 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
                 search = crosses_grid(a, o, d, tc);
                 if (search) tbest = __longlong_as_double(__double_as_longlong(tc) + 1);  // next double above tc
             }
+            // in reception-sphere mode the last segment only meets spheres: one
+            // that never enters the receivers' region needs no search
+            if ((MODE & kModeSphere) && !FIRST && a.depth == a.max_depth) search = reaches_rx_region(a, o, d);
             int best = -1;
             if (last) {
                 if (search)
                     best = traverse<false, (MODE & kModeStats) != 0, kTraceBlock, OVF, true>(
                         a.sc, lds_nodes, n_lds, o, d, st.excl, st.excl, a.tmin, tbest, stack, &ts);
-            } else {
+            } else if (search) {
                 best = traverse<false, (MODE & kModeStats) != 0, kTraceBlock, OVF>(
                     a.sc, lds_nodes, n_lds, o, d, st.excl, st.excl, a.tmin, tbest, stack, &ts);
             }
@@ -430,6 +452,12 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
                         dropped = true;
                     }
                 }
+                // likewise in reception-sphere mode for a last segment that cannot
+                // enter the receivers' region
+                if (MODE == kModeSphere && a.depth + 1 == a.max_depth && !reaches_rx_region(a, p, dout)) {
+                    alive = false;
+                    dropped = true;
+                }
                 if (MODE & kModeCandidates) {
                     if (st.prefix != -2) st.prefix = cand_insert(a.table, a.table_mask, st.prefix, sh.face, a.overflow);
                 }
@@ -439,7 +467,8 @@ void sbr_bounce(SbrArgs a, MatTable mats) {
                 }
             }
         }
-        if ((MODE & ~kModeStats) == kModeCoverage) wave_dropped += (uint32_t)__popcll(__ballot(dropped));
+        if ((MODE & ~kModeStats) == kModeCoverage || MODE == kModeSphere)
+            wave_dropped += (uint32_t)__popcll(__ballot(dropped));
         // wave-ballot compaction of the survivors into the next queue
         const uint64_t m = __ballot(alive);
         if (m) {
