@@ -237,6 +237,17 @@ void band_perm(int64_t count, int64_t stride, int64_t& F, int64_t& G) {
 }
 
 int grid_for(const rt_ctx* c) { return c->num_cu * 4; }
+// Blocks of the shoot-and-bounce launch of depth k when the queues are
+// allocated per call (measured on the large city: more, smaller blocks for the
+// coherent first bounce, fewer for the second), and the region capacity that
+// covers every such grid.  The fixed-scratch path keeps grid_for for all
+// depths: a larger grid's minimum region capacity would not fit its scratch.
+int grid_for_depth(const rt_ctx* c, int k) { return c->num_cu * (k == 0 ? 8 : k == 1 ? 2 : 4); }
+int64_t region_capacity_by_depth(const rt_ctx* c, int64_t chunk) {
+    int64_t cap = 0;
+    for (int k = 0; k < 3; ++k) cap = std::max(cap, rt::sbr_region_capacity(chunk, grid_for_depth(c, k)));
+    return cap;
+}
 
 // Runs the shoot-and-bounce launches for all rays of one transmitter.
 rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_device* tx, const rt_device* rx_ant,
@@ -245,7 +256,8 @@ rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_dev
                   uint64_t* work = nullptr, const rt::SbrArgs* sphere = nullptr, const FixedQueues* fixed = nullptr) {
     const int64_t count = traced_count(p);
     const int64_t chunk = std::min(count, fixed ? fixed->max_chunk : kChunk);
-    const int64_t region_cap = rt::sbr_region_capacity(chunk, grid_for(c));
+    const int64_t region_cap =
+        fixed ? rt::sbr_region_capacity(chunk, grid_for(c)) : region_capacity_by_depth(c, chunk);
     rt::RayState* queue[2];
     uint32_t* cnt;
     if (fixed) {
@@ -338,7 +350,7 @@ rt_status run_sbr(rt_ctx* c, rt_scene* s, const rt_trace_params* p, const rt_dev
                 e1 = c->ev_pool[c->ev_used++];
                 RT_HIP(hipEventRecord(e0, c->stream));
             }
-            RT_HIP(rt::launch_sbr_bounce(a, mats, mode, grid_for(c), c->stream));
+            RT_HIP(rt::launch_sbr_bounce(a, mats, mode, fixed ? grid_for(c) : grid_for_depth(c, k), c->stream));
             if (profiling) {
                 RT_HIP(hipEventRecord(e1, c->stream));
                 c->recs.push_back({k, e0, e1});
